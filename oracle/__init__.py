@@ -1,0 +1,21 @@
+"""Plain CPU FP64 oracle for the matrix-free DG acoustic solver -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the CPU baseline leg of the benchmark may
+import this package.  The product path (the HIP library and its binding)
+never imports it and shares no code with it.
+
+The oracle evaluates the same weak form as the GPU path, but in the plainest
+possible way: d-dimensional Lagrange polynomials evaluated directly at points
+(no sum factorization, no basis change, no collocation), full Gauss quadrature
+and a dense per-cell mass matrix inverted by Cholesky factorization.  Every
+function cites the part of the paper (Schoeder, Kormann, Wall, Kronbichler,
+"Efficient explicit time stepping of high order discontinuous Galerkin schemes
+for waves", arXiv:1805.03981) it follows.
+
+Parity status: every function is pinned by a CPU test except the point-source
+right-hand side (no closed form exists for a point source on a curved mesh
+with variable coefficients) -- "parity unpinned" there, see oracle/sources.py.
+"""
+from . import basis, mesh, operator, timestep, ader, norms, sources  # noqa: F401
+from .mesh import Mesh  # noqa: F401
+from .operator import apply_operator  # noqa: F401

@@ -1,0 +1,164 @@
+"""ADER time stepping with the Taylor-Cauchy-Kowalevski (TCK) sum (oracle).
+
+Paper, Sec. 2.3 (eq. ader-U and eq. ader): u_{n+1} = u_n - M^-1 K M^-1
+sum_{j=0}^{k+1} dt^{j+1}/(j+1)! (-1)^j int N^T S^j N u_n, i.e.
+u_{n+1} = u_n + L_h(I) with I the time integral of the local Taylor
+expansion.  Sec. 3.2 (flexible basis change, Alg. 2) evaluates the j-th
+derivatives by repeated first derivatives at Gauss points; Sec. 3.3
+(degree reduction, Alg. 3) projects every second derivative to a degree two
+lower on the reference element.
+
+Reading of Alg. 3 (its loop index and the text's degree formula disagree):
+the m-th time derivative ut^m lives at n_m Gauss points per direction with
+n_0 = k+1, n_m = n_{m-1} - 2 when m is even and n_m = n_{m-1} when m is odd,
+so that deg ut^m = k - 2 floor(m/2).  For m = 1..k+1:
+
+    w      = -S_loc ut^{m-1}                  (at the n_{m-1} Gauss points)
+    ut^m   = P_{n -> n-2} w  if m even,  else w
+    I     += dt^{m+1}/(m+1)! * E_{n_m -> k+1} ut^m,     I starts at dt ut^0,
+
+with S_loc u = ((1/rho) grad p, rho c^2 div v) evaluated pointwise from the
+level's Lagrange interpolant and the Jacobian at the level's points, P the
+L2 projection on the reference cell and E the evaluation of the level
+interpolant at the k+1 Gauss points.  A projection to fewer than one point
+per direction (and every later term) is zero.  With `reduce=False`
+(Alg. 2 only) every level has k+1 points and nothing is projected.
+
+Everything is built from dense d-dimensional tables evaluated directly.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import basis
+from .operator import apply_operator, tables
+
+
+def levels(k, reduce=True):
+    """Points per direction n_m of the time derivatives m = 0..k+1 (0 = vanished)."""
+    out = [k + 1]
+    for m in range(1, k + 2):
+        n = out[-1]
+        if reduce and m % 2 == 0:
+            n = n - 2
+        out.append(max(n, 0))
+    return out
+
+
+def projection_table(n, d):
+    """Dense L2 projection (reference cell, unit weight) from Q_{n-1} (values at the
+    n^d Gauss points) onto Q_{n-3} (values at the (n-2)^d Gauss points):
+    solve the normal equations with mass matrix int l_a l_b and right-hand side
+    int l_a l_j, both by an over-integrating Gauss rule."""
+    xs, _ = basis.gauss(n)
+    xr, _ = basis.gauss(n - 2)
+    xo, wo = basis.gauss(n + 2)
+    pts = basis.tensor_points(xo, d)
+    w = basis.tensor_weights(wo, d)
+    lr = basis.tensor_basis(xr, pts)          # [Qo][(n-2)^d]
+    ls = basis.tensor_basis(xs, pts)          # [Qo][n^d]
+    M = lr.T @ (w[:, None] * lr)
+    Bm = lr.T @ (w[:, None] * ls)
+    return np.linalg.solve(M, Bm)
+
+
+class AderTables:
+    def __init__(self, mesh, reduce=True):
+        d, k = mesh.dim, mesh.k
+        self.levels = levels(k, reduce)
+        self.reduce = reduce
+        self.pts = {}
+        self.D = {}
+        self.E = {}
+        self.from_gl = {}
+        for n in sorted(set(l for l in self.levels if l > 0)):
+            x, _ = basis.gauss(n)
+            p = basis.tensor_points(x, d)
+            self.pts[n] = p
+            self.D[n] = basis.tensor_basis_grad(x, p) if n > 1 else [np.zeros((1, 1))] * d
+            self.E[n] = basis.tensor_basis(x, mesh.cell_ref)          # level n -> k+1 Gauss points
+            self.from_gl[n] = basis.tensor_basis(mesh.xgl, p)           # GL coefficients -> level points
+        self.P = {n: projection_table(n, d) for n in self.pts if n - 2 >= 1}
+
+
+def ader_tables(mesh, reduce=True):
+    key = ("ader", reduce)
+    t = mesh._cache.get(key)
+    if t is None:
+        t = AderTables(mesh, reduce)
+        mesh._cache[key] = t
+    return t
+
+
+def level_data(mesh, cells, n):
+    """J^-1, rho and c at the n^d Gauss points of each cell (the level's own points)."""
+    key = ("level", n)
+    full = mesh._cache.get(key)
+    if full is not None:
+        return {kk: v[cells] for kk, v in full.items()}
+    T = ader_tables(mesh)
+    pts = T.pts[n] if n in T.pts else basis.tensor_points(basis.gauss(n)[0], mesh.dim)
+
+    def compute(cs):
+        x, J = mesh.map_points(cs, pts)
+        rho, c = mesh.material(x)
+        return dict(Jinv=np.linalg.inv(J), rho=np.asarray(rho, float), c=np.asarray(c, float))
+
+    if mesh._cacheable():
+        full = compute(np.arange(mesh.nc))
+        mesh._cache[key] = full
+        return {kk: v[cells] for kk, v in full.items()}
+    return compute(cells)
+
+
+def tck(mesh, U, dt, cells=None, reduce=True, source_terms=None):
+    """Time-integrated Taylor sum I (GL coefficients, float64[C][d+1][np]).
+
+    source_terms: optional callable (cells, m, n) -> additive p-values at the
+    level-n points of the (m-1)-th recursion step, float64[C][n^d] (the
+    point-source injection); None for no source.
+    """
+    d, k = mesh.dim, mesh.k
+    T = ader_tables(mesh, reduce)
+    Tb = tables(mesh)
+    cells = np.arange(mesh.nc) if cells is None else np.atleast_1d(np.asarray(cells, dtype=np.int64))
+    ut = np.einsum("qi,cvi->cvq", Tb.phi, np.asarray(U)[cells])   # ut^0 at the k+1 Gauss points
+    I = dt * ut.copy()
+    lev = T.levels
+    for m in range(1, k + 2):
+        n = lev[m - 1]
+        if n <= 0:
+            break
+        ld = level_data(mesh, cells, n)
+        Jinv = ld["Jinv"]                                    # [C][Q][b][a]
+        grads = [np.einsum("qj,cvj->cvq", T.D[n][b], ut) for b in range(d)]  # d/dxi_b of each comp
+        w = np.empty_like(ut)
+        for a in range(d):
+            w[:, a] = -(1.0 / ld["rho"]) * sum(Jinv[:, :, b, a] * grads[b][:, d] for b in range(d))
+        div = sum(Jinv[:, :, b, a] * grads[b][:, a] for a in range(d) for b in range(d))
+        w[:, d] = -ld["rho"] * ld["c"] ** 2 * div
+        if source_terms is not None:
+            w[:, d] += source_terms(cells, m, n)
+        if reduce and m % 2 == 0:
+            if n - 2 < 1:
+                break
+            ut = np.einsum("rq,cvq->cvr", T.P[n], w)
+        else:
+            ut = w
+        nm = lev[m]
+        I += dt ** (m + 1) / math.factorial(m + 1) * np.einsum("pq,cvq->cvp", T.E[nm], ut)
+    # GL coefficients of the Gauss-point values (dense solve with the GL table)
+    Ig = np.linalg.solve(Tb.phi[None, :, :], np.swapaxes(I, -1, -2))
+    return np.ascontiguousarray(np.swapaxes(Ig, -1, -2))
+
+
+def ader_step(mesh, U, dt, flux="upwind", reduce=True, source=None, t=0.0):
+    """One ADER step u + L_h(I) (+ the exact time integral of the source)."""
+    st = None if source is None else source.tck_terms(mesh, t)
+    I = tck(mesh, U, dt, reduce=reduce, source_terms=st)
+    out = np.asarray(U, dtype=np.float64) + apply_operator(mesh, I, flux=flux)
+    if source is not None:
+        out = out + source.integral(t, t + dt) * source.vector_full(mesh)
+    return out

@@ -1,0 +1,150 @@
+"""Curved-cell geometry and material sampling (oracle).
+
+The paper allows general curved quadrilaterals/hexahedra with variable
+coefficients (abstract; Sec. 3 where the Gauss rule is chosen) and uses
+pre-computed inverse Jacobians at the quadrature points (Sec. 3.4, degree
+reduction; Sec. 4.4, roofline discussion).  It does not fix a representation
+of the curved map; the reading taken here is an isoparametric-style map of
+degree q given by the positions of (q+1)^d equispaced nodes per cell:
+
+    x(xi) = sum_j X_j psi_j(xi),   J_ab = d x_a / d xi_b,
+
+with psi_j the d-dimensional Lagrange polynomials on the equispaced nodes,
+evaluated directly (no sum factorization).  Face quadrature uses the n^(d-1)
+tensor Gauss points of the face (the paper only implies this), and the face
+"area vector" folds in the face weight:  a = w_F det(J) J^-T n_ref, whose
+length is the surface element and whose direction is the outward normal.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import basis
+
+
+class Mesh:
+    """A mesh of curved quads (d=2) or hexes (d=3) with degree-k DG fields.
+
+    geo_nodes: float64[Nc][(q+1)^d][d]; neighbors: int64[Nc][2d] in face order
+    -x,+x,-y,+y,-z,+z (standard orientation, no boundary); material:
+    callable x[...,d] -> (rho, c).
+    """
+
+    def __init__(self, dim, k, geo_nodes, neighbors, material):
+        self.dim = int(dim)
+        self.k = int(k)
+        self.n = self.k + 1
+        self.geo_nodes = np.ascontiguousarray(geo_nodes, dtype=np.float64)
+        self.neighbors = np.ascontiguousarray(neighbors, dtype=np.int64)
+        self.material = material
+        self.nc = self.geo_nodes.shape[0]
+        ng = self.geo_nodes.shape[1]
+        q = int(round(ng ** (1.0 / self.dim))) - 1
+        if (q + 1) ** self.dim != ng or q < 1:
+            raise ValueError("geo_nodes must hold (q+1)^d nodes per cell")
+        self.q = q
+        self.np_ = self.n ** self.dim
+        self.nface = 2 * self.dim
+        self._geo_ref = basis.equispaced(q)
+        # reference rules
+        self.xg, self.wg = basis.gauss(self.n)
+        self.xgl, self.wgl = basis.gauss_lobatto(self.n)
+        self.cell_ref = basis.tensor_points(self.xg, self.dim)
+        self.cell_w = basis.tensor_weights(self.wg, self.dim)
+        self.face_ref = [self._face_points(f) for f in range(self.nface)]
+        self.face_w = basis.tensor_weights(self.wg, self.dim - 1) if self.dim > 1 else np.ones(1)
+        self._cache = {}
+
+    # ---- reference geometry --------------------------------------------
+    def _face_points(self, f):
+        """Reference Gauss points of face f: xi_a = side, tangential coordinates
+        in increasing direction order, the first remaining direction fastest."""
+        a, s = divmod(f, 2)
+        tang = basis.tensor_points(self.xg, self.dim - 1)
+        pts = np.empty((tang.shape[0], self.dim))
+        t = 0
+        for b in range(self.dim):
+            if b == a:
+                pts[:, b] = float(s)
+            else:
+                pts[:, b] = tang[:, t]
+                t += 1
+        return pts
+
+    def face_normal_ref(self, f):
+        a, s = divmod(f, 2)
+        nv = np.zeros(self.dim)
+        nv[a] = 1.0 if s == 1 else -1.0
+        return nv
+
+    # ---- the map ---------------------------------------------------------
+    def map_points(self, cells, ref_pts):
+        """Physical points x[C][P][d] and Jacobians J[C][P][d][d] (J[..,a,b] = dx_a/dxi_b)."""
+        cells = np.atleast_1d(np.asarray(cells, dtype=np.int64))
+        psi = basis.tensor_basis(self._geo_ref, ref_pts)          # [P][Ng]
+        dpsi = basis.tensor_basis_grad(self._geo_ref, ref_pts)    # [d][P][Ng]
+        X = self.geo_nodes[cells]                                  # [C][Ng][d]
+        x = np.einsum("pg,cga->cpa", psi, X)
+        J = np.stack([np.einsum("pg,cga->cpa", dpsi[b], X) for b in range(self.dim)], axis=-1)
+        return x, J
+
+    # ---- cached per-point data ---------------------------------------------
+    def _cacheable(self):
+        return self.nc * self.np_ * 40 * 8 < 1.5e9
+
+    def _sliced(self, key, fn, cells):
+        cells = np.atleast_1d(np.asarray(cells, dtype=np.int64))
+        if not self._cacheable():
+            return fn(cells)
+        full = self._cache.get(key)
+        if full is None:
+            parts = [fn(np.arange(s, min(s + 4096, self.nc))) for s in range(0, self.nc, 4096)]
+            full = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+            self._cache[key] = full
+        return {k: v[cells] for k, v in full.items()}
+
+    def cell_data(self, cells):
+        """Geometry and material at the n^d Gauss points of each cell."""
+        return self._sliced("cell", self._cell_data, cells)
+
+    def face_data(self, cells, f):
+        return self._sliced(("face", f), lambda c: self._face_data(c, f), cells)
+
+    def _cell_data(self, cells):
+        x, J = self.map_points(cells, self.cell_ref)
+        detJ = np.linalg.det(J)
+        if np.any(detJ <= 0.0):
+            raise ValueError("non-positive Jacobian determinant")
+        Jinv = np.linalg.inv(J)                                    # Jinv[..,b,a] = dxi_b/dx_a
+        rho, c = self.material(x)
+        return dict(x=x, J=J, detJ=detJ, Jinv=Jinv, wdet=self.cell_w[None, :] * detJ,
+                    rho=np.asarray(rho, dtype=np.float64), c=np.asarray(c, dtype=np.float64))
+
+    def _face_data(self, cells, f):
+        """Area vectors a[C][Qf][d] (face weight folded in), own and neighbour
+        impedance Z = rho c at the face points (each side samples the material
+        at its own mapped point)."""
+        x, J = self.map_points(cells, self.face_ref[f])
+        detJ = np.linalg.det(J)
+        if np.any(detJ <= 0.0):
+            raise ValueError("non-positive Jacobian determinant on a face")
+        JinvT = np.swapaxes(np.linalg.inv(J), -1, -2)
+        a = self.face_w[None, :, None] * detJ[..., None] * (JinvT @ self.face_normal_ref(f))
+        rho, c = self.material(x)
+        nbc = self.neighbors[cells, f]
+        xn, _ = self.map_points(nbc, self.face_ref[f ^ 1])
+        rhon, cn = self.material(xn)
+        return dict(a=a, x=x, Zm=np.asarray(rho * c, dtype=np.float64),
+                    Zp=np.asarray(rhon * cn, dtype=np.float64), nb=nbc)
+
+    def node_points(self, cells=None):
+        """Physical positions of the GL nodes, float64[C][n^d][d] (for interpolating
+        initial data)."""
+        cells = np.arange(self.nc) if cells is None else cells
+        x, _ = self.map_points(cells, basis.tensor_points(self.xgl, self.dim))
+        return x
+
+    def interpolate(self, fn, cells=None):
+        """GL nodal interpolant of fn(x) -> [..., d+1]: state float64[C][d+1][n^d]."""
+        x = self.node_points(cells)
+        return np.ascontiguousarray(np.moveaxis(fn(x), -1, 1))

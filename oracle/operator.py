@@ -1,0 +1,173 @@
+"""The semi-discrete DG operator L = -M^-1 K for first-order acoustics (oracle).
+
+Paper, Sec. 2 (the PDE with S, eq. general-hyp-pde), Sec. 2.1 (weak form,
+eq. weak-form; M dU/dt + K U = 0, eq. matrix-tc-sd) and Sec. 2.4 (the HDG
+flux, which with tau = 1/(c rho) is the upwind flux).
+
+Reading of the weak form with pointwise-varying rho and c (the paper places
+1/rho and rho c^2 inside S and writes an unweighted mass; with coefficients
+varying inside a cell that placement loses a gradient of 1/rho).  Here the
+material is moved into a weighted mass, which is identical for cell-wise
+constant coefficients.  For a GL test function phi and a = 1..d:
+
+    (phi, rho d/dt v_a)_K       = (d phi/d x_a, p)_K - sum_F <phi a_a, p*>_F
+    (phi, d/dt p / (rho c^2))_K = (grad phi, v)_K    - sum_F <phi |a|, v*_n>_F
+
+with Gauss quadrature on n = k+1 points per direction (Sec. 3), and
+a = w_F det J J^-T n_ref the area vector of a face point.  The numerical
+fluxes at a face point (- own side, + neighbour, n the own outward normal,
+Z = rho c sampled by each side):
+
+    upwind:  p*   = (Z+ p- + Z- p+ + Z- Z+ (v-.n - v+.n)) / (Z- + Z+)
+             v*_n = (Z- v-.n + Z+ v+.n + p- - p+)        / (Z- + Z+)
+    central: p*   = (p- + p+)/2,   v*_n = (v-.n + v+.n)/2
+
+For Z- = Z+ the upwind flux is p* = {p} + Z/2 [v_n], v*_n = {v_n} + [p]/(2Z),
+the paper's HDG flux with tau = 1/(c rho) once its rows are divided by the
+coefficients that the paper keeps inside S.
+
+The operator is evaluated with the full d-dimensional GL basis tables at the
+quadrature points (no sum factorization) and the dense per-cell mass matrices
+M_v = sum_q w detJ rho phi_i phi_j, M_p = sum_q w detJ/(rho c^2) phi_i phi_j
+are inverted through a Cholesky factorization.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import basis
+
+
+class Tables:
+    """Direct d-dimensional GL basis tables at the cell and face Gauss points."""
+
+    def __init__(self, mesh):
+        self.phi = basis.tensor_basis(mesh.xgl, mesh.cell_ref)            # [Q][np]
+        self.dphi = basis.tensor_basis_grad(mesh.xgl, mesh.cell_ref)      # [d][Q][np]
+        self.phif = [basis.tensor_basis(mesh.xgl, mesh.face_ref[f]) for f in range(mesh.nface)]
+
+
+def tables(mesh):
+    t = mesh._cache.get("tables")
+    if t is None:
+        t = Tables(mesh)
+        mesh._cache["tables"] = t
+    return t
+
+
+def numerical_flux(pm, pp, vnm, vnp, Zm, Zp, flux):
+    """(p*, v*_n) at face points; see the module docstring."""
+    if flux == "upwind":
+        s = Zm + Zp
+        ps = (Zp * pm + Zm * pp + Zm * Zp * (vnm - vnp)) / s
+        vs = (Zm * vnm + Zp * vnp + pm - pp) / s
+    elif flux == "central":
+        ps = 0.5 * (pm + pp)
+        vs = 0.5 * (vnm + vnp)
+    else:
+        raise ValueError(flux)
+    return ps, vs
+
+
+def residual(mesh, U, cells, flux="upwind"):
+    """Right-hand side r = -K U restricted to `cells`, float64[C][d+1][np] (GL test functions)."""
+    d = mesh.dim
+    T = tables(mesh)
+    cells = np.atleast_1d(np.asarray(cells, dtype=np.int64))
+    cd = mesh.cell_data(cells)
+    Uc = U[cells]
+    uq = np.einsum("qi,cvi->cvq", T.phi, Uc)          # values at the Gauss points
+    r = np.zeros((len(cells), d + 1, mesh.np_))
+    wJ = cd["wdet"][..., None, None] * cd["Jinv"]      # [C][Q][b][a] = w detJ dxi_b/dx_a
+    for b in range(d):
+        # (d phi/d x_a, p) part for the v_a tests, (grad phi, v) part for the p test
+        Fv = wJ[:, :, b, :] * uq[:, d, :, None]        # [C][Q][a]
+        Fp = np.einsum("cqa,caq->cq", wJ[:, :, b, :], uq[:, :d, :])
+        r[:, :d, :] += np.einsum("qi,cqa->cai", T.dphi[b], Fv)
+        r[:, d, :] += np.einsum("qi,cq->ci", T.dphi[b], Fp)
+    for f in range(mesh.nface):
+        fd = mesh.face_data(cells, f)
+        um = np.einsum("qi,cvi->cvq", T.phif[f], Uc)
+        up = np.einsum("qi,cvi->cvq", T.phif[f ^ 1], U[fd["nb"]])
+        a = fd["a"]                                     # [C][Qf][d]
+        area = np.sqrt(np.sum(a * a, axis=-1))
+        nrm = a / area[..., None]
+        vnm = np.einsum("cqa,caq->cq", nrm, um[:, :d, :])
+        vnp = np.einsum("cqa,caq->cq", nrm, up[:, :d, :])
+        ps, vs = numerical_flux(um[:, d], up[:, d], vnm, vnp, fd["Zm"], fd["Zp"], flux)
+        r[:, :d, :] -= np.einsum("qi,cqa->cai", T.phif[f], a * ps[..., None])
+        r[:, d, :] -= np.einsum("qi,cq->ci", T.phif[f], area * vs)
+    return r
+
+
+def mass_matrices(mesh, cells):
+    """Dense per-cell mass matrices (M_v, M_p), each float64[C][np][np]."""
+    T = tables(mesh)
+    cd = mesh.cell_data(cells)
+    wv = cd["wdet"] * cd["rho"]
+    wp = cd["wdet"] / (cd["rho"] * cd["c"] ** 2)
+    Mv = np.einsum("qi,cq,qj->cij", T.phi, wv, T.phi)
+    Mp = np.einsum("qi,cq,qj->cij", T.phi, wp, T.phi)
+    return Mv, Mp
+
+
+def cholesky_solve(M, r):
+    """Solve M x = r for stacked SPD M[C][n][n], r[C][m][n] (m right-hand sides per cell)."""
+    L = np.linalg.cholesky(M)
+    y = np.linalg.solve(L, np.swapaxes(r, -1, -2))
+    x = np.linalg.solve(np.swapaxes(L, -1, -2), y)
+    return np.swapaxes(x, -1, -2)
+
+
+def cholesky_factors(mesh, cells):
+    """Lower Cholesky factors of (M_v, M_p); cached for meshes small enough."""
+    cells = np.atleast_1d(np.asarray(cells, dtype=np.int64))
+    if mesh.nc * 2 * mesh.np_ ** 2 * 8 > 1.0e9:
+        Mv, Mp = mass_matrices(mesh, cells)
+        return np.linalg.cholesky(Mv), np.linalg.cholesky(Mp)
+    full = mesh._cache.get("chol")
+    if full is None:
+        Mv, Mp = mass_matrices(mesh, np.arange(mesh.nc))
+        full = (np.linalg.cholesky(Mv), np.linalg.cholesky(Mp))
+        mesh._cache["chol"] = full
+    return full[0][cells], full[1][cells]
+
+
+def _chol_apply(L, r):
+    y = np.linalg.solve(L, np.swapaxes(r, -1, -2))
+    x = np.linalg.solve(np.swapaxes(L, -1, -2), y)
+    return np.swapaxes(x, -1, -2)
+
+
+def apply_mass_inverse(mesh, r, cells):
+    """M^-1 r with the dense per-cell mass matrices (Cholesky)."""
+    d = mesh.dim
+    Lv, Lp = cholesky_factors(mesh, cells)
+    out = np.empty_like(r)
+    out[:, :d, :] = _chol_apply(Lv, r[:, :d, :])
+    out[:, d:, :] = _chol_apply(Lp, r[:, d:, :])
+    return out
+
+
+def _chunks(mesh, cells):
+    budget = 64 * 2 ** 20  # bytes of dense mass matrices per chunk
+    step = max(1, budget // (2 * mesh.np_ * mesh.np_ * 8))
+    for s in range(0, len(cells), step):
+        yield cells[s:s + step]
+
+
+def apply_operator(mesh, U, cells=None, flux="upwind"):
+    """L U = M^-1 (-K U) (Sec. 2.1, eq. matrix-tc-sd) on `cells` (default all).
+
+    U: float64[Nc][d+1][np] GL coefficients of the full state (neighbours are
+    read).  Returns float64[C][d+1][np].
+    """
+    U = np.asarray(U, dtype=np.float64)
+    cells = np.arange(mesh.nc) if cells is None else np.atleast_1d(np.asarray(cells, dtype=np.int64))
+    out = np.empty((len(cells), mesh.dim + 1, mesh.np_))
+    pos = 0
+    for ch in _chunks(mesh, cells):
+        r = residual(mesh, U, ch, flux)
+        out[pos:pos + len(ch)] = apply_mass_inverse(mesh, r, ch)
+        pos += len(ch)
+    return out

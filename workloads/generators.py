@@ -1,0 +1,168 @@
+"""Input recipes for the acoustic DG solver (no method arithmetic here).
+
+Conventions shared with the C ABI:
+
+* reference cell [0,1]^d; a cell's geometry is given by (q+1)^d nodes at the
+  *equispaced* points j/q of the reference cell, lexicographic with x fastest;
+* cells of the n^d box are numbered lexicographically, x fastest;
+* neighbour table columns are the faces -x,+x,-y,+y(,-z,+z); periodic wrap;
+* the state has components (v_1..v_d, p).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+TWO_PI = 2.0 * np.pi
+
+
+def _cell_index(idx, n):
+    out = 0
+    stride = 1
+    for i in idx:
+        out += (i % n) * stride
+        stride *= n
+    return out
+
+
+def box_neighbors(dim: int, ncell: int) -> np.ndarray:
+    """Periodic neighbour table int64[n^dim][2*dim] (faces -x,+x,-y,+y,-z,+z)."""
+    nc = ncell ** dim
+    nb = np.empty((nc, 2 * dim), dtype=np.int64)
+    grid = np.indices((ncell,) * dim).reshape(dim, -1)[::-1]  # grid[0] = x index (fastest)
+    for e in range(nc):
+        idx = [int(grid[a, e]) for a in range(dim)]
+        for a in range(dim):
+            for s, off in ((0, -1), (1, +1)):
+                j = list(idx)
+                j[a] += off
+                nb[e, 2 * a + s] = _cell_index(j, ncell)
+    return nb
+
+
+def box_nodes(dim: int, ncell: int, q: int, amp: float) -> np.ndarray:
+    """Geometry nodes float64[n^dim][(q+1)^dim][dim] of the periodic unit box.
+
+    Each undeformed node X is moved to X + amp * prod_j sin(2 pi X_j) in every
+    coordinate (the same displacement for all coordinates).  amp = 0 gives the
+    affine Cartesian mesh.
+    """
+    h = 1.0 / ncell
+    ref = np.arange(q + 1, dtype=np.float64) / q
+    # node offsets inside one cell, lexicographic x fastest
+    loc = np.stack(np.meshgrid(*([ref] * dim), indexing="ij"), axis=-1)  # [..][dim] with axis order (x0,x1,..)
+    loc = loc.transpose(*range(dim - 1, -1, -1), dim).reshape(-1, dim)   # x fastest
+    grid = np.indices((ncell,) * dim).reshape(dim, -1)[::-1].T          # [nc][dim], x fastest
+    X = (grid[:, None, :] + loc[None, :, :]) * h
+    disp = amp * np.prod(np.sin(TWO_PI * X), axis=-1)
+    return np.ascontiguousarray(X + disp[..., None])
+
+
+class ConstantMaterial:
+    """rho and c constant."""
+
+    def __init__(self, rho: float = 1.0, c: float = 1.0):
+        self.rho = float(rho)
+        self.c = float(c)
+
+    def __call__(self, x: np.ndarray):
+        x = np.asarray(x)
+        shp = x.shape[:-1]
+        return np.full(shp, self.rho), np.full(shp, self.c)
+
+
+class FourierMaterial:
+    """c(x) = clamp(c0 + amp * nmodes^-1/2 * sum_i a_i cos(2 pi m_i.x + phi_i), cmin, cmax), rho const.
+
+    The mode data are drawn with numpy.random.default_rng(seed): wave vectors
+    m_i uniform in {-2..2}^d without 0, a_i ~ U[-1,1], phi_i ~ U[0, 2 pi).
+    The field is 1-periodic in every coordinate.
+    """
+
+    def __init__(self, seed: int, dim: int = 3, nmodes: int = 8, amp: float = 0.3,
+                 c0: float = 1.0, cmin: float = 0.7, cmax: float = 1.3, rho: float = 1.0):
+        rng = np.random.default_rng(seed)
+        modes = []
+        while len(modes) < nmodes:
+            m = rng.integers(-2, 3, size=dim)
+            if np.any(m != 0):
+                modes.append(m)
+        self.m = np.array(modes, dtype=np.int64)
+        self.a = rng.uniform(-1.0, 1.0, size=nmodes)
+        self.phi = rng.uniform(0.0, TWO_PI, size=nmodes)
+        self.dim, self.nmodes, self.amp = dim, nmodes, amp
+        self.c0, self.cmin, self.cmax, self.rho = c0, cmin, cmax, rho
+
+    def c(self, x: np.ndarray) -> np.ndarray:
+        x = np.asarray(x, dtype=np.float64)
+        arg = TWO_PI * (x @ self.m.T.astype(np.float64)) + self.phi
+        s = np.cos(arg) @ self.a
+        return np.clip(self.c0 + self.amp / np.sqrt(self.nmodes) * s, self.cmin, self.cmax)
+
+    def __call__(self, x: np.ndarray):
+        c = self.c(x)
+        return np.full_like(c, self.rho), c
+
+
+def standing_wave_2d(x: np.ndarray, t: float = 0.0) -> np.ndarray:
+    """Exact standing wave on the periodic unit square, rho = c = 1.
+
+    p = sin(2 pi x) sin(2 pi y) cos(2 pi sqrt2 t),
+    v = -(1/sqrt2) (cos 2pi x sin 2pi y, sin 2pi x cos 2pi y) sin(2 pi sqrt2 t).
+    Returns float64[..., 3] with components (v1, v2, p).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    w = TWO_PI * np.sqrt(2.0)
+    sx, cx = np.sin(TWO_PI * x[..., 0]), np.cos(TWO_PI * x[..., 0])
+    sy, cy = np.sin(TWO_PI * x[..., 1]), np.cos(TWO_PI * x[..., 1])
+    out = np.empty(x.shape[:-1] + (3,))
+    st = np.sin(w * t)
+    out[..., 0] = -cx * sy * st / np.sqrt(2.0)
+    out[..., 1] = -sx * cy * st / np.sqrt(2.0)
+    out[..., 2] = sx * sy * np.cos(w * t)
+    return out
+
+
+def plane_wave_3d(x: np.ndarray, t: float = 0.0) -> np.ndarray:
+    """Periodic plane wave on the unit cube, rho = c = 1.
+
+    p = cos(2 pi (x+y+z) - 2 pi sqrt3 t), v = p (1,1,1)/sqrt3.
+    Returns float64[..., 4] with components (v1, v2, v3, p).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    p = np.cos(TWO_PI * (x[..., 0] + x[..., 1] + x[..., 2]) - TWO_PI * np.sqrt(3.0) * t)
+    out = np.empty(x.shape[:-1] + (4,))
+    out[..., :3] = p[..., None] / np.sqrt(3.0)
+    out[..., 3] = p
+    return out
+
+
+def gaussian_pulse(x: np.ndarray, x0, width: float = 0.05) -> np.ndarray:
+    """p = exp(-|x - x0|^2 / (2 width^2)) with minimum-image periodic distance, v = 0."""
+    x = np.asarray(x, dtype=np.float64)
+    d = x - np.asarray(x0, dtype=np.float64)
+    d -= np.round(d)
+    r2 = np.sum(d * d, axis=-1)
+    dim = x.shape[-1]
+    out = np.zeros(x.shape[:-1] + (dim + 1,))
+    out[..., dim] = np.exp(-r2 / (2.0 * width * width))
+    return out
+
+
+def random_state(seed: int, shape) -> np.ndarray:
+    """Standard-normal float64 array of the given shape."""
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+def random_points(seed: int, count: int, dim: int) -> np.ndarray:
+    """Uniform points in the unit box, float64[count][dim]."""
+    return np.random.default_rng(seed).uniform(0.0, 1.0, size=(count, dim))
+
+
+def c2_workload(ncell: int = 24, k: int = 5, seed: int = 1805):
+    """The 3D curved-hex workload: unit cube, n^3 cells deformed with amplitude
+    0.05, rho = 1, c a random Fourier field, Gaussian pulse (width 0.05) at a
+    seeded point.  Returns a dict of inputs."""
+    mat = FourierMaterial(seed, dim=3)
+    x0 = random_points(seed + 1, 1, 3)[0]
+    return dict(dim=3, ncell=ncell, k=k, q=k, amp=0.05, material=mat,
+                ic=lambda x: gaussian_pulse(x, x0, 0.05), x0=x0)

@@ -1,0 +1,280 @@
+/*
+ * dgw -- matrix-free discontinuous Galerkin solver for first-order acoustics
+ * on curved quadrilateral / hexahedral meshes, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Schoeder, Kormann, Wall, Kronbichler, "Efficient explicit time
+ * stepping of high order discontinuous Galerkin schemes for waves",
+ * arXiv:1805.03981.  Section references below are to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - dim d in {2,3}; degree k in 1..8; n = k+1 nodes per direction;
+ *    np = n^d nodes per cell; components (v_1..v_d, p), d+1 of them.
+ *  - Reference cell [0,1]^d.  The solution is stored in the Lagrange basis on
+ *    the Gauss-Lobatto (GL) nodes (Sec. 3.1: nodes on the faces keep face
+ *    access at n^(d-1) values), lexicographic with x fastest.
+ *  - State layout (device memory, FP64): u[B][n_cells][d+1][np]; B is the
+ *    batch of independent solutions (right-hand sides) sharing one mesh.
+ *  - Cell geometry: (q+1)^d nodes per cell at the equispaced reference points
+ *    j/q, lexicographic with x fastest (a degree-q map; q = k by default).
+ *  - Faces are numbered -x,+x,-y,+y,-z,+z.  Neighbour tables list, per cell
+ *    and face, the cell across it; the neighbour's matching face is the
+ *    opposite one with the same tangential orientation.
+ *  - Weak form (Sec. 2.1, eq. weak-form) with the material in a weighted
+ *    mass: (phi, rho dv/dt) = (grad phi, p) - <phi n, p*>,
+ *    (phi, dp/dt / (rho c^2)) = (grad phi, v) - <phi, v*.n>; Gauss quadrature
+ *    on n points per direction (Sec. 3); upwind flux = the paper's HDG flux
+ *    with tau = 1/(rho c) (Sec. 2.4), or central flux.
+ *  - Device pointers are caller-owned, 256-byte aligned and must not alias
+ *    unless stated.  Streams are hipStream_t passed as void* (NULL = the
+ *    null stream).  Calls that take a stream are asynchronous on it.
+ *  - Errors: every call returns a dgw_status.  Validation happens before any
+ *    launch: on an error nothing has been written.  dgw_last_error() gives
+ *    the text of the last error of the calling thread.  A mesh must not be
+ *    used from two host threads at once.
+ */
+#ifndef DGW_H
+#define DGW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int dgw_status;
+#define DGW_OK 0
+#define DGW_EINVAL (-1)        /* invalid argument or mesh                        */
+#define DGW_ENOMEM (-2)        /* device or host allocation failed / over budget  */
+#define DGW_EDEVICE (-3)       /* HIP runtime error                               */
+#define DGW_EUNSUPPORTED (-4)  /* valid but not supported (degree, boundary, ...) */
+#define DGW_EUNSTABLE (-5)     /* energy watchdog tripped (time step too large)   */
+#define DGW_EBUSY (-6)         /* resource in use                                 */
+
+enum { DGW_FLUX_UPWIND = 0, DGW_FLUX_CENTRAL = 1 };
+/* Precision of the operator arithmetic.  DGW_FP32_SPLIT: 1D contractions and
+ * flux arithmetic in FP32; state, stage and Taylor sums, metric terms and the
+ * inverse mass factors in FP64. */
+enum { DGW_FP64 = 0, DGW_FP32_SPLIT = 1 };
+enum { DGW_SCHEME_LSRK54 = 0, DGW_SCHEME_ADER = 1 };
+/* ADER flags: DGW_ADER_NOREDUCE evaluates every time derivative at k+1
+ * points per direction (Alg. 2 without the degree reduction of Sec. 3.3). */
+enum { DGW_ADER_REDUCE = 0, DGW_ADER_NOREDUCE = 1 };
+/* device = DGW_DEVICE_NONE builds the host-side setup only (no device
+ * memory): the mesh can be inspected with dgw_mesh_get but not stepped. */
+#define DGW_DEVICE_NONE (-1)
+
+/* Material callback, evaluated on the host at mapped points during setup.
+ * x: [npts][dim] physical points; writes rho[npts], c[npts]. */
+typedef void (*dgw_material_fn)(const double* x, int64_t npts, int dim, double* rho, double* c,
+                                void* ctx);
+
+typedef struct dgw_mesh dgw_mesh;
+typedef struct dgw_sources dgw_sources;
+
+/* ---------------------------------------------------------------- b1 ---- */
+typedef struct dgw_mesh_desc {
+  int dim;                   /* 2 or 3                                          */
+  int degree;                /* k, 1..8 (else DGW_EUNSUPPORTED)                 */
+  int64_t n_cells;           /* >= 1                                            */
+  int geo_degree;            /* q, 1..8; 0 = k                                  */
+  const double* geo_nodes;   /* host [n_cells][(q+1)^dim][dim]; copied          */
+  const int64_t* neighbors;  /* host [n_cells][2*dim]; -1 (boundary) gives      */
+                             /* DGW_EUNSUPPORTED (periodic / interior only)     */
+  const int* face_orient;    /* must be NULL (standard orientation)             */
+  dgw_material_fn material;  /* required                                        */
+  void* material_ctx;
+  int flux;                  /* DGW_FLUX_*                                      */
+  int precision;             /* DGW_FP64 or DGW_FP32_SPLIT                      */
+  int device;                /* HIP device ordinal or DGW_DEVICE_NONE           */
+  int max_batch;             /* >= 1: largest B accepted by the stepping calls  */
+} dgw_mesh_desc;
+
+/* Builds the setup of Sec. 3 on the host in FP64: 1D Gauss / GL rules and
+ * the basis-change, collocation-derivative, projection and embedding
+ * matrices (Sec. 3.1-3.3); the curved map at every point set (cell Gauss
+ * points, face Gauss points, the reduced Gauss sets of the degree reduction,
+ * Sec. 3.3); the pre-computed metric w det(J) J^-1, the inverse mass factors
+ * 1/(w det J rho) and rho c^2/(w det J), face area vectors w det J J^-T n and
+ * the impedances rho c of both sides of every face point.  Validates
+ * det J > 0 at every point and that the neighbour table is conforming
+ * (DGW_EINVAL otherwise) and uploads everything to the device, which the
+ * mesh owns.  *out is NULL on error. */
+dgw_status dgw_mesh_create(const dgw_mesh_desc* desc, dgw_mesh** out);
+
+/* Convenience: the periodic unit box [0,1]^dim with ncell^dim cells, each node
+ * X moved to X + amp prod_j sin(2 pi X_j) in every coordinate, geometry degree
+ * q = k, neighbours by periodic wrap.  Other fields as in dgw_mesh_desc. */
+dgw_status dgw_mesh_create_box(int dim, int ncell, int degree, double deform_amp,
+                               dgw_material_fn material, void* material_ctx, int flux,
+                               int precision, int device, int max_batch, dgw_mesh** out);
+
+/* A ready material: rho = rho0, c(x) = clamp(c0 + amp nmodes^-1/2 sum_i
+ * a_i cos(2 pi m_i.x + phi_i), cmin, cmax).  Pass dgw_material_fourier with a
+ * dgw_fourier_material* as ctx; nmodes <= 16. */
+typedef struct dgw_fourier_material {
+  int nmodes;
+  int m[16][3];
+  double a[16];
+  double phi[16];
+  double c0, amp, cmin, cmax, rho0;
+} dgw_fourier_material;
+void dgw_material_fourier(const double* x, int64_t npts, int dim, double* rho, double* c,
+                          void* ctx);
+
+/* ---------------------------------------------------------------- b2 ---- */
+void dgw_mesh_destroy(dgw_mesh* mesh);
+
+typedef struct dgw_mesh_info {
+  int dim, degree, n1d, nodes_per_cell, n_comp, geo_degree;
+  int64_t n_cells;
+  int64_t dofs;              /* per batch member: n_cells (d+1) n^d              */
+  int64_t state_bytes;       /* per batch member (FP64)                          */
+  int64_t lsrk_work_bytes;   /* per batch member, work buffer of dgw_step_lsrk   */
+  int64_t ader_work_bytes;   /* per batch member, work buffer of dgw_step_ader   */
+  int64_t device_bytes;      /* device memory owned by the mesh                  */
+  int n_levels;              /* Gauss sets of the degree reduction (Sec. 3.3)    */
+  int level_points[8];       /* points per direction of each set                 */
+  double h_min;              /* min over cells of h_K (see dt_unit)              */
+  double c_max;              /* max of c over all cell Gauss points              */
+  double dt_unit;            /* min_K(h_K / c_K) / k^1.5: dt = Cr * dt_unit      */
+                             /* (Sec. 2.3; h_K = min over the cell's Gauss points */
+                             /*  of the smallest singular value of J)            */
+  int precision, flux, max_batch, device;
+} dgw_mesh_info;
+dgw_status dgw_mesh_info_get(const dgw_mesh* mesh, dgw_mesh_info* info);
+
+/* Copies setup data to host memory (synchronous), for inspection:
+ *  DGW_GET_NODE_COORDS  [n_cells][np][dim]   physical GL node positions
+ *  DGW_GET_CELL_METRIC  [n_cells][d*d+2][np] w detJ (J^-1)_{ba} at index b*d+a,
+ *                                            then 1/(w detJ rho), rho c^2/(w detJ)
+ *  DGW_GET_FACE         [n_cells][2d][d+2][n^(d-1)] area vector a (d), Z-, Z+
+ *  DGW_GET_LEVEL(l)     [n_cells][d*d+2][m^d] same as the cell metric at the
+ *                       l-th reduced Gauss set (l >= 1), m = level_points[l] */
+enum { DGW_GET_NODE_COORDS = 0, DGW_GET_CELL_METRIC = 1, DGW_GET_FACE = 2, DGW_GET_LEVEL0 = 16 };
+#define DGW_GET_LEVEL(l) (DGW_GET_LEVEL0 + (l))
+dgw_status dgw_mesh_get(const dgw_mesh* mesh, int what, double* host_out, int64_t count);
+
+/* ---------------------------------------------------------------- b3 ---- */
+/* out = L u = -M^-1 K u (Sec. 2.1, eq. matrix-tc-sd) for B members, no source.
+ * One fused launch: GL->G basis change, pointwise metric, transposed
+ * collocation derivative, upwind face integrals with the neighbours' GL face
+ * nodes, inverse mass by basis change (Sec. 3.1).  u, out: device
+ * [B][n_cells][d+1][np]; must not alias (DGW_EINVAL).  1 <= B <= max_batch. */
+dgw_status dgw_operator_apply(dgw_mesh* mesh, const double* u, double* out, int B, void* stream);
+
+/* ---------------------------------------------------------------- sources */
+/* Point sources s_i(t) delta(x - x_i) on the pressure equation, one per batch
+ * member (member i gets source i), with a Ricker wavelet
+ * s(t) = amp (1 - 2 a tau^2) exp(-a tau^2), a = (pi f)^2, tau = t - t0.
+ * Not part of the paper.  Positions are located on the host by Newton
+ * iteration on the cell maps (lowest cell index wins); DGW_EINVAL if a point
+ * is outside the mesh. */
+typedef struct dgw_source_desc {
+  int n;                     /* number of sources = batch members they serve     */
+  const double* position;    /* host [n][dim]                                     */
+  const double* frequency;   /* host [n], peak frequency f                        */
+  const double* t0;          /* host [n] or NULL (t0 = 1.2 / f)                   */
+  const double* amplitude;   /* host [n] or NULL (1)                              */
+} dgw_source_desc;
+dgw_status dgw_sources_create(dgw_mesh* mesh, const dgw_source_desc* desc, dgw_sources** out);
+void dgw_sources_destroy(dgw_sources* src);
+
+/* ---------------------------------------------------------------- b4 ---- */
+/* nsteps steps of the five-stage fourth-order 2N-storage Runge-Kutta scheme
+ * (Sec. 2.2, LSRK4(5); Carpenter-Kennedy coefficients) from t0 with step dt:
+ * du <- A_i du + dt (L u + s(t + c_i dt) g); u <- u + B_i du.  The vector
+ * update is fused into the operator sweep (one launch per stage).  u advances
+ * in place; work: device buffer of B * lsrk_work_bytes (stage register and
+ * the ping-pong copy that keeps neighbours reading the old stage).  src may
+ * be NULL (else src->n >= B).  dt <= 0 or non-finite: DGW_EINVAL. */
+dgw_status dgw_step_lsrk(dgw_mesh* mesh, int scheme, double t0, double dt, int nsteps,
+                         double* u, double* work, int B, const dgw_sources* src, void* stream);
+
+/* ---------------------------------------------------------------- b5 ---- */
+/* nsteps ADER steps of order k+1 (Sec. 2.3, eq. ader): sweep 1 evaluates the
+ * cell-local Taylor-Cauchy-Kowalevski sum I in the collocated Gauss basis
+ * with the degree reduction every second derivative (Sec. 3.2-3.3, Alg. 3)
+ * and writes it in the GL basis; sweep 2 applies u <- u + L(I) (+ the exact
+ * time integral of the source).  Contract as dgw_step_lsrk;
+ * work = B * ader_work_bytes.  flags: DGW_ADER_REDUCE or DGW_ADER_NOREDUCE. */
+dgw_status dgw_step_ader(dgw_mesh* mesh, int flags, double t0, double dt, int nsteps, double* u,
+                         double* work, int B, const dgw_sources* src, void* stream);
+
+/* Energy (twice the acoustic energy) sum_K (v, rho v)_K + (p, p/(rho c^2))_K
+ * per member, by Gauss quadrature; host_out[B]; synchronous on stream. */
+dgw_status dgw_energy(dgw_mesh* mesh, const double* u, int B, double* host_out, void* stream);
+
+/* ---------------------------------------------------------------- b6 ---- */
+typedef struct dgw_solve_desc {
+  int scheme;                /* DGW_SCHEME_LSRK54 or DGW_SCHEME_ADER              */
+  int ader_flags;
+  double courant;            /* used when dt <= 0: dt = courant * dt_unit         */
+  double dt;                 /* rounded down so that dt = (t_end-t0)/nsteps       */
+  double t0, t_end;
+  const dgw_sources* sources;/* may be NULL                                       */
+  int use_graph;             /* capture one step in a hipGraph and replay it      */
+  int autotune;              /* time the launch shapes once and keep the fastest  */
+  int watchdog_every;        /* energy check every N steps (0 = off)              */
+  double watchdog_growth;    /* DGW_EUNSTABLE if energy > growth * initial (10)   */
+  void* stream;
+} dgw_solve_desc;
+typedef struct dgw_solve_report {
+  int64_t steps;
+  double dt, wall_s, dof_steps_per_s;
+  double energy0, energy_end;  /* member 0 */
+} dgw_solve_report;
+/* Synchronous solve of B members from t0 to t_end; work as for the scheme. */
+dgw_status dgw_solve_batch(dgw_mesh* mesh, const dgw_solve_desc* desc, double* u, double* work,
+                           int B, dgw_solve_report* report);
+
+/* ---------------------------------------------------------------- b7 ---- */
+typedef struct dgw_request {
+  double arrival_s;          /* seconds after serving starts                       */
+  int dim, ncell, degree, scheme, precision;
+  double t_end, courant, deform_amp;
+  dgw_fourier_material material;
+  double ic_center[3], ic_width; /* Gaussian pressure pulse, v = 0                 */
+} dgw_request;
+typedef struct dgw_result {
+  dgw_status status;
+  double t_arrive, t_admit, t_done;  /* seconds since serving started              */
+  int64_t steps, dofs;
+  double energy0, energy_end;
+  double* state_host;        /* optional caller buffer [dofs] for the final state  */
+} dgw_result;
+typedef struct dgw_server_desc {
+  int device;
+  double hbm_budget_bytes;   /* admission budget for all live requests             */
+  int max_live;              /* most requests in flight (streams)                  */
+  int realtime;              /* 1: honour arrival_s; 0: all arrive at 0            */
+} dgw_server_desc;
+typedef struct dgw_serve_report {
+  int n_done, n_failed;
+  double wall_s, p50_s, p99_s, dof_steps_per_s, max_wait_s;
+} dgw_serve_report;
+/* Replays a request trace: a request is admitted once it has arrived and its
+ * device footprint fits the budget; admitted requests run concurrently on
+ * their own streams, one step per scheduling round each, and retire when
+ * done.  Requests larger than the whole budget fail with DGW_ENOMEM in their
+ * result; the others continue.  Synchronous. */
+dgw_status dgw_serve(const dgw_server_desc* desc, const dgw_request* reqs, int n, dgw_result* out,
+                     dgw_serve_report* report);
+
+/* Footprint in bytes that dgw_serve charges a request (mesh + state + work). */
+int64_t dgw_request_footprint(const dgw_request* req);
+
+/* ---------------------------------------------------------------- b8 ---- */
+const char* dgw_last_error(void);
+const char* dgw_version(void);
+
+/* 1D tables of the setup, for inspection: what = 0 Gauss points, 1 Gauss
+ * weights, 2 GL points, 3 GL weights (n values each, on [0,1]); 4 S (GL->G,
+ * n x n, S[q][j] = l^GL_j(xi^G_q)), 5 S^-1, 6 D (collocation derivative on
+ * the Gauss points, D[q][j] = l^G_j'(xi^G_q)). */
+dgw_status dgw_basis_1d(int n, int what, double* host_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGW_H */

@@ -30,7 +30,7 @@ class Mesh:
     callable x[...,d] -> (rho, c).
     """
 
-    def __init__(self, dim, k, geo_nodes, neighbors, material):
+    def __init__(self, dim, k, geo_nodes, neighbors, material, cache=True):
         self.dim = int(dim)
         self.k = int(k)
         self.n = self.k + 1
@@ -54,6 +54,7 @@ class Mesh:
         self.face_ref = [self._face_points(f) for f in range(self.nface)]
         self.face_w = basis.tensor_weights(self.wg, self.dim - 1) if self.dim > 1 else np.ones(1)
         self._cache = {}
+        self._allow_cache = bool(cache)
 
     # ---- reference geometry --------------------------------------------
     def _face_points(self, f):
@@ -90,7 +91,7 @@ class Mesh:
 
     # ---- cached per-point data ---------------------------------------------
     def _cacheable(self):
-        return self.nc * self.np_ * 40 * 8 < 1.5e9
+        return self._allow_cache and self.nc * self.np_ * 40 * 8 < 1.5e9
 
     def _sliced(self, key, fn, cells):
         cells = np.atleast_1d(np.asarray(cells, dtype=np.int64))

@@ -111,18 +111,10 @@ def mass_matrices(mesh, cells):
     return Mv, Mp
 
 
-def cholesky_solve(M, r):
-    """Solve M x = r for stacked SPD M[C][n][n], r[C][m][n] (m right-hand sides per cell)."""
-    L = np.linalg.cholesky(M)
-    y = np.linalg.solve(L, np.swapaxes(r, -1, -2))
-    x = np.linalg.solve(np.swapaxes(L, -1, -2), y)
-    return np.swapaxes(x, -1, -2)
-
-
 def cholesky_factors(mesh, cells):
     """Lower Cholesky factors of (M_v, M_p); cached for meshes small enough."""
     cells = np.atleast_1d(np.asarray(cells, dtype=np.int64))
-    if mesh.nc * 2 * mesh.np_ ** 2 * 8 > 1.0e9:
+    if not mesh._allow_cache or mesh.nc * 2 * mesh.np_ ** 2 * 8 > 1.0e9:
         Mv, Mp = mass_matrices(mesh, cells)
         return np.linalg.cholesky(Mv), np.linalg.cholesky(Mp)
     full = mesh._cache.get("chol")

@@ -1,0 +1,840 @@
+// C-ABI entry points of libdgw: mesh lifecycle, operator application, the
+// LSRK(5,4) and ADER steppers, point sources, energy and the batch solver.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <tuple>
+
+#include "dgw_host.hpp"
+
+namespace dgw {
+
+const Launchers* launchers_d2_f64(int n);
+const Launchers* launchers_d2_f32(int n);
+const Launchers* launchers_d3_f64(int n);
+const Launchers* launchers_d3_f32(int n);
+
+const Launchers* launchers(int dim, int n, int precision) {
+  if (dim == 2) return precision ? launchers_d2_f32(n) : launchers_d2_f64(n);
+  if (dim == 3) return precision ? launchers_d3_f32(n) : launchers_d3_f64(n);
+  return nullptr;
+}
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+dgw_status fail(dgw_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+__global__ void advance_counter(long long* ctr, int by) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] += by;
+}
+
+// Five-stage fourth-order 2N-storage Runge-Kutta (Carpenter & Kennedy 1994),
+// Williamson form; the paper's LSRK4(5) family (Sec. 2.2).
+struct Lsrk54 {
+  double A[5], B[5], C[5];
+  Lsrk54() {
+    const long double a[5][2] = {{0, 1},
+                                 {-567301805773.0L, 1357537059087.0L},
+                                 {-2404267990393.0L, 2016746695238.0L},
+                                 {-3550918686646.0L, 2091501179385.0L},
+                                 {-1275806237668.0L, 842570457699.0L}};
+    const long double b[5][2] = {{1432997174477.0L, 9575080441755.0L},
+                                 {5161836677717.0L, 13612068292357.0L},
+                                 {1720146321549.0L, 2090206949498.0L},
+                                 {3134564353537.0L, 4481467310338.0L},
+                                 {2277821191437.0L, 14882151754819.0L}};
+    const long double c[5][2] = {{0, 1},
+                                 {1432997174477.0L, 9575080441755.0L},
+                                 {2526269341429.0L, 6820363962896.0L},
+                                 {2006345519317.0L, 3224310063776.0L},
+                                 {2802321613138.0L, 2924317926251.0L}};
+    for (int i = 0; i < 5; ++i) {
+      A[i] = (double)(a[i][0] / a[i][1]);
+      B[i] = (double)(b[i][0] / b[i][1]);
+      C[i] = (double)(c[i][0] / c[i][1]);
+    }
+  }
+};
+static const Lsrk54 kLsrk;
+
+static int ipw(int b, int e) {
+  int r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
+
+static int64_t state_elems(const dgw_mesh* m) { return m->hs.nc * m->ncomp * m->np; }
+
+static LaunchShape default_shape(int lds_per_cell, int lines_per_cell) {
+  LaunchShape s;
+  s.cpw = std::max(1, std::min(16, 40960 / std::max(1, lds_per_cell)));
+  const int lines = s.cpw * lines_per_cell;
+  s.nth = lines >= 192 ? 256 : (lines >= 96 ? 128 : 64);
+  return s;
+}
+
+static void* tab_ptr(const dgw_mesh* m) {
+  return m->precision ? static_cast<void*>(m->d_tab32) : static_cast<void*>(m->d_tab64);
+}
+
+static dgw_status check_mesh(const dgw_mesh* m) {
+  if (!m) return fail(DGW_EINVAL, "mesh is NULL");
+  if (m->device < 0) return fail(DGW_EINVAL, "mesh was created without a device (DGW_DEVICE_NONE)");
+  return DGW_OK;
+}
+
+static dgw_status set_device(const dgw_mesh* m) {
+  DGW_HIP(hipSetDevice(m->device));
+  return DGW_OK;
+}
+
+static void fill_sources(SourceParams& sp, const dgw_sources* src) {
+  std::memset(&sp, 0, sizeof(sp));
+  if (!src) return;
+  sp.cell = src->d_cell;
+  sp.gvec = src->d_gvec;
+  for (int l = 0; l < kMaxLevels; ++l) sp.glev[l] = src->d_glev[l];
+  sp.wave = src->d_wave;
+}
+
+static OpParams op_params(const dgw_mesh* m, int B, const dgw_sources* src) {
+  OpParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.geo_cell = m->d_cell;
+  p.geo_face = m->d_face;
+  p.nb = m->d_nb;
+  p.tab = tab_ptr(m);
+  p.nc = m->hs.nc;
+  p.cpw = m->op_shape.cpw;
+  p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
+  p.B = B;
+  p.central = m->flux == DGW_FLUX_CENTRAL;
+  fill_sources(p.src, src);
+  return p;
+}
+
+static TckParams tck_params(const dgw_mesh* m, int B, const dgw_sources* src) {
+  TckParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.geo_lev[0] = m->d_cell;
+  for (int l = 1; l < kMaxLevels; ++l) p.geo_lev[l] = m->d_level[l];
+  p.tab = tab_ptr(m);
+  p.tab64 = m->d_tab64;
+  p.nc = m->hs.nc;
+  p.cpw = m->tck_shape.cpw;
+  p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
+  p.B = B;
+  fill_sources(p.src, src);
+  return p;
+}
+
+static dgw_status check_batch(const dgw_mesh* m, int B, const dgw_sources* src) {
+  if (B < 1 || B > m->max_batch) return fail(DGW_EINVAL, "B must be in 1..max_batch");
+  if ((int64_t)B * (m->hs.nc / std::max<int64_t>(1, m->op_shape.cpw) + 1) > INT32_MAX)
+    return fail(DGW_EINVAL, "grid too large");
+  if (src) {
+    if (src->mesh != m) return fail(DGW_EINVAL, "sources were created for another mesh");
+    if (src->n < B) return fail(DGW_EINVAL, "fewer sources than batch members");
+  }
+  return DGW_OK;
+}
+
+// One LSRK step (5 fused stages).  cur/oth: ping-pong state buffers; returns
+// with the new state in *cur.
+static dgw_status lsrk_step(dgw_mesh* m, int B, const dgw_sources* src, double t0, double dt, int step_add,
+                            const long long* ctr, double*& cur, double*& oth, double* du, hipStream_t s) {
+  OpParams p = op_params(m, B, src);
+  p.dt = dt;
+  p.du = du;
+  p.time = StepTime{ctr, t0, dt, step_add, 0.0};
+  for (int i = 0; i < 5; ++i) {
+    p.u = cur;
+    p.u_next = oth;
+    p.acoef = kLsrk.A[i];
+    p.bcoef = kLsrk.B[i];
+    p.time.t_off = kLsrk.C[i] * dt;
+    DGW_HIP(m->L->op[EPI_LSRK](p, m->op_shape.nth, s));
+    std::swap(cur, oth);
+  }
+  return DGW_OK;
+}
+
+static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* src, double t0, double dt,
+                            int step_add, const long long* ctr, double*& cur, double*& oth, double* I,
+                            hipStream_t s) {
+  TckParams tp = tck_params(m, B, src);
+  tp.u = cur;
+  tp.I = I;
+  tp.dt = dt;
+  tp.time = StepTime{ctr, t0, dt, step_add, 0.0};
+  DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0](tp, m->tck_shape.nth, s));
+  OpParams p = op_params(m, B, src);
+  p.u = I;
+  p.u_base = cur;
+  p.u_next = oth;
+  p.time = StepTime{ctr, t0, dt, step_add, 0.0};
+  DGW_HIP(m->L->op[EPI_ADD](p, m->op_shape.nth, s));
+  std::swap(cur, oth);
+  return DGW_OK;
+}
+
+static dgw_status energy_impl(dgw_mesh* m, const double* u, int B, double* host_out, hipStream_t s) {
+  EnergyParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.u = u;
+  p.geo_cell = m->d_cell;
+  p.tab = tab_ptr(m);
+  p.partial = m->d_partial;
+  p.nc = m->hs.nc;
+  p.cpw = std::max(1, std::min(16, 16384 / m->L->energy_lds_per_cell));
+  p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
+  p.B = B;
+  DGW_HIP(m->L->energy(p, 256, s));
+  std::vector<double> part((size_t)B * p.groups);
+  DGW_HIP(hipMemcpyAsync(part.data(), m->d_partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  DGW_HIP(hipStreamSynchronize(s));
+  for (int b = 0; b < B; ++b) {
+    double acc = 0;
+    for (int g = 0; g < p.groups; ++g) acc += part[(size_t)b * p.groups + g];
+    host_out[b] = acc;
+  }
+  return DGW_OK;
+}
+
+// Times the candidate launch shapes of the operator and TCK kernels on
+// scratch buffers and keeps the fastest (Sec. 4.4's throughput depends on how
+// many cells share a workgroup; the best choice depends on k, d, precision).
+static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
+  static std::mutex cache_mtx;
+  static std::map<std::tuple<int, int, int, int, int64_t>, std::pair<LaunchShape, LaunchShape>> cache;
+  const auto key = std::make_tuple(m->hs.dim, m->hs.k, m->precision, B, m->hs.nc);
+  {
+    std::lock_guard<std::mutex> lk(cache_mtx);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      m->op_shape = it->second.first;
+      m->tck_shape = it->second.second;
+      m->tuned = true;
+      return DGW_OK;
+    }
+  }
+  const int64_t ne = state_elems(m) * B;
+  double *a = nullptr, *b = nullptr;
+  DGW_HIP(hipMalloc(&a, ne * sizeof(double)));
+  if (hipMalloc(&b, ne * sizeof(double)) != hipSuccess) {
+    (void)hipFree(a);
+    return fail(DGW_ENOMEM, "autotune scratch");
+  }
+  DGW_HIP(hipMemsetAsync(a, 0, ne * sizeof(double), s));
+  hipEvent_t e0, e1;
+  DGW_HIP(hipEventCreate(&e0));
+  DGW_HIP(hipEventCreate(&e1));
+  const int64_t lds_limit = 160 * 1024;
+  auto time_it = [&](auto&& launch) -> float {
+    for (int w = 0; w < 2; ++w)
+      if (launch() != hipSuccess) return 1e30f;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < 5; ++r) (void)launch();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return ms;
+  };
+  const int cpws[] = {1, 2, 3, 4, 6, 8, 12, 16};
+  const int nths[] = {64, 128, 256};
+  LaunchShape best_op = m->op_shape, best_tck = m->tck_shape;
+  float t_op = 1e30f, t_tck = 1e30f;
+  for (int cpw : cpws)
+    for (int nth : nths) {
+      if ((int64_t)cpw * m->L->op_lds_per_cell <= lds_limit) {
+        OpParams p = op_params(m, B, nullptr);
+        p.cpw = cpw;
+        p.groups = (int)((m->hs.nc + cpw - 1) / cpw);
+        p.u = a;
+        p.out = b;
+        const float t = time_it([&]() { return m->L->op[EPI_STORE](p, nth, s); });
+        if (t < t_op) {
+          t_op = t;
+          best_op = LaunchShape{cpw, nth};
+        }
+      }
+      if ((int64_t)cpw * m->L->tck_lds_per_cell <= lds_limit) {
+        TckParams p = tck_params(m, B, nullptr);
+        p.cpw = cpw;
+        p.groups = (int)((m->hs.nc + cpw - 1) / cpw);
+        p.u = a;
+        p.I = b;
+        p.dt = 1e-3;
+        const float t = time_it([&]() { return m->L->tck[0](p, nth, s); });
+        if (t < t_tck) {
+          t_tck = t;
+          best_tck = LaunchShape{cpw, nth};
+        }
+      }
+    }
+  (void)hipGetLastError();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  m->op_shape = best_op;
+  m->tck_shape = best_tck;
+  m->tuned = true;
+  std::lock_guard<std::mutex> lk(cache_mtx);
+  cache[key] = {best_op, best_tck};
+  return DGW_OK;
+}
+
+static dgw_status upload(dgw_mesh* m) {
+  auto& hs = m->hs;
+  auto alloc_copy = [&](auto*& dst, const auto* src, size_t count) -> dgw_status {
+    using E = std::remove_pointer_t<std::remove_reference_t<decltype(dst)>>;
+    const size_t bytes = count * sizeof(E);
+    if (hipMalloc(reinterpret_cast<void**>(&dst), std::max<size_t>(bytes, 256)) != hipSuccess) {
+      (void)hipGetLastError();
+      dst = nullptr;
+      return fail(DGW_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    m->device_bytes += bytes;
+    if (bytes) DGW_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return DGW_OK;
+  };
+  dgw_status st;
+  if ((st = alloc_copy(m->d_cell, hs.cell.data(), hs.cell.size()))) return st;
+  if ((st = alloc_copy(m->d_face, hs.face.data(), hs.face.size()))) return st;
+  if ((st = alloc_copy(m->d_nb, hs.nb.data(), hs.nb.size()))) return st;
+  for (int l = 1; l < m->nlev; ++l)
+    if ((st = alloc_copy(m->d_level[l], hs.level[l].data(), hs.level[l].size()))) return st;
+  const std::vector<double> t64 = build_tables(hs.n);
+  std::vector<float> t32(t64.begin(), t64.end());
+  if ((st = alloc_copy(m->d_tab64, t64.data(), t64.size()))) return st;
+  if ((st = alloc_copy(m->d_tab32, t32.data(), t32.size()))) return st;
+  const int cpw_e = std::max(1, std::min(16, 16384 / m->L->energy_lds_per_cell));
+  const size_t groups_e = (size_t)((hs.nc + cpw_e - 1) / cpw_e);
+  std::vector<double> zeros((size_t)m->max_batch * groups_e, 0.0);
+  if ((st = alloc_copy(m->d_partial, zeros.data(), zeros.size()))) return st;
+  return DGW_OK;
+}
+
+static void release(dgw_mesh* m) {
+  if (!m) return;
+  if (m->device >= 0) {
+    (void)hipSetDevice(m->device);
+    (void)hipFree(m->d_cell);
+    (void)hipFree(m->d_face);
+    (void)hipFree(m->d_nb);
+    for (auto* p : m->d_level) (void)hipFree(p);
+    (void)hipFree(m->d_tab64);
+    (void)hipFree(m->d_tab32);
+    (void)hipFree(m->d_partial);
+  }
+  delete m;
+}
+
+}  // namespace dgw
+
+using namespace dgw;
+
+extern "C" {
+
+const char* dgw_last_error(void) { return g_last_error.c_str(); }
+const char* dgw_version(void) { return "dgw 0.1 (gfx950)"; }
+
+dgw_status dgw_basis_1d(int n, int what, double* out) {
+  if (n < 1 || n > 9 || !out) return fail(DGW_EINVAL, "n must be in 1..9");
+  const Rule g = gauss_rule(n);
+  switch (what) {
+    case 0:
+    case 1:
+      for (int i = 0; i < n; ++i) out[i] = (double)(what == 0 ? g.x[i] : g.w[i]);
+      return DGW_OK;
+    case 2:
+    case 3: {
+      if (n < 2) return fail(DGW_EINVAL, "Gauss-Lobatto needs n >= 2");
+      const Rule gl = gauss_lobatto_rule(n);
+      for (int i = 0; i < n; ++i) out[i] = (double)(what == 2 ? gl.x[i] : gl.w[i]);
+      return DGW_OK;
+    }
+    case 4:
+    case 5:
+    case 6: {
+      if (n < 2) return fail(DGW_EINVAL, "n >= 2 needed");
+      const std::vector<double> t = build_tables(n);
+      const int off = what == 4 ? tab_S(n) : (what == 5 ? tab_Sinv(n) : tab_D(n));
+      std::copy(t.begin() + off, t.begin() + off + n * n, out);
+      return DGW_OK;
+    }
+  }
+  return fail(DGW_EINVAL, "unknown table");
+}
+
+dgw_status dgw_mesh_create(const dgw_mesh_desc* desc, dgw_mesh** out) {
+  if (!out) return fail(DGW_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(DGW_EINVAL, "desc is NULL");
+  if (desc->dim != 2 && desc->dim != 3) return fail(DGW_EUNSUPPORTED, "dim must be 2 or 3");
+  if (desc->degree < 1 || desc->degree > 8) return fail(DGW_EUNSUPPORTED, "degree must be in 1..8");
+  if (desc->n_cells < 1) return fail(DGW_EINVAL, "n_cells must be >= 1");
+  if (!desc->geo_nodes || !desc->neighbors || !desc->material)
+    return fail(DGW_EINVAL, "geo_nodes, neighbors and material are required");
+  if (desc->face_orient) return fail(DGW_EUNSUPPORTED, "only the standard face orientation is supported");
+  if (desc->flux != DGW_FLUX_UPWIND && desc->flux != DGW_FLUX_CENTRAL) return fail(DGW_EINVAL, "bad flux");
+  if (desc->precision != DGW_FP64 && desc->precision != DGW_FP32_SPLIT) return fail(DGW_EINVAL, "bad precision");
+  if (desc->max_batch < 1) return fail(DGW_EINVAL, "max_batch must be >= 1");
+  if (desc->n_cells > (int64_t)1 << 30) return fail(DGW_EUNSUPPORTED, "too many cells");
+  std::unique_ptr<dgw_mesh> m(new (std::nothrow) dgw_mesh);
+  if (!m) return fail(DGW_ENOMEM, "host allocation");
+  m->precision = desc->precision;
+  m->flux = desc->flux;
+  m->device = desc->device;
+  m->max_batch = desc->max_batch;
+  const int n = desc->degree + 1;
+  m->np = ipw(n, desc->dim);
+  m->nf = ipw(n, desc->dim - 1);
+  m->ncomp = desc->dim + 1;
+  m->nlev = num_levels(n);
+  for (int l = 0; l < m->nlev; ++l) m->level_pts.push_back(n - 2 * l);
+  m->L = launchers(desc->dim, n, desc->precision);
+  if (!m->L) return fail(DGW_EUNSUPPORTED, "no kernels for this dim/degree");
+  try {
+    dgw_status st = build_setup(*desc, m->hs);
+    if (st) return st;
+  } catch (const std::bad_alloc&) {
+    return fail(DGW_ENOMEM, "host allocation during setup");
+  }
+  m->op_shape = default_shape(m->L->op_lds_per_cell, m->ncomp * m->nf);
+  m->tck_shape = default_shape(m->L->tck_lds_per_cell, m->ncomp * m->nf);
+  if (m->device >= 0) {
+    if (hipSetDevice(m->device) != hipSuccess) return fail(DGW_EDEVICE, "hipSetDevice failed");
+    dgw_status st = upload(m.get());
+    if (st) {
+      release(m.release());
+      return st;
+    }
+    // the host copy of the bulk geometry is not needed once uploaded
+    std::vector<double>().swap(m->hs.cell);
+    std::vector<double>().swap(m->hs.face);
+    for (auto& v : m->hs.level) std::vector<double>().swap(v);
+  }
+  *out = m.release();
+  return DGW_OK;
+}
+
+void dgw_mesh_destroy(dgw_mesh* mesh) { release(mesh); }
+
+dgw_status dgw_mesh_info_get(const dgw_mesh* m, dgw_mesh_info* info) {
+  if (!m || !info) return fail(DGW_EINVAL, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->dim = m->hs.dim;
+  info->degree = m->hs.k;
+  info->n1d = m->hs.n;
+  info->nodes_per_cell = m->np;
+  info->n_comp = m->ncomp;
+  info->geo_degree = m->hs.q;
+  info->n_cells = m->hs.nc;
+  info->dofs = state_elems(m);
+  info->state_bytes = info->dofs * 8;
+  info->lsrk_work_bytes = 2 * info->state_bytes;
+  info->ader_work_bytes = 2 * info->state_bytes;
+  info->device_bytes = m->device_bytes;
+  info->n_levels = m->nlev;
+  for (int l = 0; l < m->nlev && l < 8; ++l) info->level_points[l] = m->level_pts[l];
+  info->h_min = m->hs.h_min;
+  info->c_max = m->hs.c_max;
+  info->dt_unit = m->hs.dt_unit;
+  info->precision = m->precision;
+  info->flux = m->flux;
+  info->max_batch = m->max_batch;
+  info->device = m->device;
+  return DGW_OK;
+}
+
+dgw_status dgw_mesh_get(const dgw_mesh* m, int what, double* host_out, int64_t count) {
+  if (!m || !host_out) return fail(DGW_EINVAL, "NULL argument");
+  const auto& hs = m->hs;
+  const int d = hs.dim;
+  auto fetch = [&](const std::vector<double>& h, const double* dev, size_t n) -> dgw_status {
+    if ((int64_t)n != count) return fail(DGW_EINVAL, "count must be " + std::to_string(n));
+    if (!h.empty()) {
+      std::copy(h.begin(), h.end(), host_out);
+      return DGW_OK;
+    }
+    if (!dev) return fail(DGW_EINVAL, "no such data");
+    DGW_HIP(hipSetDevice(m->device));
+    DGW_HIP(hipMemcpy(host_out, dev, n * sizeof(double), hipMemcpyDeviceToHost));
+    return DGW_OK;
+  };
+  if (what == DGW_GET_NODE_COORDS) {
+    std::vector<double> x;
+    node_coords(hs, x);
+    if ((int64_t)x.size() != count) return fail(DGW_EINVAL, "count must be " + std::to_string(x.size()));
+    std::copy(x.begin(), x.end(), host_out);
+    return DGW_OK;
+  }
+  if (what == DGW_GET_CELL_METRIC) return fetch(hs.cell, m->d_cell, (size_t)hs.nc * (d * d + 2) * m->np);
+  if (what == DGW_GET_FACE) return fetch(hs.face, m->d_face, (size_t)hs.nc * 2 * d * (d + 2) * m->nf);
+  if (what > DGW_GET_LEVEL0 && what < DGW_GET_LEVEL0 + m->nlev) {
+    const int l = what - DGW_GET_LEVEL0;
+    const size_t sz = (size_t)hs.nc * (d * d + 2) * ipw(m->level_pts[l], d);
+    return fetch(l < (int)hs.level.size() ? hs.level[l] : std::vector<double>(), m->d_level[l], sz);
+  }
+  return fail(DGW_EINVAL, "unknown item");
+}
+
+dgw_status dgw_operator_apply(dgw_mesh* m, const double* u, double* out, int B, void* stream) {
+  dgw_status st = check_mesh(m);
+  if (st) return st;
+  if (!u || !out) return fail(DGW_EINVAL, "NULL state pointer");
+  if ((st = check_batch(m, B, nullptr))) return st;
+  const int64_t bytes = state_elems(m) * 8 * B;
+  if ((const char*)u < (const char*)out + bytes && (const char*)out < (const char*)u + bytes)
+    return fail(DGW_EINVAL, "u and out must not alias");
+  std::lock_guard<std::mutex> lk(m->mtx);
+  if ((st = set_device(m))) return st;
+  OpParams p = op_params(m, B, nullptr);
+  p.u = u;
+  p.out = out;
+  DGW_HIP(m->L->op[EPI_STORE](p, m->op_shape.nth, (hipStream_t)stream));
+  return DGW_OK;
+}
+
+static dgw_status check_step(dgw_mesh* m, double dt, int nsteps, double* u, double* work, int B,
+                             const dgw_sources* src) {
+  dgw_status st = check_mesh(m);
+  if (st) return st;
+  if (!u || !work) return fail(DGW_EINVAL, "NULL state or work pointer");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(DGW_EINVAL, "dt must be positive and finite");
+  if (nsteps < 0) return fail(DGW_EINVAL, "nsteps must be >= 0");
+  if ((st = check_batch(m, B, src))) return st;
+  const int64_t bytes = state_elems(m) * 8 * B;
+  if ((char*)u < (char*)work + 2 * bytes && (char*)work < (char*)u + bytes)
+    return fail(DGW_EINVAL, "u and work must not alias");
+  return DGW_OK;
+}
+
+dgw_status dgw_step_lsrk(dgw_mesh* m, int scheme, double t0, double dt, int nsteps, double* u, double* work,
+                         int B, const dgw_sources* src, void* stream) {
+  if (scheme != DGW_SCHEME_LSRK54) return fail(DGW_EUNSUPPORTED, "only DGW_SCHEME_LSRK54");
+  dgw_status st = check_step(m, dt, nsteps, u, work, B, src);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(m->mtx);
+  if ((st = set_device(m))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  double* du = work;
+  double* cur = u;
+  double* oth = work + state_elems(m) * B;
+  for (int k = 0; k < nsteps; ++k)
+    if ((st = lsrk_step(m, B, src, t0, dt, k, nullptr, cur, oth, du, s))) return st;
+  if (cur != u) DGW_HIP(hipMemcpyAsync(u, cur, state_elems(m) * 8 * B, hipMemcpyDeviceToDevice, s));
+  return DGW_OK;
+}
+
+dgw_status dgw_step_ader(dgw_mesh* m, int flags, double t0, double dt, int nsteps, double* u, double* work, int B,
+                         const dgw_sources* src, void* stream) {
+  if (flags & ~DGW_ADER_NOREDUCE) return fail(DGW_EINVAL, "unknown ADER flags");
+  dgw_status st = check_step(m, dt, nsteps, u, work, B, src);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(m->mtx);
+  if ((st = set_device(m))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  double* I = work;
+  double* cur = u;
+  double* oth = work + state_elems(m) * B;
+  for (int k = 0; k < nsteps; ++k)
+    if ((st = ader_step(m, flags, B, src, t0, dt, k, nullptr, cur, oth, I, s))) return st;
+  if (cur != u) DGW_HIP(hipMemcpyAsync(u, cur, state_elems(m) * 8 * B, hipMemcpyDeviceToDevice, s));
+  return DGW_OK;
+}
+
+dgw_status dgw_energy(dgw_mesh* m, const double* u, int B, double* host_out, void* stream) {
+  dgw_status st = check_mesh(m);
+  if (st) return st;
+  if (!u || !host_out) return fail(DGW_EINVAL, "NULL argument");
+  if ((st = check_batch(m, B, nullptr))) return st;
+  std::lock_guard<std::mutex> lk(m->mtx);
+  if ((st = set_device(m))) return st;
+  return energy_impl(m, u, B, host_out, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------- sources
+dgw_status dgw_sources_create(dgw_mesh* m, const dgw_source_desc* desc, dgw_sources** out) {
+  if (!out) return fail(DGW_EINVAL, "out is NULL");
+  *out = nullptr;
+  dgw_status st = check_mesh(m);
+  if (st) return st;
+  if (!desc || desc->n < 1 || !desc->position || !desc->frequency) return fail(DGW_EINVAL, "bad source desc");
+  const auto& hs = m->hs;
+  const int d = hs.dim, n = hs.n, np = m->np, ng = ipw(hs.q + 1, d);
+  std::unique_ptr<dgw_sources> S(new dgw_sources);
+  S->mesh = m;
+  S->n = desc->n;
+  // bounding boxes of the geometry nodes (with a margin for curved faces)
+  std::vector<double> lo((size_t)hs.nc * d), hi((size_t)hs.nc * d);
+  for (int64_t c = 0; c < hs.nc; ++c)
+    for (int a = 0; a < d; ++a) {
+      double mn = 1e300, mx = -1e300;
+      for (int g = 0; g < ng; ++g) {
+        const double v = hs.geo_nodes[(c * ng + g) * d + a];
+        mn = std::min(mn, v);
+        mx = std::max(mx, v);
+      }
+      const double pad = 0.1 * (mx - mn) + 1e-12;
+      lo[c * d + a] = mn - pad;
+      hi[c * d + a] = mx + pad;
+    }
+  const Rule g = gauss_rule(n);
+  const std::vector<double> tab = build_tables(n);
+  std::vector<double> gvec((size_t)S->n * np), wave((size_t)S->n * 3);
+  std::vector<std::vector<double>> glev(m->nlev);
+  for (int l = 0; l < m->nlev; ++l) glev[l].assign((size_t)S->n * ipw(m->level_pts[l], d), 0.0);
+  S->cell.resize(S->n);
+  std::vector<double> mu(np);
+  for (int i = 0; i < S->n; ++i) {
+    const double* xs = desc->position + (size_t)i * d;
+    int64_t found = -1;
+    double xi[3] = {0.5, 0.5, 0.5};
+    for (int64_t c = 0; c < hs.nc && found < 0; ++c) {
+      bool in = true;
+      for (int a = 0; a < d; ++a) in = in && xs[a] >= lo[c * d + a] && xs[a] <= hi[c * d + a];
+      if (!in) continue;
+      double z[3] = {0.5, 0.5, 0.5};
+      bool ok = false;
+      for (int it = 0; it < 50; ++it) {
+        double x[3], J[9], Ji[9], r[3];
+        map_point(hs, c, z, x, J);
+        double err = 0;
+        for (int a = 0; a < d; ++a) {
+          r[a] = x[a] - xs[a];
+          err = std::max(err, std::fabs(r[a]));
+        }
+        if (err < 1e-12) {
+          ok = true;
+          break;
+        }
+        // z -= J^-1 r
+        if (d == 2) {
+          const double det = J[0] * J[3] - J[1] * J[2];
+          Ji[0] = J[3] / det; Ji[1] = -J[1] / det; Ji[2] = -J[2] / det; Ji[3] = J[0] / det;
+        } else {
+          const double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
+          const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+          Ji[0] = c00 / det; Ji[3] = c01 / det; Ji[6] = c02 / det;
+          Ji[1] = (J[2] * J[7] - J[1] * J[8]) / det; Ji[4] = (J[0] * J[8] - J[2] * J[6]) / det;
+          Ji[7] = (J[1] * J[6] - J[0] * J[7]) / det; Ji[2] = (J[1] * J[5] - J[2] * J[4]) / det;
+          Ji[5] = (J[2] * J[3] - J[0] * J[5]) / det; Ji[8] = (J[0] * J[4] - J[1] * J[3]) / det;
+        }
+        bool far = false;
+        for (int a = 0; a < d; ++a) {
+          double s = 0;
+          for (int b = 0; b < d; ++b) s += Ji[a * d + b] * r[b];
+          z[a] -= s;
+          far = far || std::fabs(z[a] - 0.5) > 2.0;
+        }
+        if (far) break;
+      }
+      bool inside = ok;
+      for (int a = 0; a < d; ++a) inside = inside && z[a] >= -1e-10 && z[a] <= 1 + 1e-10;
+      if (inside) {
+        found = c;
+        for (int a = 0; a < d; ++a) xi[a] = std::min(1.0, std::max(0.0, z[a]));
+      }
+    }
+    if (found < 0) return fail(DGW_EINVAL, "source " + std::to_string(i) + " is outside the mesh");
+    S->cell[i] = (int)found;
+    double x[3], J[9];
+    map_point(hs, found, xi, x, J);
+    double rho, c;
+    hs.material(x, 1, d, &rho, &c, hs.material_ctx);
+    // mu_p of the source cell (from the device copy of the metric)
+    DGW_HIP(hipSetDevice(m->device));
+    DGW_HIP(hipMemcpy(mu.data(), m->d_cell + ((size_t)found * (d * d + 2) + d * d + 1) * np, np * sizeof(double),
+                      hipMemcpyDeviceToHost));
+    // g in the collocated basis: mu_p * l^G(xi_s) / (rho c^2); then S^-1 to GL
+    std::vector<double> lg((size_t)d * n);
+    for (int a = 0; a < d; ++a)
+      for (int j = 0; j < n; ++j) lg[a * n + j] = (double)lagrange_value(g.x, j, (long double)xi[a]);
+    std::vector<double> gG(np), tmp(np);
+    for (int qq = 0; qq < np; ++qq) {
+      int t = qq;
+      double v = 1.0;
+      for (int a = 0; a < d; ++a) {
+        v *= lg[a * n + t % n];
+        t /= n;
+      }
+      gG[qq] = mu[qq] * v / (rho * c * c);
+    }
+    // apply a 1D matrix along every direction (host, small)
+    auto apply = [&](const std::vector<double>& in, int mi, const double* M, int mo) {
+      std::vector<double> cur = in;
+      int ext[3] = {mi, mi, d == 3 ? mi : 1};
+      for (int e = 0; e < d; ++e) {
+        int eo[3] = {ext[0], ext[1], ext[2]};
+        eo[e] = mo;
+        std::vector<double> nxt((size_t)eo[0] * eo[1] * eo[2]);
+        for (int k2 = 0; k2 < eo[2]; ++k2)
+          for (int k1 = 0; k1 < eo[1]; ++k1)
+            for (int k0 = 0; k0 < eo[0]; ++k0) {
+              int kk[3] = {k0, k1, k2};
+              const int row = kk[e];
+              double acc = 0;
+              for (int j = 0; j < ext[e]; ++j) {
+                kk[e] = j;
+                acc += M[row * ext[e] + j] * cur[kk[0] + ext[0] * (kk[1] + ext[1] * kk[2])];
+              }
+              nxt[k0 + eo[0] * (k1 + eo[1] * k2)] = acc;
+            }
+        cur.swap(nxt);
+        ext[0] = eo[0];
+        ext[1] = eo[1];
+        ext[2] = eo[2];
+      }
+      return cur;
+    };
+    const std::vector<double> gl = apply(gG, n, tab.data() + tab_Sinv(n), n);
+    std::copy(gl.begin(), gl.end(), gvec.begin() + (size_t)i * np);
+    std::copy(gG.begin(), gG.end(), glev[0].begin() + (size_t)i * np);
+    for (int l = 1; l < m->nlev; ++l) {
+      const int ml = m->level_pts[l];
+      const std::vector<double> gl_l = apply(gG, n, tab.data() + tab_level_F(n, l), ml);
+      std::copy(gl_l.begin(), gl_l.end(), glev[l].begin() + (size_t)i * ipw(ml, d));
+    }
+    const double f = desc->frequency[i];
+    wave[i * 3 + 0] = f;
+    wave[i * 3 + 1] = desc->t0 ? desc->t0[i] : 1.2 / f;
+    wave[i * 3 + 2] = desc->amplitude ? desc->amplitude[i] : 1.0;
+  }
+  DGW_HIP(hipMalloc(&S->d_cell, S->n * sizeof(int)));
+  DGW_HIP(hipMemcpy(S->d_cell, S->cell.data(), S->n * sizeof(int), hipMemcpyHostToDevice));
+  DGW_HIP(hipMalloc(&S->d_gvec, gvec.size() * sizeof(double)));
+  DGW_HIP(hipMemcpy(S->d_gvec, gvec.data(), gvec.size() * sizeof(double), hipMemcpyHostToDevice));
+  for (int l = 0; l < m->nlev; ++l) {
+    DGW_HIP(hipMalloc(&S->d_glev[l], glev[l].size() * sizeof(double)));
+    DGW_HIP(hipMemcpy(S->d_glev[l], glev[l].data(), glev[l].size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  DGW_HIP(hipMalloc(&S->d_wave, wave.size() * sizeof(double)));
+  DGW_HIP(hipMemcpy(S->d_wave, wave.data(), wave.size() * sizeof(double), hipMemcpyHostToDevice));
+  *out = S.release();
+  return DGW_OK;
+}
+
+void dgw_sources_destroy(dgw_sources* s) {
+  if (!s) return;
+  (void)hipFree(s->d_cell);
+  (void)hipFree(s->d_gvec);
+  for (auto* p : s->d_glev) (void)hipFree(p);
+  (void)hipFree(s->d_wave);
+  delete s;
+}
+
+// ---------------------------------------------------------------- solve
+dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, double* work, int B,
+                           dgw_solve_report* report) {
+  if (!desc) return fail(DGW_EINVAL, "desc is NULL");
+  dgw_status st = check_mesh(m);
+  if (st) return st;
+  if (desc->scheme != DGW_SCHEME_LSRK54 && desc->scheme != DGW_SCHEME_ADER) return fail(DGW_EINVAL, "bad scheme");
+  const double span = desc->t_end - desc->t0;
+  if (!(span > 0) || !std::isfinite(span)) return fail(DGW_EINVAL, "t_end must exceed t0");
+  double dt = desc->dt > 0 ? desc->dt : desc->courant * m->hs.dt_unit;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(DGW_EINVAL, "dt or courant must be positive");
+  const int64_t nsteps = (int64_t)std::ceil(span / dt - 1e-12);
+  dt = span / (double)nsteps;
+  if ((st = check_step(m, dt, 0, u, work, B, desc->sources))) return st;
+  std::lock_guard<std::mutex> lk(m->mtx);
+  if ((st = set_device(m))) return st;
+  hipStream_t s = (hipStream_t)desc->stream;
+  if (desc->autotune && !m->tuned)
+    if ((st = autotune(m, B, s))) return st;
+  const int64_t ne = state_elems(m) * B;
+  double* cur = u;
+  double* oth = work + ne;
+  double* aux = work;  // du (LSRK) or I (ADER)
+  const dgw_sources* src = desc->sources;
+  double e0 = 0, e1 = 0;
+  std::vector<double> en(B);
+  if (desc->watchdog_every > 0 || report) {
+    if ((st = energy_impl(m, cur, B, en.data(), s))) return st;
+    e0 = en[0];
+  }
+  const double growth = desc->watchdog_growth > 0 ? desc->watchdog_growth : 10.0;
+  auto one = [&](int64_t k, const long long* ctr, int add) -> dgw_status {
+    return desc->scheme == DGW_SCHEME_LSRK54
+               ? lsrk_step(m, B, src, desc->t0, dt, (int)(ctr ? add : k), ctr, cur, oth, aux, s)
+               : ader_step(m, desc->ader_flags, B, src, desc->t0, dt, (int)(ctr ? add : k), ctr, cur, oth, aux, s);
+  };
+  DGW_HIP(hipStreamSynchronize(s));
+  const auto tstart = std::chrono::steady_clock::now();
+  int64_t k = 0;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  long long* d_ctr = nullptr;
+  if (desc->use_graph && nsteps >= 2) {
+    // two steps per graph keep the ping-pong buffers in place between replays
+    DGW_HIP(hipMalloc(&d_ctr, sizeof(long long)));
+    const long long zero = 0;
+    DGW_HIP(hipMemcpyAsync(d_ctr, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
+    DGW_HIP(hipStreamSynchronize(s));
+    double* c0 = cur;
+    double* o0 = oth;
+    DGW_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    dgw_status cst = one(0, d_ctr, 0);
+    if (!cst) cst = one(1, d_ctr, 1);
+    hipLaunchKernelGGL(advance_counter, dim3(1), dim3(64), 0, s, d_ctr, 2);
+    const hipError_t ce = hipStreamEndCapture(s, &graph);
+    if (cst || ce != hipSuccess) {
+      (void)hipFree(d_ctr);
+      if (graph) (void)hipGraphDestroy(graph);
+      return cst ? cst : fail(DGW_EDEVICE, "graph capture failed");
+    }
+    DGW_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    cur = c0;  // the capture swapped the pointers twice: back where they were
+    oth = o0;
+    const int64_t pairs = nsteps / 2;
+    for (int64_t r = 0; r < pairs; ++r) {
+      DGW_HIP(hipGraphLaunch(gexec, s));
+      k += 2;
+      if (desc->watchdog_every > 0 && (k % desc->watchdog_every) < 2) {
+        if ((st = energy_impl(m, cur, B, en.data(), s))) break;
+        if (!(en[0] <= growth * e0)) {
+          st = fail(DGW_EUNSTABLE, "energy grew beyond the watchdog limit (time step too large?)");
+          break;
+        }
+      }
+    }
+    (void)hipGraphExecDestroy(gexec);
+    (void)hipGraphDestroy(graph);
+    (void)hipFree(d_ctr);
+    if (st) return st;
+  }
+  for (; k < nsteps; ++k) {
+    if ((st = one(k, nullptr, 0))) return st;
+    if (desc->watchdog_every > 0 && (k + 1) % desc->watchdog_every == 0) {
+      if ((st = energy_impl(m, cur, B, en.data(), s))) return st;
+      if (!(en[0] <= growth * e0)) return fail(DGW_EUNSTABLE, "energy grew beyond the watchdog limit (time step too large?)");
+    }
+  }
+  if (cur != u) DGW_HIP(hipMemcpyAsync(u, cur, ne * 8, hipMemcpyDeviceToDevice, s));
+  DGW_HIP(hipStreamSynchronize(s));
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - tstart).count();
+  if (report) {
+    if ((st = energy_impl(m, u, B, en.data(), s))) return st;
+    e1 = en[0];
+    report->steps = nsteps;
+    report->dt = dt;
+    report->wall_s = wall;
+    report->dof_steps_per_s = (double)ne * (double)nsteps / std::max(wall, 1e-12);
+    report->energy0 = e0;
+    report->energy_end = e1;
+  }
+  return DGW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Kernel parameter blocks and the launcher table shared by the host code and
+// the per-(dim, precision) kernel instantiation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "dgw_params_time.hpp"
+
+namespace dgw {
+
+constexpr int kMaxLevels = 5;  // Gauss sets of the degree reduction: k+1, k-1, ... (k <= 8)
+
+// Epilogues of the fused operator sweep.
+enum Epilogue { EPI_STORE = 0, EPI_LSRK = 1, EPI_ADD = 2 };
+
+struct SourceParams {
+  const int* cell;        // [B] source cell of each member, or nullptr (no sources)
+  const double* gvec;     // [B][np] GL coefficients of g (pressure component)
+  const double* glev[kMaxLevels];  // [B][m_l^d] g at the level-l Gauss points (ADER)
+  const double* wave;     // [B][3]: f, t0, amp of the Ricker wavelet
+};
+
+struct OpParams {
+  const double* u;        // input state, GL, [B][nc][d+1][np]
+  double* out;            // EPI_STORE: L u
+  double* du;             // EPI_LSRK: stage register (in/out)
+  const double* u_base;   // EPI_ADD: u_n (the result is u_base + L u)
+  double* u_next;         // EPI_LSRK / EPI_ADD: new state
+  const double* geo_cell; // [nc][d*d+2][np]: w detJ J^-1 (b*d+a), mu_v, mu_p
+  const double* geo_face; // [nc][2d][d+2][n^(d-1)]: a (d), Z-, Z+
+  const int* nb;          // [nc][2d]
+  const void* tab;        // 1D tables in the arithmetic precision
+  int64_t nc;
+  int cpw;                // cells per workgroup
+  int groups;             // ceil(nc / cpw)
+  int B;
+  int central;            // 1: central flux, 0: upwind
+  double acoef, bcoef, dt;  // LSRK: du <- acoef du + dt (L u + s g); u_next <- u + bcoef du
+  StepTime time;          // LSRK: source at tn + t_off; ADER update: int_{tn}^{tn+dt} s * g
+  SourceParams src;
+};
+
+struct TckParams {
+  const double* u;        // [B][nc][d+1][np] GL
+  double* I;              // [B][nc][d+1][np] GL, time-integrated Taylor sum
+  const double* geo_lev[kMaxLevels];  // level 0 = geo_cell; [nc][d*d+2][m_l^d]
+  const void* tab;
+  const double* tab64;    // FP64 tables (the accumulator's back-transform)
+  int64_t nc;
+  int cpw, groups, B;
+  double dt;
+  StepTime time;          // tn = time at the start of the step (source derivatives)
+  SourceParams src;
+};
+
+struct EnergyParams {
+  const double* u;
+  const double* geo_cell;
+  const void* tab;
+  double* partial;        // [B][groups]
+  int64_t nc;
+  int cpw, groups, B;
+};
+
+using OpLaunch = hipError_t (*)(const OpParams&, int nthreads, hipStream_t);
+using TckLaunch = hipError_t (*)(const TckParams&, int nthreads, hipStream_t);
+using EnergyLaunch = hipError_t (*)(const EnergyParams&, int nthreads, hipStream_t);
+
+struct Launchers {
+  OpLaunch op[3];         // by Epilogue
+  TckLaunch tck[2];       // [0] degree reduction, [1] no reduction
+  EnergyLaunch energy;
+  int op_lds_per_cell;    // bytes of LDS per cell
+  int tck_lds_per_cell;
+  int energy_lds_per_cell;
+};
+
+// precision: 0 = FP64, 1 = FP32 split.  nullptr if (dim, n) is unsupported.
+const Launchers* launchers(int dim, int n, int precision);
+
+// Table layout (element offsets) of the 1D matrices for n = k+1 nodes.
+// S (n x n), S^-1 (n x n), D (n x n), LF0 (n), LF1 (n); then per reduced
+// level l = 1.. with m = n - 2l points and mp = n - 2(l-1):
+// D_l (m x m), P_l (m x mp), E_l (n x m), F_l (m x n).
+__host__ __device__ constexpr int tab_S(int) { return 0; }
+__host__ __device__ constexpr int tab_Sinv(int n) { return n * n; }
+__host__ __device__ constexpr int tab_D(int n) { return 2 * n * n; }
+__host__ __device__ constexpr int tab_LF0(int n) { return 3 * n * n; }
+__host__ __device__ constexpr int tab_LF1(int n) { return 3 * n * n + n; }
+__host__ __device__ constexpr int tab_level(int n, int l) {
+  int off = 3 * n * n + 2 * n;
+  for (int j = 1; j < l; ++j) {
+    const int m = n - 2 * j, mp = n - 2 * (j - 1);
+    off += m * m + m * mp + n * m + m * n;
+  }
+  return off;
+}
+__host__ __device__ constexpr int tab_level_D(int n, int l) { return tab_level(n, l); }
+__host__ __device__ constexpr int tab_level_P(int n, int l) {
+  return tab_level(n, l) + (n - 2 * l) * (n - 2 * l);
+}
+__host__ __device__ constexpr int tab_level_E(int n, int l) {
+  return tab_level_P(n, l) + (n - 2 * l) * (n - 2 * (l - 1));
+}
+__host__ __device__ constexpr int tab_level_F(int n, int l) {
+  return tab_level_E(n, l) + n * (n - 2 * l);
+}
+__host__ __device__ constexpr int num_levels(int n) { return (n + 1) / 2; }  // n, n-2, ... >= 1
+__host__ __device__ constexpr int tab_size(int n) { return tab_level(n, num_levels(n)); }
+
+}  // namespace dgw

@@ -1,0 +1,506 @@
+// Host setup in FP64 (long double for the 1D rules): quadrature rules, the 1D
+// matrices of the basis change / collocation derivative / degree reduction,
+// and the per-point geometry and material data of the curved mesh.
+//
+// Paper references: Gauss quadrature on k+1 points and the G / GL Lagrange
+// bases (Sec. 3, Sec. 3.1); the collocated derivative and the basis change
+// (Sec. 3.2, Alg. 2); the projection to a degree two lower and the reduced
+// Gauss sets with their pre-computed inverse Jacobians (Sec. 3.3, Alg. 3).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "dgw_host.hpp"
+
+namespace dgw {
+
+using ld = long double;
+
+// ---------------------------------------------------------------- 1D rules
+static void legendre(int n, ld x, ld& p, ld& dp) {
+  // P_n and P_n' by the three-term recurrence
+  ld p0 = 1, p1 = x;
+  if (n == 0) {
+    p = 1;
+    dp = 0;
+    return;
+  }
+  for (int j = 2; j <= n; ++j) {
+    const ld p2 = ((2 * j - 1) * x * p1 - (j - 1) * p0) / j;
+    p0 = p1;
+    p1 = p2;
+  }
+  p = p1;
+  dp = (std::fabs(x) < 1) ? n * (x * p1 - p0) / (x * x - 1) : (x > 0 ? 1 : ((n % 2) ? 1 : -1)) * n * (n + 1) / 2.0L;
+}
+
+Rule gauss_rule(int n) {
+  Rule r;
+  r.x.resize(n);
+  r.w.resize(n);
+  const ld pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < n; ++i) {
+    ld x = -std::cos(pi * (i + 0.75L) / (n + 0.5L));
+    for (int it = 0; it < 100; ++it) {
+      ld p, dp;
+      legendre(n, x, p, dp);
+      const ld dx = p / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-19L) break;
+    }
+    ld p, dp;
+    legendre(n, x, p, dp);
+    r.x[i] = 0.5L * (x + 1);
+    r.w[i] = 1.0L / ((1 - x * x) * dp * dp);  // 2/((1-x^2) P'^2), halved for [0,1]
+  }
+  return r;
+}
+
+Rule gauss_lobatto_rule(int n) {
+  Rule r;
+  r.x.resize(n);
+  r.w.resize(n);
+  const ld pi = 3.141592653589793238462643383279502884L;
+  const int m = n - 1;  // interior nodes are the roots of P_m'
+  for (int i = 0; i < n; ++i) {
+    ld x;
+    if (i == 0)
+      x = -1;
+    else if (i == n - 1)
+      x = 1;
+    else {
+      x = -std::cos(pi * i / m);
+      for (int it = 0; it < 100; ++it) {
+        ld p, dp;
+        legendre(m, x, p, dp);
+        const ld d2p = (2 * x * dp - m * (m + 1) * p) / (1 - x * x);
+        const ld dx = dp / d2p;
+        x -= dx;
+        if (std::fabs(dx) < 1e-19L) break;
+      }
+    }
+    ld p, dp;
+    legendre(m, x, p, dp);
+    r.x[i] = 0.5L * (x + 1);
+    r.w[i] = 1.0L / (n * m * p * p);  // 2/(n(n-1) P_{n-1}^2), halved
+  }
+  return r;
+}
+
+long double lagrange_value(const std::vector<ld>& nodes, int j, ld x) {
+  ld v = 1;
+  for (size_t m = 0; m < nodes.size(); ++m)
+    if ((int)m != j) v *= (x - nodes[m]) / (nodes[j] - nodes[m]);
+  return v;
+}
+
+long double lagrange_deriv(const std::vector<ld>& nodes, int j, ld x) {
+  ld s = 0;
+  const int n = (int)nodes.size();
+  for (int m = 0; m < n; ++m) {
+    if (m == j) continue;
+    ld t = 1 / (nodes[j] - nodes[m]);
+    for (int l = 0; l < n; ++l)
+      if (l != j && l != m) t *= (x - nodes[l]) / (nodes[j] - nodes[l]);
+    s += t;
+  }
+  return s;
+}
+
+std::vector<double> build_tables(int n) {
+  std::vector<double> t(tab_size(n), 0.0);
+  const Rule g = gauss_rule(n), gl = gauss_lobatto_rule(n);
+  for (int q = 0; q < n; ++q)
+    for (int j = 0; j < n; ++j) {
+      t[tab_S(n) + q * n + j] = (double)lagrange_value(gl.x, j, g.x[q]);     // GL coeff -> G value
+      t[tab_Sinv(n) + q * n + j] = (double)lagrange_value(g.x, j, gl.x[q]);  // G value -> GL coeff
+      t[tab_D(n) + q * n + j] = (double)lagrange_deriv(g.x, j, g.x[q]);      // l^G_j'(xi_q)
+    }
+  for (int j = 0; j < n; ++j) {
+    t[tab_LF0(n) + j] = (double)lagrange_value(g.x, j, 0.0L);
+    t[tab_LF1(n) + j] = (double)lagrange_value(g.x, j, 1.0L);
+  }
+  for (int l = 1; l < num_levels(n); ++l) {
+    const int m = n - 2 * l, mp = n - 2 * (l - 1);
+    const Rule rm = gauss_rule(m), rp = gauss_rule(mp);
+    for (int q = 0; q < m; ++q)
+      for (int j = 0; j < m; ++j)
+        t[tab_level_D(n, l) + q * m + j] = m > 1 ? (double)lagrange_deriv(rm.x, j, rm.x[q]) : 0.0;
+    // unweighted L2 projection on the reference element, collocated form
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < mp; ++b)
+        t[tab_level_P(n, l) + a * mp + b] = (double)(rp.w[b] * lagrange_value(rm.x, a, rp.x[b]) / rm.w[a]);
+    for (int q = 0; q < n; ++q)
+      for (int a = 0; a < m; ++a) t[tab_level_E(n, l) + q * m + a] = (double)lagrange_value(rm.x, a, g.x[q]);
+    for (int q = 0; q < m; ++q)
+      for (int j = 0; j < n; ++j) t[tab_level_F(n, l) + q * n + j] = (double)lagrange_value(g.x, j, rm.x[q]);
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------- geometry
+namespace {
+
+int ipw(int b, int e) {
+  int r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
+
+// Apply per-direction matrices M[e] (mo[e] x mi) to a tensor of extents mi^d
+// (x fastest); out has extents mo[0] x mo[1] (x mo[2]).
+void tensor_eval(int d, int mi, const double* in, const std::vector<const double*>& M, const int* mo, double* out,
+                 std::vector<double>& t1, std::vector<double>& t2) {
+  int ext[3] = {mi, mi, d == 3 ? mi : 1};
+  const double* src = in;
+  for (int e = 0; e < d; ++e) {
+    int eo[3] = {ext[0], ext[1], ext[2]};
+    eo[e] = mo[e];
+    const int nout = eo[0] * eo[1] * eo[2];
+    std::vector<double>& dst = (e % 2 == 0) ? t1 : t2;
+    double* o = (e == d - 1) ? out : (dst.resize(nout), dst.data());
+    const int si[3] = {1, ext[0], ext[0] * ext[1]};
+    const int so[3] = {1, eo[0], eo[0] * eo[1]};
+    for (int k2 = 0; k2 < eo[2]; ++k2)
+      for (int k1 = 0; k1 < eo[1]; ++k1)
+        for (int k0 = 0; k0 < eo[0]; ++k0) {
+          int kk[3] = {k0, k1, k2};
+          const int io = kk[0] * so[0] + kk[1] * so[1] + kk[2] * so[2];
+          const int row = kk[e];
+          kk[e] = 0;
+          const int ib = kk[0] * si[0] + kk[1] * si[1] + kk[2] * si[2];
+          double acc = 0;
+          for (int j = 0; j < ext[e]; ++j) acc += M[e][row * ext[e] + j] * src[ib + j * si[e]];
+          o[io] = acc;
+        }
+    src = o;
+    ext[0] = eo[0];
+    ext[1] = eo[1];
+    ext[2] = eo[2];
+  }
+}
+
+struct GeoMats {
+  // value and derivative of the equispaced Lagrange polynomials at 1D points
+  std::vector<double> V, W;
+  int m = 0;
+};
+
+GeoMats geo_mats(int q, const std::vector<ld>& pts) {
+  std::vector<ld> nodes(q + 1);
+  for (int j = 0; j <= q; ++j) nodes[j] = (ld)j / q;
+  GeoMats g;
+  g.m = (int)pts.size();
+  g.V.resize(g.m * (q + 1));
+  g.W.resize(g.m * (q + 1));
+  for (int i = 0; i < g.m; ++i)
+    for (int j = 0; j <= q; ++j) {
+      g.V[i * (q + 1) + j] = (double)lagrange_value(nodes, j, pts[i]);
+      g.W[i * (q + 1) + j] = (double)lagrange_deriv(nodes, j, pts[i]);
+    }
+  return g;
+}
+
+// x [P][d] and J [P][d][d] (J[p][a][b] = dx_a/dxi_b) of one cell at the tensor
+// point set given by per-direction matrices.
+void eval_map(int d, int q, const double* X, const std::vector<const GeoMats*>& gm, double* x, double* J,
+              std::vector<double>& comp, std::vector<double>& res, std::vector<double>& t1,
+              std::vector<double>& t2) {
+  const int ng = ipw(q + 1, d);
+  int mo[3] = {gm[0]->m, gm[1]->m, d == 3 ? gm[2]->m : 1};
+  const int P = mo[0] * mo[1] * mo[2];
+  comp.resize(ng);
+  res.resize(P);
+  for (int a = 0; a < d; ++a) {
+    for (int g = 0; g < ng; ++g) comp[g] = X[g * d + a];
+    for (int b = -1; b < d; ++b) {
+      std::vector<const double*> M(d);
+      for (int e = 0; e < d; ++e) M[e] = (e == b) ? gm[e]->W.data() : gm[e]->V.data();
+      tensor_eval(d, q + 1, comp.data(), M, mo, res.data(), t1, t2);
+      for (int p = 0; p < P; ++p) {
+        if (b < 0)
+          x[p * d + a] = res[p];
+        else
+          J[(p * d + a) * d + b] = res[p];
+      }
+    }
+  }
+}
+
+double det_inv(int d, const double* J, double* Ji) {
+  if (d == 2) {
+    const double det = J[0] * J[3] - J[1] * J[2];
+    Ji[0] = J[3] / det;
+    Ji[1] = -J[1] / det;
+    Ji[2] = -J[2] / det;
+    Ji[3] = J[0] / det;
+    return det;
+  }
+  const double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
+  const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+  Ji[0] = c00 / det;
+  Ji[3] = c01 / det;
+  Ji[6] = c02 / det;
+  Ji[1] = (J[2] * J[7] - J[1] * J[8]) / det;
+  Ji[4] = (J[0] * J[8] - J[2] * J[6]) / det;
+  Ji[7] = (J[1] * J[6] - J[0] * J[7]) / det;
+  Ji[2] = (J[1] * J[5] - J[2] * J[4]) / det;
+  Ji[5] = (J[2] * J[3] - J[0] * J[5]) / det;
+  Ji[8] = (J[0] * J[4] - J[1] * J[3]) / det;
+  return det;
+}
+
+// Smallest singular value of J (eigenvalues of J^T J by Jacobi rotations).
+double sigma_min(int d, const double* J) {
+  double A[9] = {0};
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      double s = 0;
+      for (int k = 0; k < d; ++k) s += J[k * d + i] * J[k * d + j];
+      A[i * 3 + j] = s;
+    }
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0;
+    for (int i = 0; i < d; ++i)
+      for (int j = i + 1; j < d; ++j) off += A[i * 3 + j] * A[i * 3 + j];
+    if (off < 1e-40) break;
+    for (int i = 0; i < d; ++i)
+      for (int j = i + 1; j < d; ++j) {
+        if (std::fabs(A[i * 3 + j]) < 1e-300) continue;
+        const double th = 0.5 * std::atan2(2 * A[i * 3 + j], A[j * 3 + j] - A[i * 3 + i]);
+        const double c = std::cos(th), s = std::sin(th);
+        for (int k = 0; k < d; ++k) {  // rotate rows/cols i, j
+          const double aki = A[k * 3 + i], akj = A[k * 3 + j];
+          A[k * 3 + i] = c * aki - s * akj;
+          A[k * 3 + j] = s * aki + c * akj;
+        }
+        for (int k = 0; k < d; ++k) {
+          const double aik = A[i * 3 + k], ajk = A[j * 3 + k];
+          A[i * 3 + k] = c * aik - s * ajk;
+          A[j * 3 + k] = s * aik + c * ajk;
+        }
+      }
+  }
+  double mn = A[0];
+  for (int i = 1; i < d; ++i) mn = std::min(mn, A[i * 3 + i]);
+  return std::sqrt(std::max(mn, 0.0));
+}
+
+template <class F>
+void parallel_for(int64_t n, F&& f) {
+  int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+  if (n < 64) nt = 1;
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t]() {
+      for (int64_t i = t; i < n; i += nt) f(i);
+    });
+  for (auto& x : th) x.join();
+}
+
+}  // namespace
+
+void map_point(const HostSetup& hs, int64_t cell, const double* xi, double* x, double* J) {
+  std::vector<GeoMats> gm(hs.dim);
+  std::vector<const GeoMats*> gp(hs.dim);
+  for (int e = 0; e < hs.dim; ++e) {
+    gm[e] = geo_mats(hs.q, {(ld)xi[e]});
+    gp[e] = &gm[e];
+  }
+  std::vector<double> comp, res, t1, t2;
+  const int ng = ipw(hs.q + 1, hs.dim);
+  eval_map(hs.dim, hs.q, hs.geo_nodes.data() + cell * ng * hs.dim, gp, x, J, comp, res, t1, t2);
+}
+
+void node_coords(const HostSetup& hs, std::vector<double>& out) {
+  const int d = hs.dim, n = hs.n, np = ipw(n, d), ng = ipw(hs.q + 1, d);
+  const Rule gl = gauss_lobatto_rule(n);
+  const GeoMats gm = geo_mats(hs.q, gl.x);
+  std::vector<const GeoMats*> gp(d, &gm);
+  out.resize((size_t)hs.nc * np * d);
+  parallel_for(hs.nc, [&](int64_t c) {
+    std::vector<double> comp, res, t1, t2, J((size_t)np * d * d);
+    eval_map(d, hs.q, hs.geo_nodes.data() + c * ng * d, gp, out.data() + c * np * d, J.data(), comp, res, t1, t2);
+  });
+}
+
+dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs) {
+  const int d = desc.dim, k = desc.degree, n = k + 1;
+  const int q = desc.geo_degree > 0 ? desc.geo_degree : k;
+  if (q < 1 || q > 8) return fail(DGW_EUNSUPPORTED, "geo_degree must be in 1..8");
+  hs.dim = d;
+  hs.k = k;
+  hs.n = n;
+  hs.q = q;
+  hs.nc = desc.n_cells;
+  hs.material = desc.material;
+  hs.material_ctx = desc.material_ctx;
+  const int64_t nc = desc.n_cells;
+  const int np = ipw(n, d), nf = ipw(n, d - 1), ng = ipw(q + 1, d), nface = 2 * d;
+  const int ncomp_geo = d * d + 2;
+  // neighbours: conforming, periodic/interior only
+  hs.nb.resize(nc * nface);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int f = 0; f < nface; ++f) {
+      const int64_t o = desc.neighbors[c * nface + f];
+      if (o < 0) return fail(DGW_EUNSUPPORTED, "boundary faces (neighbor -1) are not supported");
+      if (o >= nc) return fail(DGW_EINVAL, "neighbor index out of range");
+      hs.nb[c * nface + f] = (int32_t)o;
+    }
+  for (int64_t c = 0; c < nc; ++c)
+    for (int f = 0; f < nface; ++f)
+      if (desc.neighbors[desc.neighbors[c * nface + f] * nface + (f ^ 1)] != c)
+        return fail(DGW_EINVAL, "neighbor table is not conforming (nb[nb[c][f]][f^1] != c)");
+  hs.geo_nodes.assign(desc.geo_nodes, desc.geo_nodes + nc * ng * d);
+
+  const Rule g = gauss_rule(n);
+  // 1D map matrices at the point sets
+  const GeoMats gm_cell = geo_mats(q, g.x);
+  const GeoMats gm_lo = geo_mats(q, {0.0L}), gm_hi = geo_mats(q, {1.0L});
+  const int nlev = num_levels(n);
+  std::vector<Rule> lrule(nlev);
+  std::vector<GeoMats> gm_lev(nlev);
+  for (int l = 1; l < nlev; ++l) {
+    lrule[l] = gauss_rule(n - 2 * l);
+    gm_lev[l] = geo_mats(q, lrule[l].x);
+  }
+  hs.cell.assign((size_t)nc * ncomp_geo * np, 0.0);
+  hs.face.assign((size_t)nc * nface * (d + 2) * nf, 0.0);
+  hs.level.assign(nlev, {});
+  for (int l = 1; l < nlev; ++l) hs.level[l].assign((size_t)nc * ncomp_geo * ipw(n - 2 * l, d), 0.0);
+  hs.hK.assign(nc, 0.0);
+  hs.cK.assign(nc, 0.0);
+  std::vector<double> Zown((size_t)nc * nface * nf);
+  // weights of the tensor rules
+  auto tensor_w = [&](const Rule& r, int dims, std::vector<double>& w) {
+    const int m = (int)r.x.size();
+    const int P = ipw(m, dims);
+    w.assign(P, 1.0);
+    for (int p = 0; p < P; ++p) {
+      int t = p;
+      long double acc = 1;
+      for (int e = 0; e < dims; ++e) {
+        acc *= r.w[t % m];
+        t /= m;
+      }
+      w[p] = (double)acc;
+    }
+  };
+  std::vector<double> wcell, wface;
+  tensor_w(g, d, wcell);
+  tensor_w(g, d - 1, wface);
+  std::vector<std::vector<double>> wlev(nlev);
+  for (int l = 1; l < nlev; ++l) tensor_w(lrule[l], d, wlev[l]);
+
+  // point sets: 0 = cell, 1..2d = faces, 2d+l = level l
+  const int nsets = 1 + nface + (nlev - 1);
+  std::vector<int> set_pts(nsets);
+  std::vector<std::vector<const GeoMats*>> set_mats(nsets, std::vector<const GeoMats*>(d));
+  for (int e = 0; e < d; ++e) set_mats[0][e] = &gm_cell;
+  set_pts[0] = np;
+  for (int f = 0; f < nface; ++f) {
+    for (int e = 0; e < d; ++e) set_mats[1 + f][e] = (e == f / 2) ? ((f & 1) ? &gm_hi : &gm_lo) : &gm_cell;
+    set_pts[1 + f] = nf;
+  }
+  for (int l = 1; l < nlev; ++l) {
+    for (int e = 0; e < d; ++e) set_mats[nface + l][e] = &gm_lev[l];
+    set_pts[nface + l] = ipw(n - 2 * l, d);
+  }
+  int pts_per_cell = 0;
+  std::vector<int> set_off(nsets);
+  for (int s = 0; s < nsets; ++s) {
+    set_off[s] = pts_per_cell;
+    pts_per_cell += set_pts[s];
+  }
+
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nc, (64ll << 20) / (8ll * pts_per_cell * (d + d * d))));
+  std::vector<double> X, Jb, rho, cc;
+  std::string err;
+  std::mutex err_mtx;
+  for (int64_t c0 = 0; c0 < nc; c0 += chunk) {
+    const int64_t cn = std::min(chunk, nc - c0);
+    X.resize((size_t)cn * pts_per_cell * d);
+    Jb.resize((size_t)cn * pts_per_cell * d * d);
+    parallel_for(cn, [&](int64_t i) {
+      std::vector<double> comp, res, t1, t2;
+      const double* Xn = hs.geo_nodes.data() + (c0 + i) * ng * d;
+      for (int s = 0; s < nsets; ++s)
+        eval_map(d, q, Xn, set_mats[s], X.data() + ((size_t)i * pts_per_cell + set_off[s]) * d,
+                 Jb.data() + ((size_t)i * pts_per_cell + set_off[s]) * d * d, comp, res, t1, t2);
+    });
+    rho.resize((size_t)cn * pts_per_cell);
+    cc.resize((size_t)cn * pts_per_cell);
+    desc.material(X.data(), cn * pts_per_cell, d, rho.data(), cc.data(), desc.material_ctx);
+    parallel_for(cn, [&](int64_t i) {
+      const int64_t cell = c0 + i;
+      double Ji[9];
+      double hmin = 1e300, cmax = 0;
+      for (int s = 0; s < nsets; ++s) {
+        for (int p = 0; p < set_pts[s]; ++p) {
+          const size_t pp = (size_t)i * pts_per_cell + set_off[s] + p;
+          const double* J = Jb.data() + pp * d * d;
+          const double det = det_inv(d, J, Ji);
+          const double r = rho[pp], c = cc[pp];
+          if (!(det > 0) || !(r > 0) || !(c > 0)) {
+            std::lock_guard<std::mutex> lk(err_mtx);
+            if (err.empty())
+              err = !(det > 0) ? "non-positive Jacobian determinant in cell " + std::to_string(cell)
+                               : "non-positive rho or c in cell " + std::to_string(cell);
+            return;
+          }
+          if (s == 0) {
+            const double wd = wcell[p] * det;
+            double* G = hs.cell.data() + (size_t)cell * ncomp_geo * np;
+            for (int b = 0; b < d; ++b)
+              for (int a = 0; a < d; ++a) G[(b * d + a) * np + p] = wd * Ji[b * d + a];
+            G[(d * d) * np + p] = 1.0 / (wd * r);
+            G[(d * d + 1) * np + p] = r * c * c / wd;
+            hmin = std::min(hmin, sigma_min(d, J));
+            cmax = std::max(cmax, c);
+          } else if (s <= nface) {
+            const int f = s - 1, dir = f / 2;
+            const double sgn = (f & 1) ? 1.0 : -1.0;
+            const double wd = wface[p] * det * sgn;
+            double* F = hs.face.data() + ((size_t)cell * nface + f) * (d + 2) * nf;
+            for (int a = 0; a < d; ++a) F[a * nf + p] = wd * Ji[dir * d + a];
+            F[d * nf + p] = r * c;
+            Zown[((size_t)cell * nface + f) * nf + p] = r * c;
+          } else {
+            const int l = s - nface;
+            const int m = set_pts[s];
+            const double wd = wlev[l][p] * det;
+            double* G = hs.level[l].data() + (size_t)cell * ncomp_geo * m;
+            for (int b = 0; b < d; ++b)
+              for (int a = 0; a < d; ++a) G[(b * d + a) * m + p] = wd * Ji[b * d + a];
+            G[(d * d) * m + p] = 1.0 / (wd * r);
+            G[(d * d + 1) * m + p] = r * c * c / wd;
+          }
+        }
+      }
+      hs.hK[cell] = hmin;
+      hs.cK[cell] = cmax;
+    });
+    if (!err.empty()) return fail(DGW_EINVAL, err);
+  }
+  // impedance of the neighbour at the shared face point (its own sample)
+  for (int64_t c = 0; c < nc; ++c)
+    for (int f = 0; f < nface; ++f) {
+      const int64_t o = hs.nb[c * nface + f];
+      double* F = hs.face.data() + ((size_t)c * nface + f) * (d + 2) * nf;
+      const double* Zo = Zown.data() + ((size_t)o * nface + (f ^ 1)) * nf;
+      for (int p = 0; p < nf; ++p) F[(d + 1) * nf + p] = Zo[p];
+    }
+  double dtu = 1e300, hmin = 1e300, cmax = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    dtu = std::min(dtu, hs.hK[c] / hs.cK[c]);
+    hmin = std::min(hmin, hs.hK[c]);
+    cmax = std::max(cmax, hs.cK[c]);
+  }
+  hs.dt_unit = dtu / std::pow((double)k, 1.5);
+  hs.h_min = hmin;
+  hs.c_max = cmax;
+  return DGW_OK;
+}
+
+}  // namespace dgw

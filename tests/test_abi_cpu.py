@@ -1,0 +1,132 @@
+"""CPU tests of the C ABI: the library loads and exports every function that
+include/dgw.h declares; the host-side setup (built with DGW_DEVICE_NONE, no
+GPU needed) agrees with the oracle's independent geometry; argument
+validation returns the documented status codes.  No compute kernel runs."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Mesh as OMesh
+from oracle import basis, timestep as ts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1805_03981_amd import binding
+    return binding
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "dgw.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(dgw_[a-z0-9_]+)\s*\(", text))
+    names.discard("dgw_material_fn")
+    return sorted(n for n in names if not n.startswith("DGW_"))
+
+
+def test_exports_every_declared_symbol(B):
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(B.lib, n), n
+    assert set(names) == set(B.EXPORTED)
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 9])
+def test_basis_tables_match_oracle(B, n):
+    xg, wg = basis.gauss(n)
+    xgl, wgl = basis.gauss_lobatto(n)
+    assert np.allclose(B.basis_1d(n, 0), xg, atol=1e-15) and np.allclose(B.basis_1d(n, 1), wg, atol=1e-15)
+    assert np.allclose(B.basis_1d(n, 2), xgl, atol=1e-15) and np.allclose(B.basis_1d(n, 3), wgl, atol=1e-15)
+    assert np.allclose(B.basis_1d(n, 4), basis.lagrange(xgl, xg), atol=1e-14)
+    assert np.allclose(B.basis_1d(n, 5), basis.lagrange(xg, xgl), atol=1e-13)
+    assert np.allclose(B.basis_1d(n, 6), basis.lagrange_deriv(xg, xg), atol=1e-12 * n * n)
+
+
+@pytest.mark.parametrize("dim,nc,k,amp", [(2, 3, 3, 0.05), (3, 2, 4, 0.05), (3, 2, 2, 0.0)])
+def test_host_setup_matches_oracle_geometry(B, dim, nc, k, amp):
+    mat = W.FourierMaterial(3, dim=dim)
+    nodes, nb = W.box_nodes(dim, nc, k, amp), W.box_neighbors(dim, nc)
+    gm = B.Mesh(dim, k, nodes, nb, mat, device=B.DEVICE_NONE)
+    om = OMesh(dim, k, nodes, nb, mat)
+    cd = om.cell_data(np.arange(om.nc))
+    G = gm.get(B.GET_CELL_METRIC)
+    want = np.moveaxis((cd["wdet"][:, :, None, None] * cd["Jinv"]).reshape(om.nc, om.np_, dim * dim), 1, 2)
+    assert np.abs(G[:, :dim * dim] - want).max() < 1e-13 * np.abs(want).max()
+    muv = 1 / (cd["wdet"] * cd["rho"])
+    mup = cd["rho"] * cd["c"] ** 2 / cd["wdet"]
+    assert np.abs(G[:, dim * dim] - muv).max() < 1e-13 * muv.max()
+    assert np.abs(G[:, dim * dim + 1] - mup).max() < 1e-13 * mup.max()
+    F = gm.get(B.GET_FACE)
+    for f in range(2 * dim):
+        fd = om.face_data(np.arange(om.nc), f)
+        assert np.abs(F[:, f, :dim] - np.moveaxis(fd["a"], 2, 1)).max() < 1e-14
+        assert np.abs(F[:, f, dim] - fd["Zm"]).max() < 1e-14
+        assert np.abs(F[:, f, dim + 1] - fd["Zp"]).max() < 1e-14
+    h, c = ts.cell_h_and_c(om)
+    assert abs(gm.info.dt_unit - (h / c).min() / k ** 1.5) < 1e-14 * gm.info.dt_unit
+    x = gm.get(B.GET_NODE_COORDS)
+    assert np.abs(x - om.node_points()).max() < 1e-14
+
+
+def test_level_metric_matches_oracle(B):
+    from oracle import ader
+    dim, nc, k = 3, 2, 5
+    mat = W.FourierMaterial(4, dim=dim)
+    nodes, nb = W.box_nodes(dim, nc, k, 0.05), W.box_neighbors(dim, nc)
+    gm = B.Mesh(dim, k, nodes, nb, mat, device=B.DEVICE_NONE)
+    om = OMesh(dim, k, nodes, nb, mat)
+    assert list(gm.info.level_points)[:gm.info.n_levels] == [6, 4, 2]
+    for l, m in ((1, 4), (2, 2)):
+        Gl = gm.get(B.GET_LEVEL0 + l)
+        ld = ader.level_data(om, np.arange(om.nc), m)
+        # stored: w detJ J^-1 and 1/(w detJ rho), rho c^2/(w detJ): their products are J^-1/rho, rho c^2 J^-1
+        jr = Gl[:, :dim * dim] * Gl[:, dim * dim:dim * dim + 1]
+        want = np.moveaxis(ld["Jinv"].reshape(om.nc, m ** dim, dim * dim), 1, 2) / ld["rho"][:, None, :]
+        assert np.abs(jr - want).max() < 1e-13 * np.abs(want).max()
+
+
+def test_footprint_and_validation(B):
+    import ctypes as C
+    r = B.Request(dim=3, ncell=8, degree=3, scheme=0, precision=0, t_end=0.1, courant=0.2, deform_amp=0.05)
+    fp = B.lib.dgw_request_footprint(C.byref(r))
+    state = 512 * 4 * 64 * 8
+    assert fp > 3 * state
+    r.degree = 9
+    assert B.lib.dgw_request_footprint(C.byref(r)) == -1
+    mat = W.ConstantMaterial()
+    with pytest.raises(B.DgwError) as e:
+        B.Mesh(3, 9, W.box_nodes(3, 2, 2, 0.0), W.box_neighbors(3, 2), mat, device=B.DEVICE_NONE)
+    assert e.value.status == B.EUNSUPPORTED
+    nb = W.box_neighbors(2, 3)
+    nb[0, 1] = 5
+    with pytest.raises(B.DgwError) as e:
+        B.Mesh(2, 2, W.box_nodes(2, 3, 2, 0.0), nb, mat, device=B.DEVICE_NONE)
+    assert e.value.status == B.EINVAL
+    nb = W.box_neighbors(2, 3)
+    nb[4, 2] = -1
+    with pytest.raises(B.DgwError) as e:
+        B.Mesh(2, 2, W.box_nodes(2, 3, 2, 0.0), nb, mat, device=B.DEVICE_NONE)
+    assert e.value.status == B.EUNSUPPORTED
+    # a folded cell (negative Jacobian)
+    nodes = W.box_nodes(2, 3, 2, 0.0)
+    nodes[0] = nodes[0].reshape(3, 3, 2)[:, ::-1].reshape(9, 2)  # mirror x: det J < 0
+    with pytest.raises(B.DgwError) as e:
+        B.Mesh(2, 2, nodes, W.box_neighbors(2, 3), mat, device=B.DEVICE_NONE)
+    assert e.value.status == B.EINVAL
+
+
+def test_c_box_nodes_match_generator(B):
+    """dgw_mesh_create_box and workloads.box_nodes describe the same mesh."""
+    mat = W.FourierMaterial(9, dim=3)
+    gm = B.Mesh.box(3, 3, 2, 0.05, B.fourier_material_struct(mat), device=B.DEVICE_NONE)
+    om = OMesh(3, 2, W.box_nodes(3, 3, 2, 0.05), W.box_neighbors(3, 3), mat)
+    assert np.abs(gm.get(B.GET_NODE_COORDS) - om.node_points()).max() < 1e-14
+    G = gm.get(B.GET_CELL_METRIC)
+    cd = om.cell_data(np.arange(om.nc))
+    assert np.abs(G[:, 10] - cd["rho"] * cd["c"] ** 2 / cd["wdet"]).max() < 1e-12 * G[:, 10].max()

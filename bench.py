@@ -1,0 +1,272 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the DG acoustic solver on one MI355X.
+
+Workload (default, "c2"): periodic unit cube, 24^3 hexahedra curved by
+x += 0.05 sin(2 pi x) sin(2 pi y) sin(2 pi z) (all coordinates), degree k = 5,
+rho = 1, c = 1 + 0.3 * 8 seeded Fourier modes (clamped to [0.7, 1.3]),
+upwind flux, Gaussian pressure pulse (width 0.05) at a seeded point:
+1.19e7 DoF.  A step is one full time step of the hot path: the ADER step
+(Taylor-Cauchy-Kowalevski sweep + fused operator/update sweep) or five fused
+LSRK(5,4) stages.  `value` is the FP64 ADER throughput in DoF-steps/s with
+the state resident in HBM; the other scheme/precision variants are reported
+beside it.  Also reported: per-kernel roofline (HIP events on the launch
+stream), FP32-split error against FP64, and the CPU FP64 oracle timed on a
+bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--variants ader-fp64,...]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1805_03981_amd/csrc/kernels.hpp", "paper_1805_03981_amd/csrc/dgw_params.hpp"]
+# Critical Courant numbers of the paper's Table 2 (3D, k = 4 and k = 7) bracket
+# k = 5; the runs use 0.9 of the smaller value.
+CR = {"lsrk": 0.9 * 0.44, "ader": 0.9 * 0.18}
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(dim, k, kernel):
+    """Minimum HBM bytes per cell of one launch (FP64 state, FP64 metric):
+    every value of the inputs read once and of the outputs written once."""
+    n = k + 1
+    np_, nf, nc = n ** dim, n ** (dim - 1), dim + 1
+    state = nc * np_ * 8
+    cell_geo = (dim * dim + 2) * np_ * 8
+    face_geo = 2 * dim * (dim + 2) * nf * 8 + 2 * dim * 4
+    levels = sum((dim * dim + 2) * m ** dim * 8 for m in range(n - 2, 0, -2))
+    if kernel == "operator_lsrk":     # read u, du; write du, u_next
+        return 4 * state + cell_geo + face_geo
+    if kernel == "operator_ader_update":  # read I, u_n; write u_next
+        return 3 * state + cell_geo + face_geo
+    if kernel == "tck":                  # read u; write I; metric of every Gauss set
+        return 2 * state + cell_geo + levels
+    raise ValueError(kernel)
+
+
+def read_traffic(kernel, workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_sources_sha256_16:\s*(\w+)", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def make_c2(B, precision, ncell=24, k=5, seed=1805):
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1805_03981_amd import binding as dg
+    wl = W.c2_workload(ncell, k, seed)
+    mat = dg.fourier_material_struct(wl["material"])
+    mesh = dg.Mesh(3, k, W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell), mat,
+                   precision=dg.FP32_SPLIT if precision == "fp32" else dg.FP64, max_batch=B)
+    x = mesh.get(dg.GET_NODE_COORDS)
+    u0 = np.ascontiguousarray(np.moveaxis(wl["ic"](x), -1, 1))
+    return mesh, torch.from_numpy(u0).to("cuda")[None].contiguous(), wl
+
+
+def run_variant(scheme, precision, steps, warmup):
+    import torch
+    from paper_1805_03981_amd import binding as dg
+    mesh, u0, wl = make_c2(1, precision)
+    mesh.autotune(1)
+    dt = CR[scheme] * mesh.info.dt_unit
+    u = u0.clone()
+    work = mesh.work(1)
+    step = (lambda n: mesh.step_ader(u, 0.0, dt, n, work=work)) if scheme == "ader" else \
+        (lambda n: mesh.step_lsrk(u, 0.0, dt, n, work=work))
+    step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dofs = mesh.info.dofs
+    prof = mesh.profile(u0.clone(), dg.ADER if scheme == "ader" else dg.LSRK54, 0.0, dt, steps, work=work)
+    res = dict(scheme=scheme, precision=precision, dofs=dofs, dt=dt, steps=steps, wall_s=wall,
+               ms_per_step=1e3 * wall / steps, dof_steps_per_s=dofs * steps / wall,
+               kernels_ms={kname: ms for kname, (ms, _) in prof.items()},
+               launch_shape={"operator": mesh.launch_shape(0), "tck": mesh.launch_shape(1)})
+    # steps to T = 0.5 at this Courant number: time to solution
+    nsteps_T = int(-(-0.5 // dt))
+    res["steps_to_T"] = nsteps_T
+    res["time_to_T_s"] = nsteps_T * wall / steps
+    return res, mesh, u
+
+
+def fp32_error(steps=5):
+    """FP32-split vs FP64 after `steps` ADER steps from the same state."""
+    import torch
+    from oracle import norms
+    out = {}
+    for scheme in ("ader", "lsrk"):
+        m64, u64, _ = make_c2(1, "fp64")
+        m32, u32, _ = make_c2(1, "fp32")
+        dt = CR[scheme] * m64.info.dt_unit
+        for m, u in ((m64, u64), (m32, u32)):
+            (m.step_ader if scheme == "ader" else m.step_lsrk)(u, 0.0, dt, steps)
+        torch.cuda.synchronize()
+        out[scheme] = norms.rel_l2(u32.cpu().numpy(), u64.cpu().numpy())
+    return out
+
+
+def cpu_baseline(target_s=15.0):
+    """The oracle (test infrastructure) timed on a sample of the c2 workload:
+    one ADER step (TCK + operator with its dense per-cell mass solve) on a
+    contiguous block of cells, scaled to DoF-steps/s."""
+    import numpy as np
+    import workloads as W
+    from oracle import Mesh, ader, apply_operator
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    wl = W.c2_workload(24, 5, 1805)
+    m = Mesh(3, 5, W.box_nodes(3, 24, 5, 0.05), W.box_neighbors(3, 24), wl["material"], cache=False)
+    U = np.zeros((m.nc, 4, m.np_))
+    U[:] = 1e-3
+    dt = CR["ader"] * 0.01
+
+    def one(cells):
+        ader.level_data(m, cells, 6)  # geometry of the sample (setup, untimed below)
+        t = time.perf_counter()
+        I = np.zeros_like(U)
+        I[cells] = ader.tck(m, U, dt, cells=cells)
+        apply_operator(m, I, cells=cells)
+        return time.perf_counter() - t
+
+    probe = np.arange(16)
+    tp = one(probe)
+    ncell = int(min(m.nc, max(16, target_s / tp * len(probe))))
+    cells = np.arange(ncell)
+    t = one(cells)
+    dof = ncell * 4 * m.np_
+    return {"value": dof / t, "unit": "DoF-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"one ADER step (TCK + operator, dense per-cell Cholesky mass solve) on {ncell} of "
+                      f"{m.nc} cells of the 24^3 k=5 workload, {t:.1f} s; geometry of the sample cells "
+                      f"recomputed inside the timed region (the oracle caches nothing at this size)"}
+
+
+def copy_calibration(mib):
+    """A plain device copy of known size, for calibrating the HBM counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {mib} MiB three times")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--variants", default="ader-fp64,lsrk-fp64,ader-fp32,lsrk-fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP32 error measurement")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design is "
+              "described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    variants = [v.split("-") for v in args.variants.split(",") if v]
+    results = {}
+    for scheme, prec in variants:
+        log(f"[bench] {scheme}-{prec}: warmup {args.warmup}, timing {args.steps} steps")
+        res, mesh, _ = run_variant(scheme, prec, args.steps, args.warmup)
+        log(f"[bench] {scheme}-{prec}: {res['dof_steps_per_s']:.3e} DoF-steps/s, {res['ms_per_step']:.3f} ms/step,"
+            f" kernels {res['kernels_ms']}")
+        results[f"{scheme}-{prec}"] = res
+        del mesh
+        torch.cuda.empty_cache()
+    head_key = "ader-fp64" if "ader-fp64" in results else next(iter(results))
+    head = results[head_key]
+    # dominant kernel of the headline variant
+    per_step = {k: ms * (5 if k == "operator_lsrk" else 1) for k, ms in head["kernels_ms"].items()}
+    dom = max(per_step, key=per_step.get)
+    ncells = 24 ** 3
+    bytes_launch = algorithmic_bytes(3, 5, dom) * ncells
+    achieved = bytes_launch / (head["kernels_ms"][dom] * 1e-3) / 1e9
+    traffic = read_traffic(dom, "c2", head["precision"])
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": bytes_launch, "launch_ms": head["kernels_ms"][dom]}
+    kernels = {}
+    for key, r in results.items():
+        for kname, ms in r["kernels_ms"].items():
+            b = algorithmic_bytes(3, 5, kname) * ncells
+            kernels[f"{key}:{kname}"] = {"ms": ms, "GB/s": b / (ms * 1e-3) / 1e9,
+                                         "frac_hbm": b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    extras = {}
+    if not args.no_extras and "ader-fp32" in results:
+        log("[bench] FP32-split error vs FP64")
+        extras["fp32_split_rel_err_5_steps"] = fp32_error()
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline (bounded sample)")
+        cpu = cpu_baseline()
+        log(f"[bench] oracle: {cpu['value']:.3e} DoF-steps/s on {cpu['cores']} threads")
+    line = {
+        "metric": "DoF-steps/s, FP64 vs FP32-split, LSRK vs ADER, at fixed error; p99 latency",
+        "value": head["dof_steps_per_s"], "unit": "DoF-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if head["precision"] == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "3D periodic unit cube, 24^3 hexes curved with amplitude 0.05, k=5 "
+                               "(1.19e7 DoF), rho=1, c = 8-mode Fourier field (seed 1805), upwind, "
+                               "Gaussian pressure pulse width 0.05",
+                   "scheme": head["scheme"], "precision": head["precision"], "dt": head["dt"],
+                   "courant": CR[head["scheme"]]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": {k: {"dof_steps_per_s": r["dof_steps_per_s"], "ms_per_step": r["ms_per_step"],
+                         "steps_to_T_0.5": r["steps_to_T"], "time_to_T_0.5_s": r["time_to_T_s"],
+                         "kernels_ms": r["kernels_ms"], "launch_shape": r["launch_shape"]}
+                     for k, r in results.items()},
+        "kernels": kernels,
+        "extras": extras,
+        "kernel_sources_sha256_16": kernel_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -201,9 +201,34 @@ dgw_status dgw_step_lsrk(dgw_mesh* mesh, int scheme, double t0, double dt, int n
 dgw_status dgw_step_ader(dgw_mesh* mesh, int flags, double t0, double dt, int nsteps, double* u,
                          double* work, int B, const dgw_sources* src, void* stream);
 
+/* Per-kernel timing of nsteps steps (the component breakdown of Sec. 4.3,
+ * Table 3): like dgw_step_lsrk / dgw_step_ader, with a HIP event pair on
+ * `stream` around every launch.  out->ms[i] is the mean duration of one launch
+ * of component i, out->launches[i] the number of launches; components:
+ * LSRK: 0 = fused operator + vector update; ADER: 0 = TCK sweep, 1 = fused
+ * operator + update.  Synchronous. */
+typedef struct dgw_profile {
+  int n;
+  double ms[4];
+  int64_t launches[4];
+  char names[4][32];
+} dgw_profile;
+dgw_status dgw_step_profile(dgw_mesh* mesh, int scheme, int ader_flags, double t0, double dt, int nsteps,
+                            double* u, double* work, int B, const dgw_sources* src, void* stream,
+                            dgw_profile* out);
+
 /* Energy (twice the acoustic energy) sum_K (v, rho v)_K + (p, p/(rho c^2))_K
  * per member, by Gauss quadrature; host_out[B]; synchronous on stream. */
 dgw_status dgw_energy(dgw_mesh* mesh, const double* u, int B, double* host_out, void* stream);
+
+/* Launch shape of the operator (which = 0) or TCK (which = 1) kernels:
+ * cells per workgroup and threads per workgroup.  Positive inputs set the
+ * shape (threads 64/128/256; the LDS tile must fit 160 KiB); the current
+ * shape is returned.  dgw_autotune times the candidates on scratch buffers
+ * for batch size B and keeps the fastest (cached per dim, k, precision, B,
+ * mesh size). */
+dgw_status dgw_launch_shape(dgw_mesh* mesh, int which, int* cells_per_group, int* threads);
+dgw_status dgw_autotune(dgw_mesh* mesh, int B, void* stream);
 
 /* ---------------------------------------------------------------- b6 ---- */
 typedef struct dgw_solve_desc {

@@ -58,6 +58,10 @@ class SourceDesc(C.Structure):
                 ("t0", C.POINTER(C.c_double)), ("amplitude", C.POINTER(C.c_double))]
 
 
+class Profile(C.Structure):
+    _fields_ = [("n", C.c_int), ("ms", C.c_double * 4), ("launches", C.c_int64 * 4), ("names", (C.c_char * 32) * 4)]
+
+
 class SolveDesc(C.Structure):
     _fields_ = [("scheme", C.c_int), ("ader_flags", C.c_int), ("courant", C.c_double), ("dt", C.c_double),
                 ("t0", C.c_double), ("t_end", C.c_double), ("sources", C.c_void_p), ("use_graph", C.c_int),
@@ -106,6 +110,9 @@ _SIGS = {
     "dgw_step_lsrk": ([_vp, _i, _d, _d, _i, _vp, _vp, _i, _vp, _vp], _i),
     "dgw_step_ader": ([_vp, _i, _d, _d, _i, _vp, _vp, _i, _vp, _vp], _i),
     "dgw_energy": ([_vp, _vp, _i, _dp, _vp], _i),
+    "dgw_step_profile": ([_vp, _i, _i, _d, _d, _i, _vp, _vp, _i, _vp, _vp, C.POINTER(Profile)], _i),
+    "dgw_autotune": ([_vp, _i, _vp], _i),
+    "dgw_launch_shape": ([_vp, _i, C.POINTER(_i), C.POINTER(_i)], _i),
     "dgw_solve_batch": ([_vp, C.POINTER(SolveDesc), _vp, _vp, _i, C.POINTER(SolveReport)], _i),
     "dgw_serve": ([C.POINTER(ServerDesc), C.POINTER(Request), _i, C.POINTER(Result), C.POINTER(ServeReport)], _i),
     "dgw_request_footprint": ([C.POINTER(Request)], _i64),
@@ -182,10 +189,16 @@ class Mesh:
                  device=0, max_batch=1, geo_degree=0):
         nodes = np.ascontiguousarray(geo_nodes, dtype=np.float64)
         nb = np.ascontiguousarray(neighbors, dtype=np.int64)
-        self._cb = material if isinstance(material, MATERIAL_FN) else material_callback(material)
+        ctx = None
+        if isinstance(material, FourierMaterial):
+            self._ctx = material
+            self._cb = FOURIER_MATERIAL_FN
+            ctx = C.cast(C.pointer(material), C.c_void_p)
+        else:
+            self._cb = material if isinstance(material, MATERIAL_FN) else material_callback(material)
         d = MeshDesc(dim=dim, degree=degree, n_cells=nodes.shape[0], geo_degree=geo_degree,
                      geo_nodes=_dptr(nodes), neighbors=nb.ctypes.data_as(C.POINTER(C.c_int64)),
-                     face_orient=None, material=self._cb, material_ctx=None, flux=flux, precision=precision,
+                     face_orient=None, material=self._cb, material_ctx=ctx, flux=flux, precision=precision,
                      device=device, max_batch=max_batch)
         h = C.c_void_p()
         check(lib.dgw_mesh_create(C.byref(d), C.byref(h)), "dgw_mesh_create")
@@ -268,6 +281,24 @@ class Mesh:
         check(lib.dgw_step_ader(self.h, flags, t0, dt, nsteps, _tptr(u), _tptr(work), B,
                                 sources.h if sources else None, _stream(stream)), "dgw_step_ader")
         return u
+
+    def profile(self, u, scheme, t0, dt, nsteps, work=None, sources=None, B=None, ader_flags=0, stream=None):
+        """Mean duration (ms) of one launch of each kernel over nsteps steps."""
+        B = B or (u.shape[0] if u.dim() == 4 else 1)
+        work = self.work(B) if work is None else work
+        pr = Profile()
+        check(lib.dgw_step_profile(self.h, scheme, ader_flags, t0, dt, nsteps, _tptr(u), _tptr(work), B,
+                                   sources.h if sources else None, _stream(stream), C.byref(pr)), "dgw_step_profile")
+        return {pr.names[i].value.decode(): (pr.ms[i], pr.launches[i]) for i in range(pr.n)}
+
+    def autotune(self, B=1, stream=None):
+        check(lib.dgw_autotune(self.h, B, _stream(stream)), "dgw_autotune")
+        return self.launch_shape(0), self.launch_shape(1)
+
+    def launch_shape(self, which, cells=0, threads=0):
+        c, t = C.c_int(cells), C.c_int(threads)
+        check(lib.dgw_launch_shape(self.h, which, C.byref(c), C.byref(t)), "dgw_launch_shape")
+        return c.value, t.value
 
     def energy(self, u, B=None, stream=None):
         B = B or (u.shape[0] if u.dim() == 4 else 1)

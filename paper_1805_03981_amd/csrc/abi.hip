@@ -2,6 +2,7 @@
 // LSRK(5,4) and ADER steppers, point sources, energy and the batch solver.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -72,11 +73,13 @@ static int ipw(int b, int e) {
 
 static int64_t state_elems(const dgw_mesh* m) { return m->hs.nc * m->ncomp * m->np; }
 
-static LaunchShape default_shape(int lds_per_cell, int lines_per_cell) {
+static const int64_t kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
+static const int NTH_HOST = 256;              // threads per workgroup of every kernel
+
+static LaunchShape default_shape(const Launchers* L, int lds_per_cell) {
   LaunchShape s;
-  s.cpw = std::max(1, std::min(16, 40960 / std::max(1, lds_per_cell)));
-  const int lines = s.cpw * lines_per_cell;
-  s.nth = lines >= 192 ? 256 : (lines >= 96 ? 128 : 64);
+  // the larger group when two of them still fit a CU twice over
+  s.sel = (int64_t)L->cpw[1] * lds_per_cell * 2 <= kLdsLimit ? 1 : 0;
   return s;
 }
 
@@ -112,7 +115,7 @@ static OpParams op_params(const dgw_mesh* m, int B, const dgw_sources* src) {
   p.nb = m->d_nb;
   p.tab = tab_ptr(m);
   p.nc = m->hs.nc;
-  p.cpw = m->op_shape.cpw;
+  p.cpw = m->L->cpw[m->op_shape.sel];
   p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
   p.B = B;
   p.central = m->flux == DGW_FLUX_CENTRAL;
@@ -128,7 +131,7 @@ static TckParams tck_params(const dgw_mesh* m, int B, const dgw_sources* src) {
   p.tab = tab_ptr(m);
   p.tab64 = m->d_tab64;
   p.nc = m->hs.nc;
-  p.cpw = m->tck_shape.cpw;
+  p.cpw = m->L->cpw[m->tck_shape.sel];
   p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
   p.B = B;
   fill_sources(p.src, src);
@@ -137,7 +140,7 @@ static TckParams tck_params(const dgw_mesh* m, int B, const dgw_sources* src) {
 
 static dgw_status check_batch(const dgw_mesh* m, int B, const dgw_sources* src) {
   if (B < 1 || B > m->max_batch) return fail(DGW_EINVAL, "B must be in 1..max_batch");
-  if ((int64_t)B * (m->hs.nc / std::max<int64_t>(1, m->op_shape.cpw) + 1) > INT32_MAX)
+  if ((int64_t)B * (m->hs.nc + 1) > INT32_MAX)
     return fail(DGW_EINVAL, "grid too large");
   if (src) {
     if (src->mesh != m) return fail(DGW_EINVAL, "sources were created for another mesh");
@@ -160,7 +163,7 @@ static dgw_status lsrk_step(dgw_mesh* m, int B, const dgw_sources* src, double t
     p.acoef = kLsrk.A[i];
     p.bcoef = kLsrk.B[i];
     p.time.t_off = kLsrk.C[i] * dt;
-    DGW_HIP(m->L->op[EPI_LSRK](p, m->op_shape.nth, s));
+    DGW_HIP(m->L->op[EPI_LSRK][m->op_shape.sel](p, s));
     std::swap(cur, oth);
   }
   return DGW_OK;
@@ -174,13 +177,13 @@ static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* sr
   tp.I = I;
   tp.dt = dt;
   tp.time = StepTime{ctr, t0, dt, step_add, 0.0};
-  DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0](tp, m->tck_shape.nth, s));
+  DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0][m->tck_shape.sel](tp, s));
   OpParams p = op_params(m, B, src);
   p.u = I;
   p.u_base = cur;
   p.u_next = oth;
   p.time = StepTime{ctr, t0, dt, step_add, 0.0};
-  DGW_HIP(m->L->op[EPI_ADD](p, m->op_shape.nth, s));
+  DGW_HIP(m->L->op[EPI_ADD][m->op_shape.sel](p, s));
   std::swap(cur, oth);
   return DGW_OK;
 }
@@ -196,7 +199,7 @@ static dgw_status energy_impl(dgw_mesh* m, const double* u, int B, double* host_
   p.cpw = std::max(1, std::min(16, 16384 / m->L->energy_lds_per_cell));
   p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
   p.B = B;
-  DGW_HIP(m->L->energy(p, 256, s));
+  DGW_HIP(m->L->energy(p, s));
   std::vector<double> part((size_t)B * p.groups);
   DGW_HIP(hipMemcpyAsync(part.data(), m->d_partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   DGW_HIP(hipStreamSynchronize(s));
@@ -236,7 +239,7 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
   hipEvent_t e0, e1;
   DGW_HIP(hipEventCreate(&e0));
   DGW_HIP(hipEventCreate(&e1));
-  const int64_t lds_limit = 160 * 1024;
+  const int64_t lds_limit = kLdsLimit;
   auto time_it = [&](auto&& launch) -> float {
     for (int w = 0; w < 2; ++w)
       if (launch() != hipSuccess) return 1e30f;
@@ -248,38 +251,36 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
     (void)hipEventElapsedTime(&ms, e0, e1);
     return ms;
   };
-  const int cpws[] = {1, 2, 3, 4, 6, 8, 12, 16};
-  const int nths[] = {64, 128, 256};
   LaunchShape best_op = m->op_shape, best_tck = m->tck_shape;
   float t_op = 1e30f, t_tck = 1e30f;
-  for (int cpw : cpws)
-    for (int nth : nths) {
-      if ((int64_t)cpw * m->L->op_lds_per_cell <= lds_limit) {
-        OpParams p = op_params(m, B, nullptr);
-        p.cpw = cpw;
-        p.groups = (int)((m->hs.nc + cpw - 1) / cpw);
-        p.u = a;
-        p.out = b;
-        const float t = time_it([&]() { return m->L->op[EPI_STORE](p, nth, s); });
-        if (t < t_op) {
-          t_op = t;
-          best_op = LaunchShape{cpw, nth};
-        }
-      }
-      if ((int64_t)cpw * m->L->tck_lds_per_cell <= lds_limit) {
-        TckParams p = tck_params(m, B, nullptr);
-        p.cpw = cpw;
-        p.groups = (int)((m->hs.nc + cpw - 1) / cpw);
-        p.u = a;
-        p.I = b;
-        p.dt = 1e-3;
-        const float t = time_it([&]() { return m->L->tck[0](p, nth, s); });
-        if (t < t_tck) {
-          t_tck = t;
-          best_tck = LaunchShape{cpw, nth};
-        }
+  for (int sel = 0; sel < 2; ++sel) {
+    const int cpw = m->L->cpw[sel];
+    if ((int64_t)cpw * m->L->op_lds_per_cell <= lds_limit) {
+      OpParams p = op_params(m, B, nullptr);
+      p.cpw = cpw;
+      p.groups = (int)((m->hs.nc + cpw - 1) / cpw);
+      p.u = a;
+      p.out = b;
+      const float t = time_it([&]() { return m->L->op[EPI_STORE][sel](p, s); });
+      if (t < t_op) {
+        t_op = t;
+        best_op.sel = sel;
       }
     }
+    if ((int64_t)cpw * m->L->tck_lds_per_cell <= lds_limit) {
+      TckParams p = tck_params(m, B, nullptr);
+      p.cpw = cpw;
+      p.groups = (int)((m->hs.nc + cpw - 1) / cpw);
+      p.u = a;
+      p.I = b;
+      p.dt = 1e-3;
+      const float t = time_it([&]() { return m->L->tck[0][sel](p, s); });
+      if (t < t_tck) {
+        t_tck = t;
+        best_tck.sel = sel;
+      }
+    }
+  }
   (void)hipGetLastError();
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -410,8 +411,8 @@ dgw_status dgw_mesh_create(const dgw_mesh_desc* desc, dgw_mesh** out) {
   } catch (const std::bad_alloc&) {
     return fail(DGW_ENOMEM, "host allocation during setup");
   }
-  m->op_shape = default_shape(m->L->op_lds_per_cell, m->ncomp * m->nf);
-  m->tck_shape = default_shape(m->L->tck_lds_per_cell, m->ncomp * m->nf);
+  m->op_shape = default_shape(m->L, m->L->op_lds_per_cell);
+  m->tck_shape = default_shape(m->L, m->L->tck_lds_per_cell);
   if (m->device >= 0) {
     if (hipSetDevice(m->device) != hipSuccess) return fail(DGW_EDEVICE, "hipSetDevice failed");
     dgw_status st = upload(m.get());
@@ -502,7 +503,7 @@ dgw_status dgw_operator_apply(dgw_mesh* m, const double* u, double* out, int B, 
   OpParams p = op_params(m, B, nullptr);
   p.u = u;
   p.out = out;
-  DGW_HIP(m->L->op[EPI_STORE](p, m->op_shape.nth, (hipStream_t)stream));
+  DGW_HIP(m->L->op[EPI_STORE][m->op_shape.sel](p, (hipStream_t)stream));
   return DGW_OK;
 }
 
@@ -551,6 +552,107 @@ dgw_status dgw_step_ader(dgw_mesh* m, int flags, double t0, double dt, int nstep
   for (int k = 0; k < nsteps; ++k)
     if ((st = ader_step(m, flags, B, src, t0, dt, k, nullptr, cur, oth, I, s))) return st;
   if (cur != u) DGW_HIP(hipMemcpyAsync(u, cur, state_elems(m) * 8 * B, hipMemcpyDeviceToDevice, s));
+  return DGW_OK;
+}
+
+dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, double dt, int nsteps, double* u,
+                            double* work, int B, const dgw_sources* src, void* stream, dgw_profile* out) {
+  if (!out) return fail(DGW_EINVAL, "out is NULL");
+  if (scheme != DGW_SCHEME_LSRK54 && scheme != DGW_SCHEME_ADER) return fail(DGW_EINVAL, "bad scheme");
+  dgw_status st = check_step(m, dt, nsteps, u, work, B, src);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(m->mtx);
+  if ((st = set_device(m))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  std::memset(out, 0, sizeof(*out));
+  const int ncomp = scheme == DGW_SCHEME_ADER ? 2 : 1;
+  out->n = ncomp;
+  std::snprintf(out->names[0], 32, "%s", scheme == DGW_SCHEME_ADER ? "tck" : "operator_lsrk");
+  if (ncomp > 1) std::snprintf(out->names[1], 32, "%s", "operator_ader_update");
+  const int per_step = scheme == DGW_SCHEME_ADER ? 2 : 5;
+  std::vector<hipEvent_t> ev((size_t)2 * per_step * std::max(nsteps, 1));
+  for (auto& e : ev) DGW_HIP(hipEventCreate(&e));
+  double* cur = u;
+  double* oth = work + state_elems(m) * B;
+  double* aux = work;
+  for (int k = 0; k < nsteps; ++k) {
+    if (scheme == DGW_SCHEME_LSRK54) {
+      OpParams p = op_params(m, B, src);
+      p.dt = dt;
+      p.du = aux;
+      p.time = StepTime{nullptr, t0, dt, k, 0.0};
+      for (int i = 0; i < 5; ++i) {
+        p.u = cur;
+        p.u_next = oth;
+        p.acoef = kLsrk.A[i];
+        p.bcoef = kLsrk.B[i];
+        p.time.t_off = kLsrk.C[i] * dt;
+        DGW_HIP(hipEventRecord(ev[(size_t)2 * (k * 5 + i)], s));
+        DGW_HIP(m->L->op[EPI_LSRK][m->op_shape.sel](p, s));
+        DGW_HIP(hipEventRecord(ev[(size_t)2 * (k * 5 + i) + 1], s));
+        std::swap(cur, oth);
+      }
+    } else {
+      TckParams tp = tck_params(m, B, src);
+      tp.u = cur;
+      tp.I = aux;
+      tp.dt = dt;
+      tp.time = StepTime{nullptr, t0, dt, k, 0.0};
+      DGW_HIP(hipEventRecord(ev[(size_t)4 * k], s));
+      DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0][m->tck_shape.sel](tp, s));
+      DGW_HIP(hipEventRecord(ev[(size_t)4 * k + 1], s));
+      OpParams p = op_params(m, B, src);
+      p.u = aux;
+      p.u_base = cur;
+      p.u_next = oth;
+      p.time = StepTime{nullptr, t0, dt, k, 0.0};
+      DGW_HIP(hipEventRecord(ev[(size_t)4 * k + 2], s));
+      DGW_HIP(m->L->op[EPI_ADD][m->op_shape.sel](p, s));
+      DGW_HIP(hipEventRecord(ev[(size_t)4 * k + 3], s));
+      std::swap(cur, oth);
+    }
+  }
+  DGW_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < nsteps; ++k)
+    for (int i = 0; i < per_step; ++i) {
+      float ms = 0;
+      DGW_HIP(hipEventElapsedTime(&ms, ev[(size_t)2 * (k * per_step + i)], ev[(size_t)2 * (k * per_step + i) + 1]));
+      const int c = scheme == DGW_SCHEME_ADER ? i : 0;
+      out->ms[c] += ms;
+      out->launches[c] += 1;
+    }
+  for (int c = 0; c < ncomp; ++c)
+    if (out->launches[c]) out->ms[c] /= (double)out->launches[c];
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (cur != u) DGW_HIP(hipMemcpyAsync(u, cur, state_elems(m) * 8 * B, hipMemcpyDeviceToDevice, s));
+  DGW_HIP(hipStreamSynchronize(s));
+  return DGW_OK;
+}
+
+dgw_status dgw_autotune(dgw_mesh* m, int B, void* stream) {
+  dgw_status st = check_mesh(m);
+  if (st) return st;
+  if ((st = check_batch(m, B, nullptr))) return st;
+  std::lock_guard<std::mutex> lk(m->mtx);
+  if ((st = set_device(m))) return st;
+  return autotune(m, B, (hipStream_t)stream);
+}
+
+dgw_status dgw_launch_shape(dgw_mesh* m, int which, int* cells_per_group, int* threads) {
+  if (!m || !cells_per_group || !threads || (which != 0 && which != 1)) return fail(DGW_EINVAL, "bad argument");
+  LaunchShape& sh = which == 0 ? m->op_shape : m->tck_shape;
+  if (*cells_per_group > 0) {
+    const int per_cell = which == 0 ? m->L->op_lds_per_cell : m->L->tck_lds_per_cell;
+    int sel = -1;
+    for (int c = 0; c < 2; ++c)
+      if (m->L->cpw[c] == *cells_per_group && (int64_t)m->L->cpw[c] * per_cell <= kLdsLimit) sel = c;
+    if (sel < 0 || (*threads > 0 && *threads != NTH_HOST))
+      return fail(DGW_EINVAL, "cells_per_group must be one of the compiled shapes (" + std::to_string(m->L->cpw[0]) +
+                                  ", " + std::to_string(m->L->cpw[1]) + ") and fit the LDS; threads must be 256");
+    sh.sel = sel;
+  }
+  *cells_per_group = m->L->cpw[sh.sel];
+  *threads = NTH_HOST;
   return DGW_OK;
 }
 

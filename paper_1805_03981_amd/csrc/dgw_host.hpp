@@ -53,8 +53,9 @@ void node_coords(const HostSetup& hs, std::vector<double>& out);
 // Evaluate the map of one cell at a reference point: x[d], J[d][d].
 void map_point(const HostSetup& hs, int64_t cell, const double* xi, double* x, double* J);
 
+// Which compiled launch shape (cells per workgroup) a kernel family uses.
 struct LaunchShape {
-  int cpw = 1, nth = 256;
+  int sel = 0;
 };
 
 }  // namespace dgw

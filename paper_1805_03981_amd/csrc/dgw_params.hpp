@@ -62,14 +62,17 @@ struct EnergyParams {
   int cpw, groups, B;
 };
 
-using OpLaunch = hipError_t (*)(const OpParams&, int nthreads, hipStream_t);
-using TckLaunch = hipError_t (*)(const TckParams&, int nthreads, hipStream_t);
-using EnergyLaunch = hipError_t (*)(const EnergyParams&, int nthreads, hipStream_t);
+using OpLaunch = hipError_t (*)(const OpParams&, hipStream_t);
+using TckLaunch = hipError_t (*)(const TckParams&, hipStream_t);
+using EnergyLaunch = hipError_t (*)(const EnergyParams&, hipStream_t);
 
+// Kernels are compiled for two launch shapes (sel 0/1: cells per workgroup
+// cpw[sel]); p.cpw must equal cpw[sel] of the launcher that is called.
 struct Launchers {
-  OpLaunch op[3];         // by Epilogue
-  TckLaunch tck[2];       // [0] degree reduction, [1] no reduction
+  OpLaunch op[3][2];      // [Epilogue][sel]
+  TckLaunch tck[2][2];    // [0 reduction, 1 no reduction][sel]
   EnergyLaunch energy;
+  int cpw[2];
   int op_lds_per_cell;    // bytes of LDS per cell
   int tck_lds_per_cell;
   int energy_lds_per_cell;
@@ -81,7 +84,9 @@ const Launchers* launchers(int dim, int n, int precision);
 // Table layout (element offsets) of the 1D matrices for n = k+1 nodes.
 // S (n x n), S^-1 (n x n), D (n x n), LF0 (n), LF1 (n); then per reduced
 // level l = 1.. with m = n - 2l points and mp = n - 2(l-1):
-// D_l (m x m), P_l (m x mp), E_l (n x m), F_l (m x n).
+// D_l (m x m) collocation derivative, P_l (m x mp) projection from level
+// l-1, E_l (mp x m) interpolation back to level l-1, F_l (m x n) evaluation
+// of a level-0 Gauss polynomial at the level-l points.
 __host__ __device__ constexpr int tab_S(int) { return 0; }
 __host__ __device__ constexpr int tab_Sinv(int n) { return n * n; }
 __host__ __device__ constexpr int tab_D(int n) { return 2 * n * n; }
@@ -91,7 +96,7 @@ __host__ __device__ constexpr int tab_level(int n, int l) {
   int off = 3 * n * n + 2 * n;
   for (int j = 1; j < l; ++j) {
     const int m = n - 2 * j, mp = n - 2 * (j - 1);
-    off += m * m + m * mp + n * m + m * n;
+    off += m * m + m * mp + mp * m + m * n;
   }
   return off;
 }
@@ -103,7 +108,7 @@ __host__ __device__ constexpr int tab_level_E(int n, int l) {
   return tab_level_P(n, l) + (n - 2 * l) * (n - 2 * (l - 1));
 }
 __host__ __device__ constexpr int tab_level_F(int n, int l) {
-  return tab_level_E(n, l) + n * (n - 2 * l);
+  return tab_level_E(n, l) + (n - 2 * (l - 1)) * (n - 2 * l);
 }
 __host__ __device__ constexpr int num_levels(int n) { return (n + 1) / 2; }  // n, n-2, ... >= 1
 __host__ __device__ constexpr int tab_size(int n) { return tab_level(n, num_levels(n)); }

@@ -12,39 +12,47 @@ static hipError_t ensure_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int D, int N, typename T, int EPI>
-hipError_t launch_op(const OpParams& p, int nth, hipStream_t s) {
-  const size_t lds = (size_t)p.cpw * OpLayout<D, N, T>::per_cell * sizeof(T);
-  hipError_t e = ensure_lds(op_kernel<D, N, T, EPI>, lds);
+template <int D, int N, typename T, int EPI, int SEL>
+hipError_t launch_op(const OpParams& p, hipStream_t s) {
+  constexpr int CPW = cells_per_group(D, N, SEL);
+  if (p.cpw != CPW) return hipErrorInvalidValue;
+  const size_t lds = (size_t)CPW * OpLayout<D, N, T>::per_cell * sizeof(T);
+  hipError_t e = ensure_lds(op_kernel<D, N, T, EPI, CPW>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((op_kernel<D, N, T, EPI>), dim3(p.groups * p.B), dim3(nth), lds, s, p);
+  hipLaunchKernelGGL((op_kernel<D, N, T, EPI, CPW>), dim3(p.groups * p.B), dim3(NTH), lds, s, p);
   return hipGetLastError();
 }
 
-template <int D, int N, typename T, bool R>
-hipError_t launch_tck(const TckParams& p, int nth, hipStream_t s) {
-  const size_t lds = (size_t)p.cpw * TckLayout<D, N, T>::bytes_per_cell;
-  hipError_t e = ensure_lds(tck_kernel<D, N, T, R>, lds);
+template <int D, int N, typename T, bool R, int SEL>
+hipError_t launch_tck(const TckParams& p, hipStream_t s) {
+  constexpr int CPW = cells_per_group(D, N, SEL);
+  if (p.cpw != CPW) return hipErrorInvalidValue;
+  const size_t lds = (size_t)CPW * TckLayout<D, N, T>::bytes_per_cell;
+  hipError_t e = ensure_lds(tck_kernel<D, N, T, R, CPW>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((tck_kernel<D, N, T, R>), dim3(p.groups * p.B), dim3(nth), lds, s, p);
+  hipLaunchKernelGGL((tck_kernel<D, N, T, R, CPW>), dim3(p.groups * p.B), dim3(NTH), lds, s, p);
   return hipGetLastError();
 }
 
 template <int D, int N, typename T>
-hipError_t launch_energy(const EnergyParams& p, int nth, hipStream_t s) {
+hipError_t launch_energy(const EnergyParams& p, hipStream_t s) {
   const size_t lds = (size_t)p.cpw * (D + 1) * ipow(N, D) * sizeof(T);
   hipError_t e = ensure_lds(energy_kernel<D, N, T>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((energy_kernel<D, N, T>), dim3(p.groups * p.B), dim3(nth), lds, s, p);
+  hipLaunchKernelGGL((energy_kernel<D, N, T>), dim3(p.groups * p.B), dim3(NTH), lds, s, p);
   return hipGetLastError();
 }
 
 template <int D, int N, typename T>
 const Launchers* make_launchers() {
   static const Launchers L = {
-      {launch_op<D, N, T, EPI_STORE>, launch_op<D, N, T, EPI_LSRK>, launch_op<D, N, T, EPI_ADD>},
-      {launch_tck<D, N, T, true>, launch_tck<D, N, T, false>},
+      {{launch_op<D, N, T, EPI_STORE, 0>, launch_op<D, N, T, EPI_STORE, 1>},
+       {launch_op<D, N, T, EPI_LSRK, 0>, launch_op<D, N, T, EPI_LSRK, 1>},
+       {launch_op<D, N, T, EPI_ADD, 0>, launch_op<D, N, T, EPI_ADD, 1>}},
+      {{launch_tck<D, N, T, true, 0>, launch_tck<D, N, T, true, 1>},
+       {launch_tck<D, N, T, false, 0>, launch_tck<D, N, T, false, 1>}},
       launch_energy<D, N, T>,
+      {cells_per_group(D, N, 0), cells_per_group(D, N, 1)},
       (int)(OpLayout<D, N, T>::per_cell * sizeof(T)),
       TckLayout<D, N, T>::bytes_per_cell,
       (int)((D + 1) * ipow(N, D) * sizeof(T))};

@@ -25,6 +25,16 @@
 namespace dgw {
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+__host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Every kernel runs 256 threads (four wavefronts) per workgroup.
+constexpr int NTH = 256;
+
+// Cells per workgroup of the two compiled launch shapes: sel 0 gives about
+// one cell point per thread, sel 1 twice as many cells.
+__host__ __device__ constexpr int cells_per_group(int d, int n, int sel) {
+  return (NTH / ipow(n, d) > 1 ? NTH / ipow(n, d) : 1) * (sel + 1);
+}
 
 // Workgroup id -> logical id so that each XCD (workgroups are dispatched round
 // robin over the 8 XCDs) processes one contiguous range of logical ids: the
@@ -79,7 +89,7 @@ __device__ __forceinline__ void tpass(const TI* in, TO* out, int nslices, const 
                                       double scale = 1.0) {
   using P = Pass<D, DIR, MI, MO, A0, A1, A2>;
   const int total = nslices * P::NL;
-  for (int w = threadIdx.x; w < total; w += blockDim.x) {
+  for (int w = threadIdx.x; w < total; w += NTH) {
     const int s = w / P::NL;
     const int L = w - s * P::NL;
     int bi, bo;
@@ -138,162 +148,183 @@ __device__ inline double ricker_integral(const double* w, double t1, double t2) 
 
 // ------------------------------------------------------------------------
 // Fused operator sweep: L u = -M^-1 K u with an epilogue.
+//
+// Every global operand of the workgroup (its state tile, the neighbours' GL
+// face nodes, the metric and mass factors of every point, the face area
+// vectors and impedances, and the epilogue's state operands) is requested
+// in one batch at the start.  The geometry stays in registers of the thread
+// that owns the point (thread-per-point phases) or the face point, so its
+// memory latency overlaps the basis-change passes and only one memory round
+// trip per workgroup is exposed.
 // ------------------------------------------------------------------------
 template <int D, int N, typename T>
 struct OpLayout {
   static constexpr int NC = D + 1, NP = ipow(N, D), NF = ipow(N, D - 1), NFACE = 2 * D;
-  static constexpr int per_cell = 2 * NC * NP + NFACE * NC * NF;  // elements of T
+  static constexpr int per_cell = 3 * NC * NP + NFACE * NC * NF;  // elements of T
 };
 
+__device__ __forceinline__ int dir_stride(int n, int dir) { return dir == 0 ? 1 : (dir == 1 ? n : n * n); }
+
+// C2 of the operator: R (+)= D_b^T F along the b-lines, plus the lifts of the
+// two face fluxes of direction b (rank one in the normal direction).
 template <int D, int N, typename T, int DIR>
-__device__ __forceinline__ void op_direction(const OpParams& p, const T* sU, T* sR, const T* sN,
-                                             int64_t cell0, int ncl) {
-  using Lay = OpLayout<D, N, T>;
-  constexpr int NC = Lay::NC, NP = Lay::NP, NF = Lay::NF, NFACE = Lay::NFACE;
+__device__ __forceinline__ void op_lines(const T* __restrict__ tab, const T* sT, const T* sN, T* sR, int ncl) {
+  constexpr int NC = D + 1, NP = ipow(N, D), NF = ipow(N, D - 1), NFACE = 2 * D;
   using P = Pass<D, DIR, N, N, N, N, N>;
-  const T* tab = static_cast<const T*>(p.tab);
   const T* Dm = tab + tab_D(N);
   const T* LF0 = tab + tab_LF0(N);
   const T* LF1 = tab + tab_LF1(N);
-  const int total = ncl * NF;
-  for (int w = threadIdx.x; w < total; w += blockDim.x) {
-    const int c = w / NF;
-    const int L = w - c * NF;
-    const int64_t cell = cell0 + c;
+  for (int w = threadIdx.x; w < ncl * NC * NF; w += NTH) {
+    const int sl = w / NF;  // c * NC + v
+    const int L = w - sl * NF;
+    const int c = sl / NC, v = sl - c * NC;
     int bq, bq2;
     P::base(L, bq, bq2);
-    const T* su = sU + c * NC * NP;
-    T x[NC][N];
+    T F[N];
 #pragma unroll
-    for (int v = 0; v < NC; ++v)
+    for (int j = 0; j < N; ++j) F[j] = sT[sl * NP + bq + j * P::STEP_IN];
+    const T f0 = sN[((c * NFACE + 2 * DIR) * NC + v) * NF + L];
+    const T f1 = sN[((c * NFACE + 2 * DIR + 1) * NC + v) * NF + L];
+    T* r = sR + sl * NP + bq;
 #pragma unroll
-      for (int j = 0; j < N; ++j) x[v][j] = su[v * NP + bq + j * P::STEP_IN];
-    // volume fluxes in FP64 metric: F_{v_a} = G_{ba} p, F_p = sum_a G_{ba} v_a
-    const double* G = p.geo_cell + cell * (int64_t)((D * D + 2) * NP) + bq;
-    T F[NC][N];
+    for (int i = 0; i < N; ++i) {
+      T acc = LF0[i] * f0;
+      acc = fma(LF1[i], f1, acc);
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const double pj = (double)x[D][j];
-      double fp = 0.0;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const double g = G[(DIR * D + a) * NP + j * P::STEP_IN];
-        F[a][j] = (T)(g * pj);
-        fp = fma(g, (double)x[a][j], fp);
-      }
-      F[D][j] = (T)fp;
+      for (int j = 0; j < N; ++j) acc = fma(Dm[j * N + i], F[j], acc);
+      if constexpr (DIR == 0)
+        r[i * P::STEP_IN] = acc;
+      else
+        r[i * P::STEP_IN] += acc;
     }
-    // R_i = sum_j D[j][i] F_j  (transposed collocation derivative)
-    T R[NC][N];
-#pragma unroll
-    for (int v = 0; v < NC; ++v)
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        T acc = Dm[i] * F[v][0];
-#pragma unroll
-        for (int j = 1; j < N; ++j) acc = fma(Dm[j * N + i], F[v][j], acc);
-        R[v][i] = acc;
-      }
-    // the two faces normal to DIR
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const T* LF = s == 0 ? LF0 : LF1;
-      const int f = 2 * DIR + s;
-      double um[NC], up[NC];
-#pragma unroll
-      for (int v = 0; v < NC; ++v) {
-        T acc = LF[0] * x[v][0];
-#pragma unroll
-        for (int j = 1; j < N; ++j) acc = fma(LF[j], x[v][j], acc);
-        um[v] = (double)acc;
-        up[v] = (double)sN[((c * NFACE + f) * NC + v) * NF + L];
-      }
-      const double* fg = p.geo_face + ((cell * NFACE + f) * (int64_t)(D + 2)) * NF + L;
-      double a[D];
-      double area2 = 0.0, vnm = 0.0, vnp = 0.0;
-#pragma unroll
-      for (int e = 0; e < D; ++e) {
-        a[e] = fg[e * NF];
-        area2 = fma(a[e], a[e], area2);
-        vnm = fma(a[e], um[e], vnm);
-        vnp = fma(a[e], up[e], vnp);
-      }
-      const double area = sqrt(area2);
-      vnm /= area;
-      vnp /= area;
-      double ps, vs;
-      if (p.central) {
-        ps = 0.5 * (um[D] + up[D]);
-        vs = 0.5 * (vnm + vnp);
-      } else {
-        const double Zm = fg[D * NF], Zp = fg[(D + 1) * NF];
-        const double inv = 1.0 / (Zm + Zp);
-        ps = (Zp * um[D] + Zm * up[D] + Zm * Zp * (vnm - vnp)) * inv;
-        vs = (Zm * vnm + Zp * vnp + um[D] - up[D]) * inv;
-      }
-      T fl[NC];
-#pragma unroll
-      for (int e = 0; e < D; ++e) fl[e] = (T)(-a[e] * ps);
-      fl[D] = (T)(-area * vs);
-#pragma unroll
-      for (int v = 0; v < NC; ++v)
-#pragma unroll
-        for (int i = 0; i < N; ++i) R[v][i] = fma(LF[i], fl[v], R[v][i]);
-    }
-    T* sr = sR + c * NC * NP;
-#pragma unroll
-    for (int v = 0; v < NC; ++v)
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const int q = v * NP + bq + i * P::STEP_IN;
-        if constexpr (DIR == 0)
-          sr[q] = R[v][i];
-        else
-          sr[q] += R[v][i];
-      }
   }
 }
 
-template <int D, int N, typename T, int EPI>
-__global__ void __launch_bounds__(256) op_kernel(OpParams p) {
+// C1 of the operator: the pointwise volume fluxes of direction b in FP64,
+// F_{v_a} = G_{ba} p, F_p = sum_a G_{ba} v_a, with G = w det J J^-1.
+template <int D, int N, typename T, int PS, int DIR>
+__device__ __forceinline__ void op_points(const double (&g)[PS][D * D + 2], const T* sU, T* sT, int ncl) {
+  constexpr int NC = D + 1, NP = ipow(N, D);
+#pragma unroll
+  for (int s = 0; s < PS; ++s) {
+    const int i = threadIdx.x + s * NTH;
+    if (i < ncl * NP) {
+      const int c = i / NP, q = i - c * NP;
+      const T* su = sU + c * NC * NP + q;
+      T* st = sT + c * NC * NP + q;
+      const double pq = (double)su[D * NP];
+      double fp = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const double gba = g[s][DIR * D + a];
+        st[a * NP] = (T)(gba * pq);
+        fp = fma(gba, (double)su[a * NP], fp);
+      }
+      st[D * NP] = (T)fp;
+    }
+  }
+}
+
+template <int D, int N, typename T, int EPI, int CPW>
+__global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
   using Lay = OpLayout<D, N, T>;
-  constexpr int NC = Lay::NC, NP = Lay::NP, NF = Lay::NF, NFACE = Lay::NFACE;
+  constexpr int NC = Lay::NC, NP = Lay::NP, NF = Lay::NF, NFACE = Lay::NFACE, G2 = D * D + 2;
+  constexpr int PS = cdiv(CPW * NP, NTH);             // cell points per thread
+  constexpr int FS = cdiv(CPW * NFACE * NF, NTH);     // face points per thread
+  constexpr int ES = cdiv(CPW * NC * NP, NTH);        // tile elements per thread
+  constexpr int NS = cdiv(CPW * NFACE * NC * NF, NTH);  // neighbour trace values per thread
   extern __shared__ __align__(16) unsigned char smem[];
   T* sU = reinterpret_cast<T*>(smem);
-  T* sR = sU + p.cpw * NC * NP;
-  T* sN = sR + p.cpw * NC * NP;
+  T* sR = sU + CPW * NC * NP;
+  T* sT = sR + CPW * NC * NP;
+  T* sN = sT + CPW * NC * NP;
   const T* tab = static_cast<const T*>(p.tab);
+  const int tid = threadIdx.x;
 
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int member = logical % p.B;
   const int group = logical / p.B;
-  const int64_t cell0 = (int64_t)group * p.cpw;
-  const int ncl = (int)min((int64_t)p.cpw, p.nc - cell0);
+  const int64_t cell0 = (int64_t)group * CPW;
+  const int ncl = (int)min((int64_t)CPW, p.nc - cell0);
   const int64_t moff = (int64_t)member * p.nc * NC * NP;
-  const double* u = p.u + moff;
+  const int64_t gofs = moff + cell0 * NC * NP;
+  const int nel = ncl * NC * NP;
 
-  // A: cell tiles (contiguous) and neighbour GL face nodes
-  {
-    const double* src = u + cell0 * NC * NP;
-    for (int i = threadIdx.x; i < ncl * NC * NP; i += blockDim.x) sU[i] = (T)src[i];
-    const int tot = ncl * NFACE * NC * NF;
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-      const int t = i % NF;
-      int r = i / NF;
-      const int v = r % NC;
-      r /= NC;
-      const int f = r % NFACE;
-      const int c = r / NFACE;
-      const int nbc = p.nb[(cell0 + c) * NFACE + f];
-      // GL node on the neighbour's face opposite to f, tangential index t
-      const int fo = f ^ 1, dir = fo >> 1, side = fo & 1;
-      const int st = dir == 0 ? 1 : (dir == 1 ? N : N * N);
-      const int q = (t % st) + (side ? (N - 1) * st : 0) + (t / st) * st * N;
-      sN[i] = (T)u[(int64_t)nbc * NC * NP + v * NP + q];
+  // ---- A: all global operands, in dependency order
+  int nbi[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = tid + s * NTH;
+    nbi[s] = 0;
+    if (i < ncl * NFACE * NC * NF) {
+      const int cf = i / (NC * NF);  // c * NFACE + f
+      nbi[s] = p.nb[cell0 * NFACE + cf];
     }
   }
+  double ev[ES];
+#pragma unroll
+  for (int s = 0; s < ES; ++s) {
+    const int i = tid + s * NTH;
+    ev[s] = i < nel ? p.u[gofs + i] : 0.0;
+  }
+  double nv[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = tid + s * NTH;
+    nv[s] = 0.0;
+    if (i < ncl * NFACE * NC * NF) {
+      const int t = i % NF;
+      const int r = i / NF;
+      const int v = r % NC;
+      const int f = (r / NC) % NFACE;
+      // GL node of the neighbour's face opposite to f, tangential index t
+      const int fo = f ^ 1, dir = fo >> 1, side = fo & 1;
+      const int st = dir_stride(N, dir);
+      const int q = (t % st) + (side ? (N - 1) * st : 0) + (t / st) * st * N;
+      nv[s] = p.u[moff + (int64_t)nbi[s] * NC * NP + v * NP + q];
+    }
+  }
+  double g[PS][G2];
+#pragma unroll
+  for (int s = 0; s < PS; ++s) {
+    const int i = tid + s * NTH;
+    const int c = i / NP, q = i - (i / NP) * NP;
+    const double* gp = p.geo_cell + (cell0 + c) * (int64_t)(G2 * NP) + q;
+#pragma unroll
+    for (int e = 0; e < G2; ++e) g[s][e] = i < ncl * NP ? gp[e * NP] : 0.0;
+  }
+  double fg[FS][D + 2];
+#pragma unroll
+  for (int s = 0; s < FS; ++s) {
+    const int i = tid + s * NTH;
+    const int cf = i / NF, t = i - (i / NF) * NF;  // cf = c * NFACE + f
+    const double* fp = p.geo_face + (cell0 * NFACE + cf) * (int64_t)((D + 2) * NF) + t;
+#pragma unroll
+    for (int e = 0; e < D + 2; ++e) fg[s][e] = i < ncl * NFACE * NF ? fp[e * NF] : 1.0;
+  }
+  double eb[ES];
+#pragma unroll
+  for (int s = 0; s < ES; ++s) {
+    const int i = tid + s * NTH;
+    eb[s] = 0.0;
+    if constexpr (EPI == EPI_ADD)
+      if (i < nel) eb[s] = p.u_base[gofs + i];
+    if constexpr (EPI == EPI_LSRK)
+      if (i < nel && p.acoef != 0.0) eb[s] = p.du[gofs + i];
+  }
+#pragma unroll
+  for (int s = 0; s < ES; ++s) {
+    const int i = tid + s * NTH;
+    if (i < nel) sU[i] = (T)ev[s];
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = tid + s * NTH;
+    if (i < ncl * NFACE * NC * NF) sN[i] = (T)nv[s];
+  }
   __syncthreads();
-  // B: GL -> G of the cell tiles; tangential GL -> G of the neighbour traces
+
+  // ---- B: GL -> G of the cell tiles; tangential GL -> G of the neighbour traces
   {
     const T* S = tab + tab_S(N);
     tpass<D, 0, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
@@ -308,31 +339,89 @@ __global__ void __launch_bounds__(256) op_kernel(OpParams p) {
       __syncthreads();
     }
   }
-  // C: volume and face integrals, one direction at a time
-  op_direction<D, N, T, 0>(p, sU, sR, sN, cell0, ncl);
+  // ---- F: numerical fluxes at every face point, written over the neighbour traces
+  {
+    T lf0[N], lf1[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      lf0[j] = tab[tab_LF0(N) + j];
+      lf1[j] = tab[tab_LF1(N) + j];
+    }
+#pragma unroll
+    for (int s = 0; s < FS; ++s) {
+      const int i = tid + s * NTH;
+      if (i < ncl * NFACE * NF) {
+        const int cf = i / NF, t = i - (i / NF) * NF;
+        const int c = cf / NFACE, f = cf - c * NFACE;
+        const int dir = f >> 1, side = f & 1;
+        const int st = dir_stride(N, dir);
+        const T* su = sU + c * NC * NP + (t % st) + (t / st) * st * N;
+        double um[NC], up[NC];
+#pragma unroll
+        for (int v = 0; v < NC; ++v) {
+          T acc = 0;
+#pragma unroll
+          for (int j = 0; j < N; ++j) acc = fma(side ? lf1[j] : lf0[j], su[v * NP + j * st], acc);
+          um[v] = (double)acc;
+          up[v] = (double)sN[(cf * NC + v) * NF + t];
+        }
+        double area2 = 0.0, vnm = 0.0, vnp = 0.0;
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+          area2 = fma(fg[s][e], fg[s][e], area2);
+          vnm = fma(fg[s][e], um[e], vnm);
+          vnp = fma(fg[s][e], up[e], vnp);
+        }
+        const double area = sqrt(area2), inv_area = 1.0 / area;
+        vnm *= inv_area;
+        vnp *= inv_area;
+        double ps, vs;
+        if (p.central) {
+          ps = 0.5 * (um[D] + up[D]);
+          vs = 0.5 * (vnm + vnp);
+        } else {
+          const double Zm = fg[s][D], Zp = fg[s][D + 1];
+          const double inv = 1.0 / (Zm + Zp);
+          ps = (Zp * um[D] + Zm * up[D] + Zm * Zp * (vnm - vnp)) * inv;
+          vs = (Zm * vnm + Zp * vnp + um[D] - up[D]) * inv;
+        }
+#pragma unroll
+        for (int e = 0; e < D; ++e) sN[(cf * NC + e) * NF + t] = (T)(-fg[s][e] * ps);
+        sN[(cf * NC + D) * NF + t] = (T)(-area * vs);
+      }
+    }
+  }
   __syncthreads();
-  op_direction<D, N, T, 1>(p, sU, sR, sN, cell0, ncl);
+  // ---- C: per direction, pointwise fluxes then lines (derivative + lifts)
+  op_points<D, N, T, PS, 0>(g, sU, sT, ncl);
+  __syncthreads();
+  op_lines<D, N, T, 0>(tab, sT, sN, sR, ncl);
+  __syncthreads();
+  op_points<D, N, T, PS, 1>(g, sU, sT, ncl);
+  __syncthreads();
+  op_lines<D, N, T, 1>(tab, sT, sN, sR, ncl);
   __syncthreads();
   if constexpr (D == 3) {
-    op_direction<D, N, T, 2>(p, sU, sR, sN, cell0, ncl);
+    op_points<D, N, T, PS, 2>(g, sU, sT, ncl);
+    __syncthreads();
+    op_lines<D, N, T, 2>(tab, sT, sN, sR, ncl);
     __syncthreads();
   }
-  // D: inverse mass (pointwise, FP64 factors) then G -> GL
-  {
-    for (int i = threadIdx.x; i < ncl * NC * NP; i += blockDim.x) {
-      const int q = i % NP;
-      const int r = i / NP;
-      const int v = r % NC;
-      const int c = r / NC;
-      const double mu = p.geo_cell[(cell0 + c) * (int64_t)((D * D + 2) * NP) + (D * D + (v == D)) * NP + q];
-      sR[i] = (T)(mu * (double)sR[i]);
+  // ---- D: inverse mass (pointwise FP64 factors), G -> GL
+#pragma unroll
+  for (int s = 0; s < PS; ++s) {
+    const int i = tid + s * NTH;
+    if (i < ncl * NP) {
+      const int c = i / NP, q = i - c * NP;
+      T* r = sR + c * NC * NP + q;
+#pragma unroll
+      for (int v = 0; v < NC; ++v) r[v * NP] = (T)(g[s][D * D + (v == D)] * (double)r[v * NP]);
     }
-    __syncthreads();
-    tensor_apply_inplace<D, N, T>(sR, ncl * NC, tab + tab_Sinv(N));
   }
-  // E: epilogue (coalesced)
+  __syncthreads();
+  tensor_apply_inplace<D, N, T>(sR, ncl * NC, tab + tab_Sinv(N));
+  // ---- E: epilogue (coalesced, operands prefetched in A)
   {
-    const int64_t gofs = moff + cell0 * NC * NP;
     int scell = -1;
     if (p.src.cell) scell = p.src.cell[member];
     const bool has_src = scell >= cell0 && scell < cell0 + ncl;
@@ -342,8 +431,11 @@ __global__ void __launch_bounds__(256) op_kernel(OpParams p) {
       if constexpr (EPI == EPI_LSRK) sval = ricker_deriv(p.src.wave + 3 * member, tn + p.time.t_off, 0);
       if constexpr (EPI == EPI_ADD) sval = ricker_integral(p.src.wave + 3 * member, tn, tn + p.time.dt);
     }
-    for (int i = threadIdx.x; i < ncl * NC * NP; i += blockDim.x) {
-      double val = (double)sR[i];
+#pragma unroll
+    for (int s = 0; s < ES; ++s) {
+      const int i = tid + s * NTH;
+      if (i >= nel) continue;
+      const double val = (double)sR[i];
       const int64_t gi = gofs + i;
       if constexpr (EPI == EPI_STORE) {
         p.out[gi] = val;
@@ -355,11 +447,11 @@ __global__ void __launch_bounds__(256) op_kernel(OpParams p) {
           if (cell0 + c == scell && v == D) add = sval * p.src.gvec[(int64_t)member * NP + (i % NP)];
         }
         if constexpr (EPI == EPI_LSRK) {
-          const double d = (p.acoef == 0.0 ? 0.0 : p.acoef * p.du[gi]) + p.dt * (val + add);
+          const double d = p.acoef * eb[s] + p.dt * (val + add);
           p.du[gi] = d;
-          p.u_next[gi] = p.u[gi] + p.bcoef * d;
+          p.u_next[gi] = ev[s] + p.bcoef * d;
         } else {
-          p.u_next[gi] = p.u_base[gi] + val + add;
+          p.u_next[gi] = eb[s] + val + add;
         }
       }
     }
@@ -367,283 +459,327 @@ __global__ void __launch_bounds__(256) op_kernel(OpParams p) {
 }
 
 // ------------------------------------------------------------------------
-// ADER sweep 1: Taylor-Cauchy-Kowalevski sum in the collocated Gauss basis
-// with the degree reduction (Sec. 3.2, 3.3).  Buffers: three T tiles
-// (current derivative, next derivative, scratch) and the FP64 accumulator.
+// ADER sweep 1: the Taylor-Cauchy-Kowalevski sum in the collocated Gauss
+// basis with the degree reduction (Sec. 3.2, 3.3, Alg. 3).
+//
+// Per time derivative m at the level with NL points per direction: one line
+// phase computes the collocated derivative along all d directions of every
+// component (tiles Db[0..d-1]); one point phase applies the metric of the
+// level (prefetched into registers of the point's thread), scales by the
+// mass factors and adds the source term, giving ut^m.  Every second
+// derivative is projected to NL-2 points.  The Taylor sum is accumulated per
+// level in FP64 registers: I = A_0 + E(A_1 + E(A_2 + ...)), embedded level by
+// level at the end (E between consecutive Gauss sets is exact on the lower
+// degree).  LDS: the current derivative C and d derivative tiles.
 // ------------------------------------------------------------------------
 template <int D, int N, typename T>
 struct TckLayout {
   static constexpr int NC = D + 1, NP = ipow(N, D);
-  static constexpr int bytes_per_cell = 3 * NC * NP * (int)sizeof(T) + NC * NP * 8;
+  static constexpr int tiles = 1 + D;
+  static constexpr int bytes_per_cell =
+      (tiles * NC * NP * (int)sizeof(T) > NC * NP * 8 + NC * NP * (int)sizeof(T))
+          ? tiles * NC * NP * (int)sizeof(T)
+          : NC * NP * 8 + NC * NP * (int)sizeof(T);
 };
 
-template <int D, int N, typename T, bool REDUCE, int M, int NL, int CUR>
-struct TckStep {
-  __device__ static void run(const TckParams& p, T* const* bufs, double* sI, int64_t cell0, int ncl,
-                             int member) {
-    constexpr int NC = D + 1, NP = ipow(N, D), NPL = ipow(NL, D);
-    if constexpr (M > N || NL < 1) {
-      return;
-    } else {
-      constexpr int LVL = (N - NL) / 2;  // index of the Gauss set with NL points
-      constexpr int NXT = (CUR + 1) % 3, SCR = (CUR + 2) % 3;
-      const T* tab = static_cast<const T*>(p.tab);
-      T* cur = bufs[CUR];
-      T* w = bufs[NXT];
-      const double* G = p.geo_lev[LVL];
-      // w = -S_loc cur: accumulate over directions G_{ba} d_b p and sum_a G_{ba} d_b v_a
-      if constexpr (NL > 1) {
-        const T* Dl = tab + (LVL == 0 ? tab_D(N) : tab_level_D(N, LVL));
-        tck_deriv<0>(p, cur, w, G, Dl, cell0, ncl);
-        __syncthreads();
-        tck_deriv<1>(p, cur, w, G, Dl, cell0, ncl);
-        __syncthreads();
-        if constexpr (D == 3) {
-          tck_deriv<2>(p, cur, w, G, Dl, cell0, ncl);
-          __syncthreads();
-        }
-      }
-      // scale by -1/(w detJ rho), -rho c^2/(w detJ); source injection s^(M-1)(t) g
-      {
-        int scell = -1;
-        if (p.src.cell) scell = p.src.cell[member];
-        double sd = 0.0;
-        if (scell >= cell0 && scell < cell0 + ncl) sd = ricker_deriv(p.src.wave + 3 * member, p.time.tn(), M - 1);
-        for (int i = threadIdx.x; i < ncl * NC * NPL; i += blockDim.x) {
-          const int q = i % NPL;
-          const int r = i / NPL;
-          const int v = r % NC;
-          const int c = r / NC;
-          double val = 0.0;
-          if constexpr (NL > 1) {
-            const double mu = G[(cell0 + c) * (int64_t)((D * D + 2) * NPL) + (D * D + (v == D)) * NPL + q];
-            val = -mu * (double)w[(c * NC + v) * NP + q];
-          }
-          if (v == D && cell0 + c == scell) val += sd * p.src.glev[LVL][(int64_t)member * NPL + q];
-          w[(c * NC + v) * NP + q] = (T)val;
-        }
-        __syncthreads();
-      }
-      constexpr double coef = taylor_coef(M);
-      if constexpr (REDUCE && (M % 2 == 0)) {
-        constexpr int NR = NL - 2;
-        if constexpr (NR >= 1) {
-          // project w (NL^D) to NR^D, ping-pong w -> cur -> w (-> cur)
-          const T* Pm = tab + tab_level_P(N, LVL + 1);
-          project<NR>(w, cur, ncl, Pm);
-          constexpr int RES = (D == 3) ? CUR : NXT;
-          accumulate<NR, RES>(p, bufs, sI, ncl, coef * dtpow<M + 1>(p.dt), LVL + 1);
-          TckStep<D, N, T, REDUCE, M + 1, NR, RES>::run(p, bufs, sI, cell0, ncl, member);
-        }
-      } else {
-        accumulate<NL, NXT>(p, bufs, sI, ncl, coef * dtpow<M + 1>(p.dt), LVL);
-        TckStep<D, N, T, REDUCE, M + 1, NL, NXT>::run(p, bufs, sI, cell0, ncl, member);
-      }
-    }
-  }
+template <int D, int N, int CPW, bool REDUCE>
+struct TckRegs {
+  static constexpr int G2 = D * D + 2, NC = D + 1;
+  static constexpr int NLV = REDUCE ? (N + 1) / 2 : 1;
+  static constexpr int PS0 = cdiv(CPW * ipow(N, D), NTH);
+  double g[NLV][PS0][G2];   // metric and mass factors of every level
+  double A[NLV][PS0][NC];   // Taylor sums per level (FP64)
+};
 
-  static constexpr double taylor_coef(int m) {
+template <int D, int N, typename T, bool REDUCE, int CPW>
+struct Tck {
+  static constexpr int NC = D + 1, NP = ipow(N, D), G2 = D * D + 2;
+  using Regs = TckRegs<D, N, CPW, REDUCE>;
+
+  static constexpr double inv_fact(int m) {  // 1/(m+1)!
     double f = 1.0;
     for (int j = 2; j <= m + 1; ++j) f *= j;
     return 1.0 / f;
   }
-  template <int E>
-  __device__ static __forceinline__ double dtpow(double dt) {
-    double r = 1.0;
-#pragma unroll
-    for (int j = 0; j < E; ++j) r *= dt;
-    return r;
-  }
+  static constexpr int npl(int L) { return ipow(N - 2 * L, D); }
+  static constexpr int psl(int L) { return cdiv(CPW * npl(L), NTH); }
 
-  template <int DIR>
-  __device__ static __forceinline__ void tck_deriv(const TckParams& p, const T* cur, T* w, const double* G,
-                                                   const T* Dl, int64_t cell0, int ncl) {
-    constexpr int NC = D + 1, NP = ipow(N, D), NPL = ipow(NL, D);
-    using P = Pass<D, DIR, NL, NL, NL, NL, NL>;
-    const int total = ncl * P::NL;
-    for (int wi = threadIdx.x; wi < total; wi += blockDim.x) {
-      const int c = wi / P::NL;
-      const int L = wi - c * P::NL;
-      int bq, bq2;
-      P::base(L, bq, bq2);
-      T x[NC][NL];
+  // derivative of every component along every direction at level NL: C -> Db
+  template <int NL>
+  __device__ static __forceinline__ void lines(const T* C, T* const* Db, const T* __restrict__ Dl, int ncl) {
+    constexpr int NLL = ipow(NL, D - 1);
+    const int per_dir = ncl * NC * NLL;
+    for (int wi = threadIdx.x; wi < D * per_dir; wi += NTH) {
+      const int dir = wi / per_dir;
+      const int r = wi - dir * per_dir;
+      const int sl = r / NLL;
+      const int L = r - sl * NLL;
+      // line base and stride inside the NL^D tensor (x fastest)
+      const int st = dir == 0 ? 1 : (dir == 1 ? NL : NL * NL);
+      const int base = (L % st) + (L / st) * st * NL;
+      const T* src = C + sl * NP + base;
+      T* dst = Db[dir] + sl * NP + base;
+      T x[NL];
 #pragma unroll
-      for (int v = 0; v < NC; ++v)
-#pragma unroll
-        for (int j = 0; j < NL; ++j) x[v][j] = cur[(c * NC + v) * NP + bq + j * P::STEP_IN];
-      T dx[NC][NL];
-#pragma unroll
-      for (int v = 0; v < NC; ++v)
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-          T acc = Dl[i * NL] * x[v][0];
-#pragma unroll
-          for (int j = 1; j < NL; ++j) acc = fma(Dl[i * NL + j], x[v][j], acc);
-          dx[v][i] = acc;
-        }
-      const double* g = G + (cell0 + c) * (int64_t)((D * D + 2) * NPL) + bq;
-      T* wc = w + c * NC * NP + bq;
+      for (int j = 0; j < NL; ++j) x[j] = src[j * st];
 #pragma unroll
       for (int i = 0; i < NL; ++i) {
-        const int q = i * P::STEP_IN;
-        double dv = 0.0;
+        T acc = Dl[i * NL] * x[0];
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const double gba = g[(DIR * D + a) * NPL + q];
-          const T va = (T)(gba * (double)dx[D][i]);
-          dv = fma(gba, (double)dx[a][i], dv);
-          if constexpr (DIR == 0)
-            wc[a * NP + q] = va;
-          else
-            wc[a * NP + q] += va;
-        }
-        if constexpr (DIR == 0)
-          wc[D * NP + q] = (T)dv;
-        else
-          wc[D * NP + q] += (T)dv;
+        for (int j = 1; j < NL; ++j) acc = fma(Dl[i * NL + j], x[j], acc);
+        dst[i * st] = acc;
       }
     }
   }
 
-  // Projection P (NR x NL) along every direction: src (NL^D) -> ... ; the
-  // intermediate tensors use the NP-strided slices of the two buffers.
-  template <int NR>
-  __device__ static __forceinline__ void project(T* w, T* cur, int ncl, const T* Pm) {
-    constexpr int NC = D + 1, NP = ipow(N, D);
-    // slices are NP apart; Pass uses dense sub-tensors of its own extents
-    proj_pass<0, NL, NL, NL, NR>(w, cur, ncl, Pm);
-    __syncthreads();
-    proj_pass<1, NR, NL, NL, NR>(cur, w, ncl, Pm);
-    __syncthreads();
-    if constexpr (D == 3) {
-      proj_pass<2, NR, NR, NL, NR>(w, cur, ncl, Pm);
-      __syncthreads();
-    }
-    (void)NC;
-    (void)NP;
-  }
-
-  // One pass of a size-changing 1D matrix (MO x MI) along DIR between two
-  // buffers whose cell-component slices are NP apart.
-  template <int DIR, int E0, int E1, int E2, int MO>
-  __device__ static __forceinline__ void proj_pass(const T* in, T* out, int ncl, const T* Mx) {
-    constexpr int NC = D + 1, NP = ipow(N, D);
+  // size-changing pass (MO x MI matrix) along DIR between buffers with
+  // NP-strided cell-component slices
+  template <int DIR, int E0, int E1, int E2, int MO, typename TI, typename TO>
+  __device__ static __forceinline__ void pass(const TI* in, TO* out, int ncl, const T* __restrict__ Mx) {
     constexpr int MI = DIR == 0 ? E0 : (DIR == 1 ? E1 : E2);
     using P = Pass<D, DIR, MI, MO, E0, E1, E2>;
-    const int total = ncl * NC * P::NL;
-    for (int wi = threadIdx.x; wi < total; wi += blockDim.x) {
+    for (int wi = threadIdx.x; wi < ncl * NC * P::NL; wi += NTH) {
       const int s = wi / P::NL;
       const int L = wi - s * P::NL;
       int bi, bo;
       P::base(L, bi, bo);
-      const T* src = in + s * NP + bi;
-      T* dst = out + s * NP + bo;
+      const TI* src = in + s * NP + bi;
+      TO* dst = out + s * NP + bo;
       T x[MI];
 #pragma unroll
-      for (int j = 0; j < MI; ++j) x[j] = src[j * P::STEP_IN];
+      for (int j = 0; j < MI; ++j) x[j] = (T)src[j * P::STEP_IN];
 #pragma unroll
       for (int i = 0; i < MO; ++i) {
         T acc = Mx[i * MI] * x[0];
 #pragma unroll
         for (int j = 1; j < MI; ++j) acc = fma(Mx[i * MI + j], x[j], acc);
-        dst[i * P::STEP_OUT] = acc;
+        dst[i * P::STEP_OUT] = (TO)acc;
       }
     }
   }
 
-  // sI += scale * E (level NLm -> N) of bufs[RES]; uses the two other buffers
-  // as scratch for the size-changing passes.
-  template <int NLm, int RES>
-  __device__ static __forceinline__ void accumulate(const TckParams& p, T* const* bufs, double* sI, int ncl,
-                                                    double scale, int lvl) {
-    constexpr int NC = D + 1, NP = ipow(N, D);
-    const T* src = bufs[RES];
-    if constexpr (NLm == N) {
-      for (int i = threadIdx.x; i < ncl * NC * NP; i += blockDim.x) sI[i] += scale * (double)src[i];
+  // separable map of a level-NI tensor to a level-NO tensor with the same
+  // matrix in every direction, buf0 -> ... -> buf0 through buf1, buf2
+  template <int NI, int NO>
+  __device__ static __forceinline__ void tensor_map(T* b0, T* b1, T* b2, int ncl, const T* Mx) {
+    pass<0, NI, NI, NI, NO>(b0, b1, ncl, Mx);
+    __syncthreads();
+    if constexpr (D == 2) {
+      pass<1, NO, NI, 1, NO>(b1, b0, ncl, Mx);
       __syncthreads();
     } else {
-      const T* tab = static_cast<const T*>(p.tab);
-      const T* E = tab + tab_level_E(N, (N - NLm) / 2);
-      T* s1 = bufs[(RES + 1) % 3];
-      T* s2 = bufs[(RES + 2) % 3];
-      proj_pass<0, NLm, NLm, NLm, N>(src, s1, ncl, E);
+      pass<1, NO, NI, NI, NO>(b1, b2, ncl, Mx);
       __syncthreads();
-      if constexpr (D == 2) {
-        emb_last<1, N, NLm, 1>(s1, sI, ncl, E, scale);
-        __syncthreads();
-      } else {
-        proj_pass<1, N, NLm, NLm, N>(s1, s2, ncl, E);
-        __syncthreads();
-        emb_last<2, N, N, NLm>(s2, sI, ncl, E, scale);
-        __syncthreads();
-      }
+      pass<2, NO, NO, NI, NO>(b2, b0, ncl, Mx);
+      __syncthreads();
     }
-    (void)lvl;
   }
 
-  template <int DIR, int E0, int E1, int E2>
-  __device__ static __forceinline__ void emb_last(const T* in, double* sI, int ncl, const T* Mx, double scale) {
-    constexpr int NC = D + 1, NP = ipow(N, D);
-    constexpr int MI = DIR == 0 ? E0 : (DIR == 1 ? E1 : E2);
-    using P = Pass<D, DIR, MI, N, E0, E1, E2>;
-    const int total = ncl * NC * P::NL;
-    for (int wi = threadIdx.x; wi < total; wi += blockDim.x) {
-      const int s = wi / P::NL;
-      const int L = wi - s * P::NL;
-      int bi, bo;
-      P::base(L, bi, bo);
-      const T* src = in + s * NP + bi;
-      double* dst = sI + s * NP + bo;
-      T x[MI];
+  // time derivative M at level index L (NL = N - 2L points), current in C
+  template <int M, int L>
+  __device__ static __forceinline__ void step(const TckParams& p, T* C, T* const* Db, Regs& R, int64_t cell0,
+                                              int ncl, int member) {
+    constexpr int NL = N - 2 * L;
+    if constexpr (M <= N && NL >= 1) {
+      constexpr int NPL = ipow(NL, D);
+      constexpr int PSL = cdiv(CPW * NPL, NTH);
+      constexpr bool PROJECT = REDUCE && (M % 2 == 0);
+      const T* tab = static_cast<const T*>(p.tab);
+      double dtp = 1.0;
 #pragma unroll
-      for (int j = 0; j < MI; ++j) x[j] = src[j * P::STEP_IN];
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        T acc = Mx[i * MI] * x[0];
-#pragma unroll
-        for (int j = 1; j < MI; ++j) acc = fma(Mx[i * MI + j], x[j], acc);
-        dst[i * P::STEP_OUT] += scale * (double)acc;
+      for (int j = 0; j <= M; ++j) dtp *= p.dt;
+      const double coef = inv_fact(M) * dtp;
+      if constexpr (NL > 1) {
+        lines<NL>(C, Db, tab + (L == 0 ? tab_D(N) : tab_level_D(N, L)), ncl);
+        __syncthreads();
       }
+      // point phase: ut^M = -mu * metric(derivatives) + s^(M-1)(t) g, into C
+      int scell = -1;
+      if (p.src.cell) scell = p.src.cell[member];
+      double sd = 0.0;
+      if (scell >= cell0 && scell < cell0 + ncl) sd = ricker_deriv(p.src.wave + 3 * member, p.time.tn(), M - 1);
+#pragma unroll
+      for (int s = 0; s < PSL; ++s) {
+        const int i = threadIdx.x + s * NTH;
+        if (i < ncl * NPL) {
+          const int c = i / NPL, q = i - c * NPL;
+          double w[NC];
+#pragma unroll
+          for (int v = 0; v < NC; ++v) w[v] = 0.0;
+          if constexpr (NL > 1) {
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+              const T* t = Db[b] + c * NC * NP + q;
+              const double dp = (double)t[D * NP];
+#pragma unroll
+              for (int a = 0; a < D; ++a) {
+                const double gba = R.g[L][s][b * D + a];
+                w[a] = fma(gba, dp, w[a]);
+                w[D] = fma(gba, (double)t[a * NP], w[D]);
+              }
+            }
+#pragma unroll
+            for (int v = 0; v < NC; ++v) w[v] *= -R.g[L][s][D * D + (v == D)];
+          }
+          if (cell0 + c == scell) w[D] += sd * p.src.glev[L][(int64_t)member * NPL + q];
+#pragma unroll
+          for (int v = 0; v < NC; ++v) {
+            const T wt = (T)w[v];
+            C[(c * NC + v) * NP + q] = wt;
+            if constexpr (!PROJECT) R.A[L][s][v] += coef * (double)wt;
+          }
+        }
+      }
+      __syncthreads();
+      if constexpr (PROJECT) {
+        constexpr int NR = NL - 2;
+        if constexpr (NR >= 1) {
+          tensor_map<NL, NR>(C, Db[0], Db[1], ncl, tab + tab_level_P(N, L + 1));
+          constexpr int PSR = cdiv(CPW * ipow(NR, D), NTH);
+#pragma unroll
+          for (int s = 0; s < PSR; ++s) {
+            const int i = threadIdx.x + s * NTH;
+            if (i < ncl * ipow(NR, D)) {
+              const int c = i / ipow(NR, D), q = i - c * ipow(NR, D);
+#pragma unroll
+              for (int v = 0; v < NC; ++v) R.A[L + 1][s][v] += coef * (double)C[(c * NC + v) * NP + q];
+            }
+          }
+          step<M + 1, L + 1>(p, C, Db, R, cell0, ncl, member);
+        }
+      } else {
+        step<M + 1, L>(p, C, Db, R, cell0, ncl, member);
+      }
+    }
+  }
+
+  // I_G = A_0 + E(A_1 + E(A_2 + ...)): from the coarsest level L upwards,
+  // leaving level L-1's partial sum in tile C
+  template <int L>
+  __device__ static __forceinline__ void collapse(const TckParams& p, T* C, T* const* Db, Regs& R, int ncl) {
+    constexpr int NLV = Regs::NLV;
+    if constexpr (L >= 1 && L < NLV) {
+      constexpr int NPL = npl(L);
+      // tile <- A_L (+ the embedded sum of the coarser levels already in C)
+#pragma unroll
+      for (int s = 0; s < psl(L); ++s) {
+        const int i = threadIdx.x + s * NTH;
+        if (i < ncl * NPL) {
+          const int c = i / NPL, q = i - c * NPL;
+#pragma unroll
+          for (int v = 0; v < NC; ++v) {
+            T* x = C + (c * NC + v) * NP + q;
+            const double prev = (L == NLV - 1) ? 0.0 : (double)*x;
+            *x = (T)(prev + R.A[L][s][v]);
+          }
+        }
+      }
+      __syncthreads();
+      const T* tab = static_cast<const T*>(p.tab);
+      tensor_map<N - 2 * L, N - 2 * (L - 1)>(C, Db[0], Db[1], ncl, tab + tab_level_E(N, L));
+      collapse<L - 1>(p, C, Db, R, ncl);
     }
   }
 };
 
-template <int D, int N, typename T, bool REDUCE>
-__global__ void __launch_bounds__(256) tck_kernel(TckParams p) {
+template <int D, int N, int CPW, bool REDUCE, int L>
+__device__ __forceinline__ void tck_load_levels(TckRegs<D, N, CPW, REDUCE>& R, const TckParams& p, int64_t cell0,
+                                                int ncl) {
+  constexpr int NLV = TckRegs<D, N, CPW, REDUCE>::NLV;
+  if constexpr (L < NLV) {
+    constexpr int G2 = D * D + 2;
+    constexpr int NPL = ipow(N - 2 * L, D);
+    constexpr int PSL = cdiv(CPW * NPL, NTH);
+    const double* base = p.geo_lev[L];
+#pragma unroll
+    for (int s = 0; s < PSL; ++s) {
+      const int i = threadIdx.x + s * NTH;
+      const int c = i / NPL, q = i - (i / NPL) * NPL;
+      const double* gp = base + (cell0 + c) * (int64_t)(G2 * NPL) + q;
+#pragma unroll
+      for (int e = 0; e < G2; ++e) R.g[L][s][e] = i < ncl * NPL ? gp[e * NPL] : 0.0;
+#pragma unroll
+      for (int v = 0; v < D + 1; ++v) R.A[L][s][v] = 0.0;
+    }
+    tck_load_levels<D, N, CPW, REDUCE, L + 1>(R, p, cell0, ncl);
+  }
+}
+
+template <int D, int N, typename T, bool REDUCE, int CPW>
+__global__ void __launch_bounds__(NTH) tck_kernel(TckParams p) {
+  using K = Tck<D, N, T, REDUCE, CPW>;
   constexpr int NC = D + 1, NP = ipow(N, D);
+  constexpr int ES = cdiv(CPW * NC * NP, NTH);
+  constexpr int PS0 = cdiv(CPW * NP, NTH);
   extern __shared__ __align__(16) unsigned char smem[];
-  double* sI = reinterpret_cast<double*>(smem);
-  T* b0 = reinterpret_cast<T*>(sI + p.cpw * NC * NP);
-  T* bufs[3] = {b0, b0 + p.cpw * NC * NP, b0 + 2 * p.cpw * NC * NP};
+  T* C = reinterpret_cast<T*>(smem);
+  T* Db[3] = {C + CPW * NC * NP, C + 2 * CPW * NC * NP, C + 3 * CPW * NC * NP};
   const T* tab = static_cast<const T*>(p.tab);
 
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int member = logical % p.B;
   const int group = logical / p.B;
-  const int64_t cell0 = (int64_t)group * p.cpw;
-  const int ncl = (int)min((int64_t)p.cpw, p.nc - cell0);
+  const int64_t cell0 = (int64_t)group * CPW;
+  const int ncl = (int)min((int64_t)CPW, p.nc - cell0);
   const int64_t gofs = (int64_t)member * p.nc * NC * NP + cell0 * NC * NP;
+  const int nel = ncl * NC * NP;
 
-  for (int i = threadIdx.x; i < ncl * NC * NP; i += blockDim.x) bufs[0][i] = (T)p.u[gofs + i];
+  double ev[ES];
+#pragma unroll
+  for (int s = 0; s < ES; ++s) {
+    const int i = threadIdx.x + s * NTH;
+    ev[s] = i < nel ? p.u[gofs + i] : 0.0;
+  }
+  TckRegs<D, N, CPW, REDUCE> R;
+  tck_load_levels<D, N, CPW, REDUCE, 0>(R, p, cell0, ncl);
+#pragma unroll
+  for (int s = 0; s < ES; ++s) {
+    const int i = threadIdx.x + s * NTH;
+    if (i < nel) C[i] = (T)ev[s];
+  }
   __syncthreads();
-  tensor_apply_inplace<D, N, T>(bufs[0], ncl * NC, tab + tab_S(N));
-  for (int i = threadIdx.x; i < ncl * NC * NP; i += blockDim.x) sI[i] = p.dt * (double)bufs[0][i];
+  tensor_apply_inplace<D, N, T>(C, ncl * NC, tab + tab_S(N));
+  // m = 0 term: dt u_G
+#pragma unroll
+  for (int s = 0; s < PS0; ++s) {
+    const int i = threadIdx.x + s * NTH;
+    if (i < ncl * NP) {
+      const int c = i / NP, q = i - c * NP;
+#pragma unroll
+      for (int v = 0; v < NC; ++v) R.A[0][s][v] = p.dt * (double)C[(c * NC + v) * NP + q];
+    }
+  }
+  K::template step<1, 0>(p, C, Db, R, cell0, ncl, member);
+  __syncthreads();  // the last accumulation may still read C
+  // collapse the coarser levels into level 0, add A_0 in FP64, then G -> GL in FP64
+  K::template collapse<TckRegs<D, N, CPW, REDUCE>::NLV - 1>(p, C, Db, R, ncl);
+  double* sI = reinterpret_cast<double*>(Db[0]);  // FP64 tile over the derivative tiles
+#pragma unroll
+  for (int s = 0; s < PS0; ++s) {
+    const int i = threadIdx.x + s * NTH;
+    if (i < ncl * NP) {
+      const int c = i / NP, q = i - c * NP;
+#pragma unroll
+      for (int v = 0; v < NC; ++v) {
+        const double lower = TckRegs<D, N, CPW, REDUCE>::NLV > 1 ? (double)C[(c * NC + v) * NP + q] : 0.0;
+        sI[(c * NC + v) * NP + q] = R.A[0][s][v] + lower;
+      }
+    }
+  }
   __syncthreads();
-  TckStep<D, N, T, REDUCE, 1, N, 0>::run(p, bufs, sI, cell0, ncl, member);
-  // G -> GL of the FP64 accumulator, then store
   tensor_apply_inplace<D, N, double>(sI, ncl * NC, p.tab64 + tab_Sinv(N));
-  for (int i = threadIdx.x; i < ncl * NC * NP; i += blockDim.x) p.I[gofs + i] = sI[i];
+  for (int i = threadIdx.x; i < nel; i += NTH) p.I[gofs + i] = sI[i];
 }
 
 // ------------------------------------------------------------------------
 // Energy sum_q |v|^2 / mu_v + p^2 / mu_p at the Gauss points (per group).
 // ------------------------------------------------------------------------
 template <int D, int N, typename T>
-__global__ void __launch_bounds__(256) energy_kernel(EnergyParams p) {
+__global__ void __launch_bounds__(NTH) energy_kernel(EnergyParams p) {
   constexpr int NC = D + 1, NP = ipow(N, D);
   extern __shared__ __align__(16) unsigned char smem[];
   T* sU = reinterpret_cast<T*>(smem);
-  __shared__ double red[256];
+  __shared__ double red[NTH];
   const T* tab = static_cast<const T*>(p.tab);
   const int logical = blockIdx.x;
   const int member = logical % p.B;
@@ -651,11 +787,11 @@ __global__ void __launch_bounds__(256) energy_kernel(EnergyParams p) {
   const int64_t cell0 = (int64_t)group * p.cpw;
   const int ncl = (int)min((int64_t)p.cpw, p.nc - cell0);
   const int64_t gofs = (int64_t)member * p.nc * NC * NP + cell0 * NC * NP;
-  for (int i = threadIdx.x; i < ncl * NC * NP; i += blockDim.x) sU[i] = (T)p.u[gofs + i];
+  for (int i = threadIdx.x; i < ncl * NC * NP; i += NTH) sU[i] = (T)p.u[gofs + i];
   __syncthreads();
   tensor_apply_inplace<D, N, T>(sU, ncl * NC, tab + tab_S(N));
   double acc = 0.0;
-  for (int i = threadIdx.x; i < ncl * NC * NP; i += blockDim.x) {
+  for (int i = threadIdx.x; i < ncl * NC * NP; i += NTH) {
     const int q = i % NP;
     const int r = i / NP;
     const int v = r % NC;
@@ -666,7 +802,7 @@ __global__ void __launch_bounds__(256) energy_kernel(EnergyParams p) {
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+  for (int s = NTH / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }

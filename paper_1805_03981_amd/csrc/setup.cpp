@@ -131,8 +131,8 @@ std::vector<double> build_tables(int n) {
     for (int a = 0; a < m; ++a)
       for (int b = 0; b < mp; ++b)
         t[tab_level_P(n, l) + a * mp + b] = (double)(rp.w[b] * lagrange_value(rm.x, a, rp.x[b]) / rm.w[a]);
-    for (int q = 0; q < n; ++q)
-      for (int a = 0; a < m; ++a) t[tab_level_E(n, l) + q * m + a] = (double)lagrange_value(rm.x, a, g.x[q]);
+    for (int q = 0; q < mp; ++q)
+      for (int a = 0; a < m; ++a) t[tab_level_E(n, l) + q * m + a] = (double)lagrange_value(rm.x, a, rp.x[q]);
     for (int q = 0; q < m; ++q)
       for (int j = 0; j < n; ++j) t[tab_level_F(n, l) + q * n + j] = (double)lagrange_value(g.x, j, rm.x[q]);
   }

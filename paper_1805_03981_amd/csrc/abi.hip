@@ -18,6 +18,10 @@ const Launchers* launchers_d2_f64(int n);
 const Launchers* launchers_d2_f32(int n);
 const Launchers* launchers_d3_f64(int n);
 const Launchers* launchers_d3_f32(int n);
+hipError_t launchers_d2_f64_upload(const double*, const float*);
+hipError_t launchers_d2_f32_upload(const double*, const float*);
+hipError_t launchers_d3_f64_upload(const double*, const float*);
+hipError_t launchers_d3_f32_upload(const double*, const float*);
 
 const Launchers* launchers(int dim, int n, int precision) {
   if (dim == 2) return precision ? launchers_d2_f32(n) : launchers_d2_f64(n);
@@ -83,8 +87,24 @@ static LaunchShape default_shape(const Launchers* L, int lds_per_cell) {
   return s;
 }
 
-static void* tab_ptr(const dgw_mesh* m) {
-  return m->precision ? static_cast<void*>(m->d_tab32) : static_cast<void*>(m->d_tab64);
+// The 1D tables of every degree go to each kernel unit's constant memory,
+// once per device.
+static dgw_status ensure_tables(int device) {
+  static std::mutex mtx;
+  static std::vector<int> done;
+  std::lock_guard<std::mutex> lk(mtx);
+  if (std::find(done.begin(), done.end(), device) != done.end()) return DGW_OK;
+  std::vector<double> t64(kTabTotal, 0.0);
+  for (int n = kMinN; n <= kMaxN; ++n) {
+    const std::vector<double> t = build_tables(n);
+    std::copy(t.begin(), t.end(), t64.begin() + tab_base(n));
+  }
+  std::vector<float> t32(t64.begin(), t64.end());
+  const TableUpload up[4] = {launchers_d2_f64_upload, launchers_d2_f32_upload, launchers_d3_f64_upload,
+                             launchers_d3_f32_upload};
+  for (auto f : up) DGW_HIP(f(t64.data(), t32.data()));
+  done.push_back(device);
+  return DGW_OK;
 }
 
 static dgw_status check_mesh(const dgw_mesh* m) {
@@ -113,7 +133,6 @@ static OpParams op_params(const dgw_mesh* m, int B, const dgw_sources* src) {
   p.geo_cell = m->d_cell;
   p.geo_face = m->d_face;
   p.nb = m->d_nb;
-  p.tab = tab_ptr(m);
   p.nc = m->hs.nc;
   p.cpw = m->L->cpw[m->op_shape.sel];
   p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
@@ -128,8 +147,6 @@ static TckParams tck_params(const dgw_mesh* m, int B, const dgw_sources* src) {
   std::memset(&p, 0, sizeof(p));
   p.geo_lev[0] = m->d_cell;
   for (int l = 1; l < kMaxLevels; ++l) p.geo_lev[l] = m->d_level[l];
-  p.tab = tab_ptr(m);
-  p.tab64 = m->d_tab64;
   p.nc = m->hs.nc;
   p.cpw = m->L->cpw[m->tck_shape.sel];
   p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
@@ -193,7 +210,6 @@ static dgw_status energy_impl(dgw_mesh* m, const double* u, int B, double* host_
   std::memset(&p, 0, sizeof(p));
   p.u = u;
   p.geo_cell = m->d_cell;
-  p.tab = tab_ptr(m);
   p.partial = m->d_partial;
   p.nc = m->hs.nc;
   p.cpw = std::max(1, std::min(16, 16384 / m->L->energy_lds_per_cell));
@@ -314,10 +330,7 @@ static dgw_status upload(dgw_mesh* m) {
   if ((st = alloc_copy(m->d_nb, hs.nb.data(), hs.nb.size()))) return st;
   for (int l = 1; l < m->nlev; ++l)
     if ((st = alloc_copy(m->d_level[l], hs.level[l].data(), hs.level[l].size()))) return st;
-  const std::vector<double> t64 = build_tables(hs.n);
-  std::vector<float> t32(t64.begin(), t64.end());
-  if ((st = alloc_copy(m->d_tab64, t64.data(), t64.size()))) return st;
-  if ((st = alloc_copy(m->d_tab32, t32.data(), t32.size()))) return st;
+  if ((st = ensure_tables(m->device))) return st;
   const int cpw_e = std::max(1, std::min(16, 16384 / m->L->energy_lds_per_cell));
   const size_t groups_e = (size_t)((hs.nc + cpw_e - 1) / cpw_e);
   std::vector<double> zeros((size_t)m->max_batch * groups_e, 0.0);
@@ -333,8 +346,6 @@ static void release(dgw_mesh* m) {
     (void)hipFree(m->d_face);
     (void)hipFree(m->d_nb);
     for (auto* p : m->d_level) (void)hipFree(p);
-    (void)hipFree(m->d_tab64);
-    (void)hipFree(m->d_tab32);
     (void)hipFree(m->d_partial);
   }
   delete m;
@@ -879,41 +890,64 @@ dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, d
   hipGraph_t graph = nullptr;
   long long* d_ctr = nullptr;
   if (desc->use_graph && nsteps >= 2) {
-    // two steps per graph keep the ping-pong buffers in place between replays
-    DGW_HIP(hipMalloc(&d_ctr, sizeof(long long)));
+    // Capture needs a stream of our own (the legacy default stream cannot be
+    // captured); two steps per graph keep the ping-pong buffers in place
+    // between replays; the device step counter advances inside the graph.
+    hipStream_t gs = nullptr;
+    DGW_HIP(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+    hipStream_t caller = s;
+    s = gs;
+    auto cleanup = [&]() {
+      if (gexec) (void)hipGraphExecDestroy(gexec);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (d_ctr) (void)hipFree(d_ctr);
+      (void)hipStreamSynchronize(gs);
+      (void)hipStreamDestroy(gs);
+    };
+    if (hipMalloc(&d_ctr, sizeof(long long)) != hipSuccess) {
+      cleanup();
+      return fail(DGW_ENOMEM, "graph step counter");
+    }
     const long long zero = 0;
-    DGW_HIP(hipMemcpyAsync(d_ctr, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
-    DGW_HIP(hipStreamSynchronize(s));
+    if (hipMemcpyAsync(d_ctr, &zero, sizeof(zero), hipMemcpyHostToDevice, gs) != hipSuccess ||
+        hipStreamSynchronize(gs) != hipSuccess) {
+      cleanup();
+      return fail(DGW_EDEVICE, "graph step counter init");
+    }
     double* c0 = cur;
     double* o0 = oth;
-    DGW_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    if (hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      cleanup();
+      return fail(DGW_EDEVICE, "hipStreamBeginCapture failed");
+    }
     dgw_status cst = one(0, d_ctr, 0);
     if (!cst) cst = one(1, d_ctr, 1);
-    hipLaunchKernelGGL(advance_counter, dim3(1), dim3(64), 0, s, d_ctr, 2);
-    const hipError_t ce = hipStreamEndCapture(s, &graph);
-    if (cst || ce != hipSuccess) {
-      (void)hipFree(d_ctr);
-      if (graph) (void)hipGraphDestroy(graph);
+    hipLaunchKernelGGL(advance_counter, dim3(1), dim3(64), 0, gs, d_ctr, 2);
+    const hipError_t ce = hipStreamEndCapture(gs, &graph);
+    if (cst || ce != hipSuccess || hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      cleanup();
       return cst ? cst : fail(DGW_EDEVICE, "graph capture failed");
     }
-    DGW_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
     cur = c0;  // the capture swapped the pointers twice: back where they were
     oth = o0;
     const int64_t pairs = nsteps / 2;
-    for (int64_t r = 0; r < pairs; ++r) {
-      DGW_HIP(hipGraphLaunch(gexec, s));
+    for (int64_t r = 0; r < pairs && !st; ++r) {
+      if (hipGraphLaunch(gexec, gs) != hipSuccess) {
+        st = fail(DGW_EDEVICE, "hipGraphLaunch failed");
+        break;
+      }
       k += 2;
       if (desc->watchdog_every > 0 && (k % desc->watchdog_every) < 2) {
-        if ((st = energy_impl(m, cur, B, en.data(), s))) break;
-        if (!(en[0] <= growth * e0)) {
+        if ((st = energy_impl(m, cur, B, en.data(), gs))) break;
+        if (!(en[0] <= growth * e0))
           st = fail(DGW_EUNSTABLE, "energy grew beyond the watchdog limit (time step too large?)");
-          break;
-        }
       }
     }
-    (void)hipGraphExecDestroy(gexec);
-    (void)hipGraphDestroy(graph);
-    (void)hipFree(d_ctr);
+    cleanup();
+    s = caller;
+    gexec = nullptr;
+    graph = nullptr;
+    d_ctr = nullptr;
     if (st) return st;
   }
   for (; k < nsteps; ++k) {

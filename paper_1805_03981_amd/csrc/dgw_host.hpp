@@ -71,8 +71,6 @@ struct dgw_mesh {
   double* d_face = nullptr;
   double* d_level[dgw::kMaxLevels] = {};
   int32_t* d_nb = nullptr;
-  double* d_tab64 = nullptr;
-  float* d_tab32 = nullptr;
   double* d_partial = nullptr;  // energy partial sums [max_batch][groups]
   int64_t device_bytes = 0;
   dgw::LaunchShape op_shape, tck_shape;

@@ -29,7 +29,6 @@ struct OpParams {
   const double* geo_cell; // [nc][d*d+2][np]: w detJ J^-1 (b*d+a), mu_v, mu_p
   const double* geo_face; // [nc][2d][d+2][n^(d-1)]: a (d), Z-, Z+
   const int* nb;          // [nc][2d]
-  const void* tab;        // 1D tables in the arithmetic precision
   int64_t nc;
   int cpw;                // cells per workgroup
   int groups;             // ceil(nc / cpw)
@@ -44,8 +43,6 @@ struct TckParams {
   const double* u;        // [B][nc][d+1][np] GL
   double* I;              // [B][nc][d+1][np] GL, time-integrated Taylor sum
   const double* geo_lev[kMaxLevels];  // level 0 = geo_cell; [nc][d*d+2][m_l^d]
-  const void* tab;
-  const double* tab64;    // FP64 tables (the accumulator's back-transform)
   int64_t nc;
   int cpw, groups, B;
   double dt;
@@ -56,7 +53,6 @@ struct TckParams {
 struct EnergyParams {
   const double* u;
   const double* geo_cell;
-  const void* tab;
   double* partial;        // [B][groups]
   int64_t nc;
   int cpw, groups, B;
@@ -112,5 +108,17 @@ __host__ __device__ constexpr int tab_level_F(int n, int l) {
 }
 __host__ __device__ constexpr int num_levels(int n) { return (n + 1) / 2; }  // n, n-2, ... >= 1
 __host__ __device__ constexpr int tab_size(int n) { return tab_level(n, num_levels(n)); }
+// All degrees share one constant-memory table: n = 2..9 back to back.
+constexpr int kMinN = 2, kMaxN = 9;
+__host__ __device__ constexpr int tab_base(int n) {
+  int off = 0;
+  for (int m = kMinN; m < n; ++m) off += tab_size(m);
+  return off;
+}
+constexpr int kTabTotal = tab_base(kMaxN + 1);
+
+// Uploads the 1D tables of every degree to the constant memory of the
+// current device, for the kernels of one (dim, precision) unit.
+using TableUpload = hipError_t (*)(const double* t64, const float* t32);
 
 }  // namespace dgw

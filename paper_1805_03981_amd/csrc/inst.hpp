@@ -27,7 +27,7 @@ template <int D, int N, typename T, bool R, int SEL>
 hipError_t launch_tck(const TckParams& p, hipStream_t s) {
   constexpr int CPW = cells_per_group(D, N, SEL);
   if (p.cpw != CPW) return hipErrorInvalidValue;
-  const size_t lds = (size_t)CPW * TckLayout<D, N, T>::bytes_per_cell;
+  const size_t lds = (size_t)CPW * TckLayout<D, N, T>::bytes_per_cell(R);
   hipError_t e = ensure_lds(tck_kernel<D, N, T, R, CPW>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((tck_kernel<D, N, T, R, CPW>), dim3(p.groups * p.B), dim3(NTH), lds, s, p);
@@ -54,7 +54,7 @@ const Launchers* make_launchers() {
       launch_energy<D, N, T>,
       {cells_per_group(D, N, 0), cells_per_group(D, N, 1)},
       (int)(OpLayout<D, N, T>::per_cell * sizeof(T)),
-      TckLayout<D, N, T>::bytes_per_cell,
+      TckLayout<D, N, T>::bytes_per_cell(true),
       (int)((D + 1) * ipow(N, D) * sizeof(T))};
   return &L;
 }
@@ -63,6 +63,13 @@ const Launchers* make_launchers() {
 
 #define DGW_DEFINE_INST(NAME, DIM, TYPE)                          \
   namespace dgw {                                                 \
+  hipError_t NAME##_upload(const double* t64, const float* t32) { \
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_tab64), t64,    \
+                                     kTabTotal * sizeof(double)); \
+    if (e != hipSuccess) return e;                                \
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_tab32), t32,            \
+                             kTabTotal * sizeof(float));          \
+  }                                                               \
   const Launchers* NAME(int n) {                                  \
     switch (n) {                                                  \
       case 2: return make_launchers<DIM, 2, TYPE>();              \

@@ -30,6 +30,22 @@ __host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 // Every kernel runs 256 threads (four wavefronts) per workgroup.
 constexpr int NTH = 256;
 
+// 1D tables of every degree (layout tab_base / tab_*) in constant memory:
+// uniform reads of the matrix entries go through the scalar cache.  Each
+// translation unit has its own copy, filled by its upload function.
+static __constant__ double c_tab64[kTabTotal];
+static __constant__ float c_tab32[kTabTotal];
+template <typename T>
+__device__ __forceinline__ const T* ctab(int n);
+template <>
+__device__ __forceinline__ const double* ctab<double>(int n) {
+  return c_tab64 + tab_base(n);
+}
+template <>
+__device__ __forceinline__ const float* ctab<float>(int n) {
+  return c_tab32 + tab_base(n);
+}
+
 // Cells per workgroup of the two compiled launch shapes: sel 0 gives about
 // one cell point per thread, sel 1 twice as many cells.
 __host__ __device__ constexpr int cells_per_group(int d, int n, int sel) {
@@ -238,7 +254,7 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
   T* sR = sU + CPW * NC * NP;
   T* sT = sR + CPW * NC * NP;
   T* sN = sT + CPW * NC * NP;
-  const T* tab = static_cast<const T*>(p.tab);
+  const T* tab = ctab<T>(N);
   const int tid = threadIdx.x;
 
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
@@ -474,12 +490,22 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
 // ------------------------------------------------------------------------
 template <int D, int N, typename T>
 struct TckLayout {
-  static constexpr int NC = D + 1, NP = ipow(N, D);
-  static constexpr int tiles = 1 + D;
-  static constexpr int bytes_per_cell =
-      (tiles * NC * NP * (int)sizeof(T) > NC * NP * 8 + NC * NP * (int)sizeof(T))
-          ? tiles * NC * NP * (int)sizeof(T)
-          : NC * NP * 8 + NC * NP * (int)sizeof(T);
+  static constexpr int NC = D + 1, NP = ipow(N, D), G2 = D * D + 2;
+  static constexpr int tiles = 1 + D;  // C and the d derivative tiles (an FP64 tile fits in Db)
+  // metric of the reduced Gauss sets (levels >= 1), FP64, per cell
+  static constexpr int lev_elems() {
+    int e = 0;
+    for (int m = N - 2; m >= 1; m -= 2) e += G2 * ipow(m, D);
+    return e;
+  }
+  static constexpr int lev_offset(int L) {  // start of level L >= 1 (elements per cell)
+    int e = 0;
+    for (int l = 1; l < L; ++l) e += G2 * ipow(N - 2 * l, D);
+    return e;
+  }
+  static constexpr int bytes_per_cell(bool reduce) {
+    return tiles * NC * NP * (int)sizeof(T) + (reduce ? 8 * lev_elems() : 0);
+  }
 };
 
 template <int D, int N, int CPW, bool REDUCE>
@@ -487,8 +513,9 @@ struct TckRegs {
   static constexpr int G2 = D * D + 2, NC = D + 1;
   static constexpr int NLV = REDUCE ? (N + 1) / 2 : 1;
   static constexpr int PS0 = cdiv(CPW * ipow(N, D), NTH);
-  double g[NLV][PS0][G2];   // metric and mass factors of every level
+  double g[PS0][G2];        // metric and mass factors of level 0
   double A[NLV][PS0][NC];   // Taylor sums per level (FP64)
+  const double* glev;       // LDS: metric of the levels >= 1, [level][cell][G2][m^D]
 };
 
 template <int D, int N, typename T, bool REDUCE, int CPW>
@@ -502,12 +529,23 @@ struct Tck {
     return 1.0 / f;
   }
   static constexpr int npl(int L) { return ipow(N - 2 * L, D); }
+
+  // metric entry e at point q of cell c on level L (registers for level 0)
+  template <int L, int NPL>
+  __device__ static __forceinline__ double geo(const Regs& R, int s, int c, int q, int e) {
+    if constexpr (L == 0)
+      return R.g[s][e];
+    else
+      return R.glev[CPW * TckLayout<D, N, T>::lev_offset(L) + (c * G2 + e) * NPL + q];
+  }
   static constexpr int psl(int L) { return cdiv(CPW * npl(L), NTH); }
 
   // derivative of every component along every direction at level NL: C -> Db
+  // (the d derivative tiles are contiguous, TILE elements apart)
   template <int NL>
-  __device__ static __forceinline__ void lines(const T* C, T* const* Db, const T* __restrict__ Dl, int ncl) {
+  __device__ static __forceinline__ void lines(const T* C, T* Db0, const T* __restrict__ Dl, int ncl) {
     constexpr int NLL = ipow(NL, D - 1);
+    constexpr int TILE = CPW * NC * NP;
     const int per_dir = ncl * NC * NLL;
     for (int wi = threadIdx.x; wi < D * per_dir; wi += NTH) {
       const int dir = wi / per_dir;
@@ -518,7 +556,7 @@ struct Tck {
       const int st = dir == 0 ? 1 : (dir == 1 ? NL : NL * NL);
       const int base = (L % st) + (L / st) * st * NL;
       const T* src = C + sl * NP + base;
-      T* dst = Db[dir] + sl * NP + base;
+      T* dst = Db0 + dir * TILE + sl * NP + base;
       T x[NL];
 #pragma unroll
       for (int j = 0; j < NL; ++j) x[j] = src[j * st];
@@ -584,13 +622,13 @@ struct Tck {
       constexpr int NPL = ipow(NL, D);
       constexpr int PSL = cdiv(CPW * NPL, NTH);
       constexpr bool PROJECT = REDUCE && (M % 2 == 0);
-      const T* tab = static_cast<const T*>(p.tab);
+      const T* tab = ctab<T>(N);
       double dtp = 1.0;
 #pragma unroll
       for (int j = 0; j <= M; ++j) dtp *= p.dt;
       const double coef = inv_fact(M) * dtp;
       if constexpr (NL > 1) {
-        lines<NL>(C, Db, tab + (L == 0 ? tab_D(N) : tab_level_D(N, L)), ncl);
+        lines<NL>(C, Db[0], tab + (L == 0 ? tab_D(N) : tab_level_D(N, L)), ncl);
         __syncthreads();
       }
       // point phase: ut^M = -mu * metric(derivatives) + s^(M-1)(t) g, into C
@@ -613,13 +651,13 @@ struct Tck {
               const double dp = (double)t[D * NP];
 #pragma unroll
               for (int a = 0; a < D; ++a) {
-                const double gba = R.g[L][s][b * D + a];
+                const double gba = geo<L, NPL>(R, s, c, q, b * D + a);
                 w[a] = fma(gba, dp, w[a]);
                 w[D] = fma(gba, (double)t[a * NP], w[D]);
               }
             }
 #pragma unroll
-            for (int v = 0; v < NC; ++v) w[v] *= -R.g[L][s][D * D + (v == D)];
+            for (int v = 0; v < NC; ++v) w[v] *= -geo<L, NPL>(R, s, c, q, D * D + (v == D));
           }
           if (cell0 + c == scell) w[D] += sd * p.src.glev[L][(int64_t)member * NPL + q];
 #pragma unroll
@@ -675,35 +713,71 @@ struct Tck {
         }
       }
       __syncthreads();
-      const T* tab = static_cast<const T*>(p.tab);
+      const T* tab = ctab<T>(N);
       tensor_map<N - 2 * L, N - 2 * (L - 1)>(C, Db[0], Db[1], ncl, tab + tab_level_E(N, L));
       collapse<L - 1>(p, C, Db, R, ncl);
     }
   }
 };
 
-template <int D, int N, int CPW, bool REDUCE, int L>
-__device__ __forceinline__ void tck_load_levels(TckRegs<D, N, CPW, REDUCE>& R, const TckParams& p, int64_t cell0,
+template <int D, int N, int CPW, bool REDUCE>
+__device__ __forceinline__ void tck_load_level0(TckRegs<D, N, CPW, REDUCE>& R, const TckParams& p, int64_t cell0,
                                                 int ncl) {
-  constexpr int NLV = TckRegs<D, N, CPW, REDUCE>::NLV;
-  if constexpr (L < NLV) {
-    constexpr int G2 = D * D + 2;
-    constexpr int NPL = ipow(N - 2 * L, D);
-    constexpr int PSL = cdiv(CPW * NPL, NTH);
-    const double* base = p.geo_lev[L];
+  constexpr int G2 = D * D + 2, NP = ipow(N, D);
+  constexpr int PS0 = cdiv(CPW * NP, NTH);
 #pragma unroll
-    for (int s = 0; s < PSL; ++s) {
-      const int i = threadIdx.x + s * NTH;
-      const int c = i / NPL, q = i - (i / NPL) * NPL;
-      const double* gp = base + (cell0 + c) * (int64_t)(G2 * NPL) + q;
+  for (int s = 0; s < PS0; ++s) {
+    const int i = threadIdx.x + s * NTH;
+    const int c = i / NP, q = i - (i / NP) * NP;
+    const double* gp = p.geo_lev[0] + (cell0 + c) * (int64_t)(G2 * NP) + q;
 #pragma unroll
-      for (int e = 0; e < G2; ++e) R.g[L][s][e] = i < ncl * NPL ? gp[e * NPL] : 0.0;
-#pragma unroll
-      for (int v = 0; v < D + 1; ++v) R.A[L][s][v] = 0.0;
-    }
-    tck_load_levels<D, N, CPW, REDUCE, L + 1>(R, p, cell0, ncl);
+    for (int e = 0; e < G2; ++e) R.g[s][e] = i < ncl * NP ? gp[e * NP] : 0.0;
   }
+#pragma unroll
+  for (int l = 0; l < TckRegs<D, N, CPW, REDUCE>::NLV; ++l)
+#pragma unroll
+    for (int s = 0; s < PS0; ++s)
+#pragma unroll
+      for (int v = 0; v < D + 1; ++v) R.A[l][s][v] = 0.0;
 }
+
+// levels >= 1: the cells of a group are contiguous in each level's array, so
+// the copy to LDS is one coalesced stream per level (values held in
+// registers until the first barrier)
+template <int D, int N, int CPW, int L, int NLV>
+struct LevelStage {
+  static constexpr int G2 = D * D + 2;
+  static constexpr int CNT = CPW * G2 * ipow(N - 2 * L, D);
+  static constexpr int SL = cdiv(CNT, NTH);
+  double v[SL];
+  LevelStage<D, N, CPW, L + 1, NLV> next;
+  __device__ __forceinline__ void load(const TckParams& p, int64_t cell0, int ncl) {
+    const int cnt = ncl * G2 * ipow(N - 2 * L, D);
+    const double* src = p.geo_lev[L] + cell0 * (int64_t)(G2 * ipow(N - 2 * L, D));
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int i = threadIdx.x + s * NTH;
+      v[s] = i < cnt ? src[i] : 0.0;
+    }
+    next.load(p, cell0, ncl);
+  }
+  template <typename T>
+  __device__ __forceinline__ void store(double* lds) {
+    double* dst = lds + CPW * TckLayout<D, N, T>::lev_offset(L);
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int i = threadIdx.x + s * NTH;
+      if (i < CNT) dst[i] = v[s];
+    }
+    next.template store<T>(lds);
+  }
+};
+template <int D, int N, int CPW, int NLV>
+struct LevelStage<D, N, CPW, NLV, NLV> {
+  __device__ __forceinline__ void load(const TckParams&, int64_t, int) {}
+  template <typename T>
+  __device__ __forceinline__ void store(double*) {}
+};
 
 template <int D, int N, typename T, bool REDUCE, int CPW>
 __global__ void __launch_bounds__(NTH) tck_kernel(TckParams p) {
@@ -714,7 +788,7 @@ __global__ void __launch_bounds__(NTH) tck_kernel(TckParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* C = reinterpret_cast<T*>(smem);
   T* Db[3] = {C + CPW * NC * NP, C + 2 * CPW * NC * NP, C + 3 * CPW * NC * NP};
-  const T* tab = static_cast<const T*>(p.tab);
+  const T* tab = ctab<T>(N);
 
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int member = logical % p.B;
@@ -731,11 +805,24 @@ __global__ void __launch_bounds__(NTH) tck_kernel(TckParams p) {
     ev[s] = i < nel ? p.u[gofs + i] : 0.0;
   }
   TckRegs<D, N, CPW, REDUCE> R;
-  tck_load_levels<D, N, CPW, REDUCE, 0>(R, p, cell0, ncl);
+  tck_load_level0<D, N, CPW, REDUCE>(R, p, cell0, ncl);
+  double* lev_lds = reinterpret_cast<double*>(C + (1 + D) * CPW * NC * NP);
+  R.glev = lev_lds;
+  if constexpr (REDUCE) {
+    LevelStage<D, N, CPW, 1, (N + 1) / 2> stage;
+    stage.load(p, cell0, ncl);
 #pragma unroll
-  for (int s = 0; s < ES; ++s) {
-    const int i = threadIdx.x + s * NTH;
-    if (i < nel) C[i] = (T)ev[s];
+    for (int s = 0; s < ES; ++s) {
+      const int i = threadIdx.x + s * NTH;
+      if (i < nel) C[i] = (T)ev[s];
+    }
+    stage.template store<T>(lev_lds);
+  } else {
+#pragma unroll
+    for (int s = 0; s < ES; ++s) {
+      const int i = threadIdx.x + s * NTH;
+      if (i < nel) C[i] = (T)ev[s];
+    }
   }
   __syncthreads();
   tensor_apply_inplace<D, N, T>(C, ncl * NC, tab + tab_S(N));
@@ -767,7 +854,7 @@ __global__ void __launch_bounds__(NTH) tck_kernel(TckParams p) {
     }
   }
   __syncthreads();
-  tensor_apply_inplace<D, N, double>(sI, ncl * NC, p.tab64 + tab_Sinv(N));
+  tensor_apply_inplace<D, N, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
   for (int i = threadIdx.x; i < nel; i += NTH) p.I[gofs + i] = sI[i];
 }
 
@@ -780,7 +867,7 @@ __global__ void __launch_bounds__(NTH) energy_kernel(EnergyParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* sU = reinterpret_cast<T*>(smem);
   __shared__ double red[NTH];
-  const T* tab = static_cast<const T*>(p.tab);
+  const T* tab = ctab<T>(N);
   const int logical = blockIdx.x;
   const int member = logical % p.B;
   const int group = logical / p.B;

@@ -1,0 +1,183 @@
+"""GPU system tests: the batch solver with and without hipGraph replay, the
+energy watchdog, the first workload end to end against its closed form, the
+full-size 3D workloads on sampled cells against the oracle, and the request
+server (each result identical alone and in the mix)."""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import Mesh as OMesh
+from oracle import apply_operator, ader, norms, timestep as ts
+from tolerances import op_tol
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def test_standing_wave_2d_against_closed_form(gpu_lib):
+    """2D periodic 8x8 affine quads, k=3, rho=c=1, upwind, LSRK(5,4), Cr 0.2, 200 steps."""
+    say("c1 standing wave")
+    B = gpu_lib
+    k, nc = 3, 8
+    gm = B.Mesh(2, k, W.box_nodes(2, nc, k, 0.0), W.box_neighbors(2, nc), W.ConstantMaterial())
+    om = OMesh(2, k, W.box_nodes(2, nc, k, 0.0), W.box_neighbors(2, nc), W.ConstantMaterial())
+    U0 = om.interpolate(lambda x: W.standing_wave_2d(x, 0.0))
+    dt = 0.2 * gm.info.dt_unit
+    assert abs(dt - 0.2 / 8 / 3 ** 1.5) < 1e-15
+    u = to_dev(U0)[None]
+    rep = gm.solve(u, B.LSRK54, t_end=200 * dt, dt=dt)
+    assert rep.steps == 200
+    T = 200 * dt
+    got = u[0].cpu().numpy()
+    ep, ev = norms.l2_error(om, got, W.standing_wave_2d, T)
+    say(f"c1: T={T:.4f} L2(p)={ep:.3e} L2(v)={ev:.3e}")
+    assert ep < 2e-4 and ev < 3e-4
+    # and the same 200 steps on the oracle
+    want = U0
+    for s in range(200):
+        want = ts.lsrk_step(lambda x, t: apply_operator(om, x), want, s * dt, dt)
+    assert norms.rel_l2(got, want) < 1e-11
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_graph_replay_equals_eager(gpu_lib, scheme):
+    """dgw_solve_batch with a captured two-step hipGraph replayed many times
+    gives bitwise the eager result (sources included: the step counter lives
+    on the device)."""
+    say("graph", scheme)
+    B = gpu_lib
+    dim, nc, k, Bn = 3, 4, 3, 2
+    mat = W.FourierMaterial(2, dim=dim)
+    gm = B.Mesh(dim, k, W.box_nodes(dim, nc, k, 0.05), W.box_neighbors(dim, nc), mat, max_batch=Bn)
+    src = B.Sources(gm, W.random_points(5, Bn, dim), frequency=6.0)
+    U = W.random_state(3, (Bn,) + gm.shape) * 0.1
+    dt = 0.2 * gm.info.dt_unit
+    nsteps = 9
+    a = to_dev(U)
+    b = to_dev(U)
+    ra = gm.solve(a, scheme, t_end=0.1 + nsteps * dt, dt=dt, t0=0.1, sources=src, use_graph=False)
+    rb = gm.solve(b, scheme, t_end=0.1 + nsteps * dt, dt=dt, t0=0.1, sources=src, use_graph=True)
+    assert ra.steps == rb.steps == nsteps and ra.dt == rb.dt
+    assert torch.equal(a, b)
+    # explicit stepping from the same state agrees too
+    c = to_dev(U)
+    (gm.step_ader if scheme else gm.step_lsrk)(c, 0.1, ra.dt, nsteps, sources=src, B=Bn)
+    assert torch.equal(a, c)
+
+
+def test_autotune_keeps_results(gpu_lib):
+    say("autotune")
+    B = gpu_lib
+    gm = B.Mesh(3, 5, W.box_nodes(3, 3, 5, 0.05), W.box_neighbors(3, 3), W.FourierMaterial(1, dim=3))
+    U = to_dev(W.random_state(1, (1,) + gm.shape))
+    shapes = []
+    outs = []
+    for cells in (gm.launch_shape(0)[0],):
+        outs.append(gm.apply(U).clone())
+    gm.autotune(1)
+    shapes.append(gm.launch_shape(0))
+    outs.append(gm.apply(U))
+    assert torch.allclose(outs[0], outs[1], rtol=0, atol=1e-12 * outs[0].abs().max().item())
+
+
+def test_watchdog_trips_on_unstable_step(gpu_lib):
+    """A time step far above the stability limit is reported as DGW_EUNSTABLE."""
+    say("watchdog")
+    B = gpu_lib
+    gm = B.Mesh(2, 3, W.box_nodes(2, 4, 3, 0.0), W.box_neighbors(2, 4), W.ConstantMaterial())
+    u = to_dev(W.random_state(2, (1,) + gm.shape))
+    with pytest.raises(B.DgwError) as e:
+        gm.solve(u, B.ADER, t_end=200 * 3.0 * gm.info.dt_unit, courant=3.0, watchdog_every=10)
+    assert e.value.status == B.EUNSTABLE
+
+
+def _sampled_parity(B, ncell, k, precision, tol, nsample=24):
+    wl = W.c2_workload(ncell, k, 1805)
+    nodes, nb = W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell)
+    gm = B.Mesh(3, k, nodes, nb, B.fourier_material_struct(wl["material"]), precision=precision)
+    om = OMesh(3, k, nodes, nb, wl["material"], cache=False)
+    rng = np.random.default_rng(ncell * 10 + k)
+    cells = np.unique(np.concatenate([rng.choice(om.nc, nsample, replace=False), [0, om.nc - 1]]))
+    # smooth state: the pulse plus noise (state built on the host, same array for both sides)
+    x = gm.get(B.GET_NODE_COORDS)
+    U = np.ascontiguousarray(np.moveaxis(wl["ic"](x), -1, 1)) + 0.01 * rng.standard_normal((om.nc, 4, om.np_))
+    gm.autotune(1)
+    # operator on a random state (no cancellation between volume and face
+    # terms, so the relative difference measures rounding, not conditioning)
+    Ur = rng.standard_normal((om.nc, 4, om.np_))
+    L = gm.apply(to_dev(Ur)[None])[0].cpu().numpy()
+    want = apply_operator(om, Ur, cells=cells)
+    e_op = norms.rel_l2(L[cells], want)
+    # one ADER step: TCK on the sampled cells and their face neighbours, then
+    # the update on the sampled cells
+    dt = 0.16 * gm.info.dt_unit
+    u = to_dev(U)[None]
+    gm.step_ader(u, 0.0, dt, 1)
+    nbrs = np.unique(np.concatenate([cells, om.neighbors[cells].ravel()]))
+    I = np.zeros_like(U)
+    I[nbrs] = ader.tck(om, U, dt, cells=nbrs)
+    want = U[cells] + apply_operator(om, I, cells=cells)
+    e_ad = norms.rel_l2(u[0].cpu().numpy()[cells], want)
+    say(f"sampled {ncell}^3 k={k} prec={precision}: operator {e_op:.2e}, ADER step {e_ad:.2e}")
+    assert e_op < max(tol, op_tol(k, 3)) and e_ad < tol
+
+
+def test_full_size_c2_sampled(gpu_lib):
+    """24^3 curved hexes, k=5 (1.19e7 DoF), in the launch shape the benchmark
+    uses, on sampled cells."""
+    say("c2 full size")
+    _sampled_parity(gpu_lib, 24, 5, 0, 1e-12)
+
+
+def test_full_size_c3_sampled(gpu_lib):
+    """48^3 curved hexes, k=7 (2.26e8 DoF), FP64 and FP32-split, sampled cells."""
+    say("c3 full size")
+    _sampled_parity(gpu_lib, 48, 7, 0, 1e-12, nsample=8)
+    _sampled_parity(gpu_lib, 48, 7, 1, 1e-5, nsample=8)
+
+
+def _request(B, seed, ncell, k, scheme, t_end, arrival):
+    mat = W.FourierMaterial(seed, dim=3)
+    r = B.Request(arrival_s=arrival, dim=3, ncell=ncell, degree=k, scheme=scheme, precision=1,
+                  t_end=t_end, courant=0.8 * (0.44 if scheme == 0 else 0.18), deform_amp=0.05)
+    r.material = B.fourier_material_struct(mat)
+    c = W.random_points(seed + 1000, 1, 3)[0]
+    for a in range(3):
+        r.ic_center[a] = c[a]
+    r.ic_width = 0.1
+    return r
+
+
+def test_serving_alone_equals_mix(gpu_lib):
+    """Requests served concurrently give bitwise the states they give alone; a
+    request larger than the budget fails with DGW_ENOMEM and the rest go on."""
+    say("serve")
+    B = gpu_lib
+    reqs = [_request(B, 10 + i, n, k, i % 2, t, 0.002 * i)
+            for i, (n, k, t) in enumerate([(4, 2, 0.05), (6, 3, 0.04), (5, 4, 0.03), (8, 2, 0.05), (4, 5, 0.02)])]
+    big = _request(B, 99, 40, 8, 0, 0.1, 0.0)
+    budget = 3 * max(B.lib.dgw_request_footprint(C.byref(r)) for r in reqs)
+    assert B.lib.dgw_request_footprint(C.byref(big)) > budget
+    rep, res, states = B.serve(reqs + [big], budget_bytes=budget, max_live=4, realtime=True, keep_states=True)
+    say(f"serve: done {rep.n_done} failed {rep.n_failed} p50 {rep.p50_s:.4f}s p99 {rep.p99_s:.4f}s "
+        f"{rep.dof_steps_per_s:.3e} DoF-steps/s")
+    assert res[-1].status == B.ENOMEM
+    assert rep.n_done == len(reqs) and rep.n_failed == 1
+    for i, r in enumerate(reqs):
+        assert res[i].status == 0 and res[i].steps > 0
+        rep1, res1, st1 = B.serve([r], budget_bytes=budget, max_live=1, realtime=False, keep_states=True)
+        assert res1[0].status == 0
+        assert np.array_equal(states[i], st1[0])
+        assert res[i].t_admit >= res[i].t_arrive - 1e-9 and res[i].t_done >= res[i].t_admit
+    assert rep.p99_s >= rep.p50_s > 0

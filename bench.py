@@ -175,6 +175,100 @@ def cpu_baseline(target_s=15.0):
                       f"recomputed inside the timed region (the oracle caches nothing at this size)"}
 
 
+def batched_sources(B=64, steps=500, precision="fp32", ncell=32, k=5, seed=64, use_graph=True):
+    """Many Ricker point sources (peak frequency 8, t0 = 1.2/8, seeded uniform
+    positions) on one 32^3 curved mesh as a batch of B right-hand sides, zero
+    initial state, ADER order k+1, autotuned launch shape, hipGraph-captured
+    steps.  Returns aggregate DoF-steps/s."""
+    import torch
+    import workloads as W
+    from paper_1805_03981_amd import binding as dg
+    wl = W.c2_workload(ncell, k, 1805)
+    mesh = dg.Mesh(3, k, W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell),
+                   dg.fourier_material_struct(wl["material"]),
+                   precision=dg.FP32_SPLIT if precision == "fp32" else dg.FP64, max_batch=B)
+    src = dg.Sources(mesh, W.random_points(seed, B, 3), frequency=8.0)
+    u = torch.zeros((B,) + mesh.shape, dtype=torch.float64, device="cuda")
+    work = mesh.work(B)
+    dt = CR["ader"] * mesh.info.dt_unit
+    rep = mesh.solve(u, dg.ADER, t_end=steps * dt, dt=dt, sources=src, use_graph=use_graph, autotune=True,
+                     work=work, B=B)
+    e = mesh.energy(u, B=B)
+    out = {"workload": f"{ncell}^3 curved hexes, k={k}, {B} Ricker sources (f=8) as batch members, ADER, "
+                       f"{precision}, hipGraph={bool(use_graph)}, autotuned",
+           "B": B, "steps": int(rep.steps), "wall_s": rep.wall_s, "dof_steps_per_s": rep.dof_steps_per_s,
+           "dofs_total": mesh.info.dofs * B, "energy_member0_end": float(e[0]),
+           "launch_shape": {"operator": mesh.launch_shape(0), "tck": mesh.launch_shape(1)}}
+    del u, work, src, mesh
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving(nreq=24, seed=5, load=0.8, nmin=6, nmax=20, tmin=0.05, tmax=0.2):
+    """A Poisson stream of solve requests: seeded periodic curved boxes with
+    n^3 cells (n log-uniform in [nmin, nmax]), k uniform in 2..8, LSRK or
+    ADER, FP32-split, final time U[tmin, tmax], Cr = 0.8 Cr_crit; arrival
+    rate = `load` x the measured capacity.  Reports p50/p99 latency."""
+    import ctypes as C
+    import numpy as np
+    import workloads as W
+    from paper_1805_03981_amd import binding as dg
+    rng = np.random.default_rng(seed)
+    reqs = []
+    work = []
+    for i in range(nreq):
+        n = int(round(np.exp(rng.uniform(np.log(nmin), np.log(nmax)))))
+        k = int(rng.integers(2, 9))
+        scheme = int(rng.integers(0, 2))
+        t_end = float(rng.uniform(tmin, tmax))
+        r = dg.Request(arrival_s=0.0, dim=3, ncell=n, degree=k, scheme=scheme, precision=1, t_end=t_end,
+                       courant=0.8 * (0.44 if scheme == 0 else 0.18), deform_amp=0.05)
+        r.material = dg.fourier_material_struct(W.FourierMaterial(seed * 1000 + i, dim=3))
+        c = W.random_points(seed * 1000 + i, 1, 3)[0]
+        for a in range(3):
+            r.ic_center[a] = c[a]
+        r.ic_width = 0.1
+        reqs.append(r)
+    # capacity: all requests at once, no arrival process
+    cap, _, _ = dg.serve(reqs, realtime=False, max_live=8)
+    mean_s = cap.wall_s / nreq
+    gaps = rng.exponential(mean_s / load, size=nreq)
+    t = np.cumsum(gaps) - gaps[0]
+    for r, a in zip(reqs, t):
+        r.arrival_s = float(a)
+    rep, res, _ = dg.serve(reqs, realtime=True, max_live=8)
+    return {"workload": f"{nreq} requests, 3D curved periodic boxes n^3, n log-uniform [{nmin},{nmax}], k in 2..8, "
+                        f"LSRK/ADER, FP32-split, T in [{tmin},{tmax}], Poisson arrivals at {load} x capacity",
+            "p50_s": rep.p50_s, "p99_s": rep.p99_s, "dof_steps_per_s": rep.dof_steps_per_s,
+            "max_wait_s": rep.max_wait_s, "n_done": rep.n_done, "n_failed": rep.n_failed,
+            "capacity_dof_steps_per_s": cap.dof_steps_per_s, "wall_s": rep.wall_s}
+
+
+def ceilings():
+    """Measured ceilings: device copy and triad bandwidth, FP64 GEMM rate."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    c = torch.ones_like(a)
+
+    def timeit(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+    tc = timeit(lambda: b.copy_(a))
+    tt = timeit(lambda: torch.add(a, c, alpha=2.0, out=b))
+    m = 8192
+    A = torch.randn(m, m, dtype=torch.float64, device="cuda")
+    tg = timeit(lambda: A @ A, reps=5)
+    return {"copy_GBps": 2 * n * 8 / tc / 1e9, "triad_GBps": 3 * n * 8 / tt / 1e9,
+            "fp64_gemm_TFLOPs": 2 * m ** 3 / tg / 1e12}
+
+
 def copy_calibration(mib):
     """A plain device copy of known size, for calibrating the HBM counters."""
     import torch
@@ -196,6 +290,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 error measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--no-serving", action="store_true", help="skip the small serving trace")
+    ap.add_argument("--batched", action="store_true",
+                    help="also run the 32^3 k=5 batch of 64 point sources (500 ADER steps)")
+    ap.add_argument("--ceilings", action="store_true", help="also measure copy/triad/DGEMM ceilings")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design is "
@@ -240,6 +338,17 @@ def main():
     if not args.no_extras and "ader-fp32" in results:
         log("[bench] FP32-split error vs FP64")
         extras["fp32_split_rel_err_5_steps"] = fp32_error()
+    if not args.no_serving:
+        log("[bench] serving trace")
+        extras["serving"] = serving()
+        log(f"[bench] serving: {extras['serving']}")
+    if args.batched:
+        log("[bench] batched sources")
+        extras["batched_sources"] = batched_sources()
+        log(f"[bench] batched: {extras['batched_sources']}")
+    if args.ceilings:
+        extras["ceilings"] = ceilings()
+        log(f"[bench] ceilings: {extras['ceilings']}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (bounded sample)")

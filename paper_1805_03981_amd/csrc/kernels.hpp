@@ -181,6 +181,15 @@ struct OpLayout {
 
 __device__ __forceinline__ int dir_stride(int n, int dir) { return dir == 0 ? 1 : (dir == 1 ? n : n * n); }
 
+// Offset of the start of the line along `dir` through tangential face index
+// t (the other coordinates in increasing direction order, first fastest):
+// (t % st) + (t / st) st N with st = N^dir, written with constant divisors.
+template <int D, int N>
+__device__ __forceinline__ int face_line_base(int dir, int t) {
+  if constexpr (D == 2) return dir == 0 ? t * N : t;
+  return dir == 0 ? t * N : (dir == 1 ? (t % N) + (t / N) * N * N : t);
+}
+
 // C2 of the operator: R (+)= D_b^T F along the b-lines, plus the lifts of the
 // two face fluxes of direction b (rank one in the normal direction).
 template <int D, int N, typename T, int DIR>
@@ -295,8 +304,7 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
       const int f = (r / NC) % NFACE;
       // GL node of the neighbour's face opposite to f, tangential index t
       const int fo = f ^ 1, dir = fo >> 1, side = fo & 1;
-      const int st = dir_stride(N, dir);
-      const int q = (t % st) + (side ? (N - 1) * st : 0) + (t / st) * st * N;
+      const int q = face_line_base<D, N>(dir, t) + (side ? (N - 1) * dir_stride(N, dir) : 0);
       nv[s] = p.u[moff + (int64_t)nbi[s] * NC * NP + v * NP + q];
     }
   }
@@ -371,7 +379,7 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
         const int c = cf / NFACE, f = cf - c * NFACE;
         const int dir = f >> 1, side = f & 1;
         const int st = dir_stride(N, dir);
-        const T* su = sU + c * NC * NP + (t % st) + (t / st) * st * N;
+        const T* su = sU + c * NC * NP + face_line_base<D, N>(dir, t);
         double um[NC], up[NC];
 #pragma unroll
         for (int v = 0; v < NC; ++v) {
@@ -546,12 +554,17 @@ struct Tck {
   __device__ static __forceinline__ void lines(const T* C, T* Db0, const T* __restrict__ Dl, int ncl) {
     constexpr int NLL = ipow(NL, D - 1);
     constexpr int TILE = CPW * NC * NP;
-    const int per_dir = ncl * NC * NLL;
-    for (int wi = threadIdx.x; wi < D * per_dir; wi += NTH) {
-      const int dir = wi / per_dir;
-      const int r = wi - dir * per_dir;
+    constexpr int PER_DIR = CPW * NC * NLL;  // compile-time: no runtime division
+    constexpr int ITERS = cdiv(D * PER_DIR, NTH);
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+      const int wi = threadIdx.x + it * NTH;
+      if (wi >= D * PER_DIR) break;
+      const int dir = wi / PER_DIR;
+      const int r = wi - dir * PER_DIR;
       const int sl = r / NLL;
       const int L = r - sl * NLL;
+      if (sl >= ncl * NC) continue;  // ragged last group
       // line base and stride inside the NL^D tensor (x fastest)
       const int st = dir == 0 ? 1 : (dir == 1 ? NL : NL * NL);
       const int base = (L % st) + (L / st) * st * NL;

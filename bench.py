@@ -324,7 +324,7 @@ def main():
     ncells = 24 ** 3
     bytes_launch = algorithmic_bytes(3, 5, dom) * ncells
     achieved = bytes_launch / (head["kernels_ms"][dom] * 1e-3) / 1e9
-    traffic = read_traffic(dom, "c2", head["precision"])
+    traffic = read_traffic(dom, "hex24k5", head["precision"])
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": bytes_launch, "launch_ms": head["kernels_ms"][dom]}

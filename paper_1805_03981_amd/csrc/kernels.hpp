@@ -68,33 +68,62 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
 // direction has MI entries on input and MO on output.
 template <int D, int DIR, int MI, int MO, int A0, int A1, int A2>
 struct Pass {
-  static constexpr int ext(int e, int m) { return e == DIR ? m : (e == 0 ? A0 : (e == 1 ? A1 : A2)); }
-  static constexpr int stride(int e, int m) { return e == 0 ? 1 : stride(e - 1, m) * ext(e - 1, m); }
-  static constexpr int size(int m) { return stride(D - 1, m) * ext(D - 1, m); }
-  static constexpr int nlines() {
-    int r = 1;
-    for (int e = 0; e < D; ++e)
-      if (e != DIR) r *= ext(e, MI);
-    return r;
-  }
-  static constexpr int SIN = size(MI), SOUT = size(MO), NL = nlines();
-  static constexpr int STEP_IN = stride(DIR, MI), STEP_OUT = stride(DIR, MO);
+  // extents of the input (direction DIR has MI entries) and output (MO)
+  static constexpr int EI0 = DIR == 0 ? MI : A0, EI1 = DIR == 1 ? MI : A1, EI2 = DIR == 2 ? MI : A2;
+  static constexpr int EO0 = DIR == 0 ? MO : A0, EO1 = DIR == 1 ? MO : A1, EO2 = DIR == 2 ? MO : A2;
+  // strides (x fastest), plain constants: no recursion for the compiler to keep
+  static constexpr int SI0 = 1, SI1 = EI0, SI2 = EI0 * EI1;
+  static constexpr int SO0 = 1, SO1 = EO0, SO2 = EO0 * EO1;
+  static constexpr int SIN = D == 1 ? EI0 : (D == 2 ? EI0 * EI1 : EI0 * EI1 * EI2);
+  static constexpr int SOUT = D == 1 ? EO0 : (D == 2 ? EO0 * EO1 : EO0 * EO1 * EO2);
+  static constexpr int NL = SIN / MI;  // lines: product of the other input extents
+  static constexpr int STEP_IN = DIR == 0 ? SI0 : (DIR == 1 ? SI1 : SI2);
+  static constexpr int STEP_OUT = DIR == 0 ? SO0 : (DIR == 1 ? SO1 : SO2);
+  // input / output offset of the start of line L (the other coordinates in
+  // increasing direction order, first fastest)
   __device__ static __forceinline__ void base(int L, int& bi, int& bo) {
-    bi = 0;
-    bo = 0;
-#pragma unroll
-    for (int e = 0; e < D; ++e) {
-      if (e == DIR) continue;
-      const int x = ext(e, MI);
-      const int c = L % x;
-      L /= x;
-      bi += c * stride(e, MI);
-      bo += c * stride(e, MO);
+    if constexpr (D == 1) {
+      bi = 0;
+      bo = 0;
+    } else if constexpr (D == 2) {
+      if constexpr (DIR == 0) {
+        bi = L * SI1;
+        bo = L * SO1;
+      } else {
+        bi = L;
+        bo = L;
+      }
+    } else {
+      if constexpr (DIR == 0) {
+        const int c1 = L % EI1, c2 = L / EI1;
+        bi = c1 * SI1 + c2 * SI2;
+        bo = c1 * SO1 + c2 * SO2;
+      } else if constexpr (DIR == 1) {
+        const int c0 = L % EI0, c2 = L / EI0;
+        bi = c0 + c2 * SI2;
+        bo = c0 + c2 * SO2;
+      } else {
+        const int c0 = L % EI0, c1 = L / EI0;
+        bi = c0 + c1 * SI1;
+        bo = c0 + c1 * SO1;
+      }
     }
   }
 };
 
 enum PassMode { PM_STORE = 0, PM_ADD_SCALED = 1 };
+
+// acc = M x for an MO x MI matrix (row-major), written column by column so
+// that the MO accumulations are independent chains (FMA latency overlaps).
+template <int MI, int MO, typename TM>
+__device__ __forceinline__ void contract(const TM* __restrict__ M, const TM (&x)[MI], TM (&acc)[MO]) {
+#pragma unroll
+  for (int i = 0; i < MO; ++i) acc[i] = M[i * MI] * x[0];
+#pragma unroll
+  for (int j = 1; j < MI; ++j)
+#pragma unroll
+    for (int i = 0; i < MO; ++i) acc[i] = fma(M[i * MI + j], x[j], acc[i]);
+}
 
 // out = M in along DIR, for nslices independent tensors (cells x components).
 // in and out may be the same buffer when MI == MO (each line is read whole
@@ -115,15 +144,14 @@ __device__ __forceinline__ void tpass(const TI* in, TO* out, int nslices, const 
     TM x[MI];
 #pragma unroll
     for (int j = 0; j < MI; ++j) x[j] = (TM)src[j * P::STEP_IN];
+    TM acc[MO];
+    contract<MI, MO>(M, x, acc);
 #pragma unroll
     for (int i = 0; i < MO; ++i) {
-      TM acc = M[i * MI] * x[0];
-#pragma unroll
-      for (int j = 1; j < MI; ++j) acc = fma(M[i * MI + j], x[j], acc);
       if constexpr (MODE == PM_STORE)
-        dst[i * P::STEP_OUT] = (TO)acc;
+        dst[i * P::STEP_OUT] = (TO)acc[i];
       else
-        dst[i * P::STEP_OUT] += (TO)(scale * (double)acc);
+        dst[i * P::STEP_OUT] += (TO)(scale * (double)acc[i]);
     }
   }
 }
@@ -211,16 +239,19 @@ __device__ __forceinline__ void op_lines(const T* __restrict__ tab, const T* sT,
     const T f0 = sN[((c * NFACE + 2 * DIR) * NC + v) * NF + L];
     const T f1 = sN[((c * NFACE + 2 * DIR + 1) * NC + v) * NF + L];
     T* r = sR + sl * NP + bq;
+    T acc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = fma(LF1[i], f1, LF0[i] * f0);
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc[i] = fma(Dm[j * N + i], F[j], acc[i]);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      T acc = LF0[i] * f0;
-      acc = fma(LF1[i], f1, acc);
-#pragma unroll
-      for (int j = 0; j < N; ++j) acc = fma(Dm[j * N + i], F[j], acc);
       if constexpr (DIR == 0)
-        r[i * P::STEP_IN] = acc;
+        r[i * P::STEP_IN] = acc[i];
       else
-        r[i * P::STEP_IN] += acc;
+        r[i * P::STEP_IN] += acc[i];
     }
   }
 }
@@ -567,19 +598,16 @@ struct Tck {
       if (sl >= ncl * NC) continue;  // ragged last group
       // line base and stride inside the NL^D tensor (x fastest)
       const int st = dir == 0 ? 1 : (dir == 1 ? NL : NL * NL);
-      const int base = (L % st) + (L / st) * st * NL;
+      const int base = face_line_base<D, NL>(dir, L);
       const T* src = C + sl * NP + base;
       T* dst = Db0 + dir * TILE + sl * NP + base;
       T x[NL];
 #pragma unroll
       for (int j = 0; j < NL; ++j) x[j] = src[j * st];
+      T acc[NL];
+      contract<NL, NL>(Dl, x, acc);
 #pragma unroll
-      for (int i = 0; i < NL; ++i) {
-        T acc = Dl[i * NL] * x[0];
-#pragma unroll
-        for (int j = 1; j < NL; ++j) acc = fma(Dl[i * NL + j], x[j], acc);
-        dst[i * st] = acc;
-      }
+      for (int i = 0; i < NL; ++i) dst[i * st] = acc[i];
     }
   }
 
@@ -599,13 +627,10 @@ struct Tck {
       T x[MI];
 #pragma unroll
       for (int j = 0; j < MI; ++j) x[j] = (T)src[j * P::STEP_IN];
+      T acc[MO];
+      contract<MI, MO>(Mx, x, acc);
 #pragma unroll
-      for (int i = 0; i < MO; ++i) {
-        T acc = Mx[i * MI] * x[0];
-#pragma unroll
-        for (int j = 1; j < MI; ++j) acc = fma(Mx[i * MI + j], x[j], acc);
-        dst[i * P::STEP_OUT] = (TO)acc;
-      }
+      for (int i = 0; i < MO; ++i) dst[i * P::STEP_OUT] = (TO)acc[i];
     }
   }
 

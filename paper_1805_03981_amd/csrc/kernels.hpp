@@ -520,31 +520,21 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
 // Per time derivative m at the level with NL points per direction: one line
 // phase computes the collocated derivative along all d directions of every
 // component (tiles Db[0..d-1]); one point phase applies the metric of the
-// level (prefetched into registers of the point's thread), scales by the
-// mass factors and adds the source term, giving ut^m.  Every second
-// derivative is projected to NL-2 points.  The Taylor sum is accumulated per
-// level in FP64 registers: I = A_0 + E(A_1 + E(A_2 + ...)), embedded level by
-// level at the end (E between consecutive Gauss sets is exact on the lower
-// degree).  LDS: the current derivative C and d derivative tiles.
+// level (held in registers of the point's thread), scales by the mass
+// factors and adds the source term, giving ut^m.  Every second derivative is
+// projected to NL-2 points; the metric of the coarser level is requested
+// into the same registers as soon as the last point phase of the finer level
+// is done, so its latency overlaps the projection passes.  The Taylor sum is
+// accumulated per level in FP64 registers: I = A_0 + E(A_1 + E(A_2 + ...)),
+// embedded level by level at the end (E between consecutive Gauss sets is
+// exact on the lower degree).  LDS: the current derivative C and d
+// derivative tiles, nothing else, so that more workgroups fit on a CU.
 // ------------------------------------------------------------------------
 template <int D, int N, typename T>
 struct TckLayout {
   static constexpr int NC = D + 1, NP = ipow(N, D), G2 = D * D + 2;
   static constexpr int tiles = 1 + D;  // C and the d derivative tiles (an FP64 tile fits in Db)
-  // metric of the reduced Gauss sets (levels >= 1), FP64, per cell
-  static constexpr int lev_elems() {
-    int e = 0;
-    for (int m = N - 2; m >= 1; m -= 2) e += G2 * ipow(m, D);
-    return e;
-  }
-  static constexpr int lev_offset(int L) {  // start of level L >= 1 (elements per cell)
-    int e = 0;
-    for (int l = 1; l < L; ++l) e += G2 * ipow(N - 2 * l, D);
-    return e;
-  }
-  static constexpr int bytes_per_cell(bool reduce) {
-    return tiles * NC * NP * (int)sizeof(T) + (reduce ? 8 * lev_elems() : 0);
-  }
+  static constexpr int bytes_per_cell(bool /*reduce*/) { return tiles * NC * NP * (int)sizeof(T); }
 };
 
 template <int D, int N, int CPW, bool REDUCE>
@@ -552,10 +542,26 @@ struct TckRegs {
   static constexpr int G2 = D * D + 2, NC = D + 1;
   static constexpr int NLV = REDUCE ? (N + 1) / 2 : 1;
   static constexpr int PS0 = cdiv(CPW * ipow(N, D), NTH);
-  double g[PS0][G2];        // metric and mass factors of level 0
+  double g[PS0][G2];        // metric and mass factors of the current level
   double A[NLV][PS0][NC];   // Taylor sums per level (FP64)
-  const double* glev;       // LDS: metric of the levels >= 1, [level][cell][G2][m^D]
 };
+
+// metric and mass factors of level L (N - 2L points per direction) of the
+// group's cells into the registers of the threads that own the points
+template <int D, int N, int CPW, bool REDUCE, int L>
+__device__ __forceinline__ void tck_load_geo(TckRegs<D, N, CPW, REDUCE>& R, const TckParams& p, int64_t cell0,
+                                             int ncl) {
+  constexpr int G2 = D * D + 2, NPL = ipow(N - 2 * L, D);
+  constexpr int PSL = cdiv(CPW * NPL, NTH);
+#pragma unroll
+  for (int s = 0; s < PSL; ++s) {
+    const int i = threadIdx.x + s * NTH;
+    const int c = i / NPL, q = i - c * NPL;
+    const double* gp = p.geo_lev[L] + (cell0 + c) * (int64_t)(G2 * NPL) + q;
+#pragma unroll
+    for (int e = 0; e < G2; ++e) R.g[s][e] = i < ncl * NPL ? gp[e * NPL] : 0.0;
+  }
+}
 
 template <int D, int N, typename T, bool REDUCE, int CPW>
 struct Tck {
@@ -569,14 +575,8 @@ struct Tck {
   }
   static constexpr int npl(int L) { return ipow(N - 2 * L, D); }
 
-  // metric entry e at point q of cell c on level L (registers for level 0)
-  template <int L, int NPL>
-  __device__ static __forceinline__ double geo(const Regs& R, int s, int c, int q, int e) {
-    if constexpr (L == 0)
-      return R.g[s][e];
-    else
-      return R.glev[CPW * TckLayout<D, N, T>::lev_offset(L) + (c * G2 + e) * NPL + q];
-  }
+  // metric entry e of the s-th point of this thread on the current level
+  __device__ static __forceinline__ double geo(const Regs& R, int s, int e) { return R.g[s][e]; }
   static constexpr int psl(int L) { return cdiv(CPW * npl(L), NTH); }
 
   // derivative of every component along every direction at level NL: C -> Db
@@ -689,13 +689,13 @@ struct Tck {
               const double dp = (double)t[D * NP];
 #pragma unroll
               for (int a = 0; a < D; ++a) {
-                const double gba = geo<L, NPL>(R, s, c, q, b * D + a);
+                const double gba = geo(R, s, b * D + a);
                 w[a] = fma(gba, dp, w[a]);
                 w[D] = fma(gba, (double)t[a * NP], w[D]);
               }
             }
 #pragma unroll
-            for (int v = 0; v < NC; ++v) w[v] *= -geo<L, NPL>(R, s, c, q, D * D + (v == D));
+            for (int v = 0; v < NC; ++v) w[v] *= -geo(R, s, D * D + (v == D));
           }
           if (cell0 + c == scell) w[D] += sd * p.src.glev[L][(int64_t)member * NPL + q];
 #pragma unroll
@@ -706,6 +706,8 @@ struct Tck {
           }
         }
       }
+      // the last use of this level's metric: request the next level's
+      if constexpr (PROJECT && NL - 2 >= 1) tck_load_geo<D, N, CPW, REDUCE, L + 1>(R, p, cell0, ncl);
       __syncthreads();
       if constexpr (PROJECT) {
         constexpr int NR = NL - 2;
@@ -758,67 +760,22 @@ struct Tck {
   }
 };
 
-template <int D, int N, int CPW, bool REDUCE>
-__device__ __forceinline__ void tck_load_level0(TckRegs<D, N, CPW, REDUCE>& R, const TckParams& p, int64_t cell0,
-                                                int ncl) {
-  constexpr int G2 = D * D + 2, NP = ipow(N, D);
-  constexpr int PS0 = cdiv(CPW * NP, NTH);
-#pragma unroll
-  for (int s = 0; s < PS0; ++s) {
-    const int i = threadIdx.x + s * NTH;
-    const int c = i / NP, q = i - (i / NP) * NP;
-    const double* gp = p.geo_lev[0] + (cell0 + c) * (int64_t)(G2 * NP) + q;
-#pragma unroll
-    for (int e = 0; e < G2; ++e) R.g[s][e] = i < ncl * NP ? gp[e * NP] : 0.0;
-  }
-#pragma unroll
-  for (int l = 0; l < TckRegs<D, N, CPW, REDUCE>::NLV; ++l)
-#pragma unroll
-    for (int s = 0; s < PS0; ++s)
-#pragma unroll
-      for (int v = 0; v < D + 1; ++v) R.A[l][s][v] = 0.0;
+// Register budget of the TCK: with one point per thread the kernel is
+// compiled for the waves per SIMD that the LDS of one workgroup allows (a
+// 256-thread group puts one wave on each SIMD; 160 KiB of LDS per CU),
+// capped at 5 (at most 102 VGPRs), so that the registers never limit
+// occupancy below the LDS.  With more points per thread the registers hold
+// several metric sets and no budget is imposed (it would spill).
+template <int D, int N, typename T, int CPW>
+constexpr int tck_waves_per_simd() {
+  if (cdiv(CPW * ipow(N, D), NTH) > 1) return 1;
+  const int wg = (160 * 1024) / (CPW * TckLayout<D, N, T>::bytes_per_cell(true));
+  return wg < 1 ? 1 : (wg > 5 ? 5 : wg);
 }
 
-// levels >= 1: the cells of a group are contiguous in each level's array, so
-// the copy to LDS is one coalesced stream per level (values held in
-// registers until the first barrier)
-template <int D, int N, int CPW, int L, int NLV>
-struct LevelStage {
-  static constexpr int G2 = D * D + 2;
-  static constexpr int CNT = CPW * G2 * ipow(N - 2 * L, D);
-  static constexpr int SL = cdiv(CNT, NTH);
-  double v[SL];
-  LevelStage<D, N, CPW, L + 1, NLV> next;
-  __device__ __forceinline__ void load(const TckParams& p, int64_t cell0, int ncl) {
-    const int cnt = ncl * G2 * ipow(N - 2 * L, D);
-    const double* src = p.geo_lev[L] + cell0 * (int64_t)(G2 * ipow(N - 2 * L, D));
-#pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      const int i = threadIdx.x + s * NTH;
-      v[s] = i < cnt ? src[i] : 0.0;
-    }
-    next.load(p, cell0, ncl);
-  }
-  template <typename T>
-  __device__ __forceinline__ void store(double* lds) {
-    double* dst = lds + CPW * TckLayout<D, N, T>::lev_offset(L);
-#pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      const int i = threadIdx.x + s * NTH;
-      if (i < CNT) dst[i] = v[s];
-    }
-    next.template store<T>(lds);
-  }
-};
-template <int D, int N, int CPW, int NLV>
-struct LevelStage<D, N, CPW, NLV, NLV> {
-  __device__ __forceinline__ void load(const TckParams&, int64_t, int) {}
-  template <typename T>
-  __device__ __forceinline__ void store(double*) {}
-};
-
 template <int D, int N, typename T, bool REDUCE, int CPW>
-__global__ void __launch_bounds__(NTH) tck_kernel(TckParams p) {
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW>())))
+tck_kernel(TckParams p) {
   using K = Tck<D, N, T, REDUCE, CPW>;
   constexpr int NC = D + 1, NP = ipow(N, D);
   constexpr int ES = cdiv(CPW * NC * NP, NTH);
@@ -843,24 +800,17 @@ __global__ void __launch_bounds__(NTH) tck_kernel(TckParams p) {
     ev[s] = i < nel ? p.u[gofs + i] : 0.0;
   }
   TckRegs<D, N, CPW, REDUCE> R;
-  tck_load_level0<D, N, CPW, REDUCE>(R, p, cell0, ncl);
-  double* lev_lds = reinterpret_cast<double*>(C + (1 + D) * CPW * NC * NP);
-  R.glev = lev_lds;
-  if constexpr (REDUCE) {
-    LevelStage<D, N, CPW, 1, (N + 1) / 2> stage;
-    stage.load(p, cell0, ncl);
+  tck_load_geo<D, N, CPW, REDUCE, 0>(R, p, cell0, ncl);
 #pragma unroll
-    for (int s = 0; s < ES; ++s) {
-      const int i = threadIdx.x + s * NTH;
-      if (i < nel) C[i] = (T)ev[s];
-    }
-    stage.template store<T>(lev_lds);
-  } else {
+  for (int l = 0; l < TckRegs<D, N, CPW, REDUCE>::NLV; ++l)
 #pragma unroll
-    for (int s = 0; s < ES; ++s) {
-      const int i = threadIdx.x + s * NTH;
-      if (i < nel) C[i] = (T)ev[s];
-    }
+    for (int s = 0; s < PS0; ++s)
+#pragma unroll
+      for (int v = 0; v < NC; ++v) R.A[l][s][v] = 0.0;
+#pragma unroll
+  for (int s = 0; s < ES; ++s) {
+    const int i = threadIdx.x + s * NTH;
+    if (i < nel) C[i] = (T)ev[s];
   }
   __syncthreads();
   tensor_apply_inplace<D, N, T>(C, ncl * NC, tab + tab_S(N));

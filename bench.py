@@ -10,10 +10,14 @@ upwind flux, Gaussian pressure pulse (width 0.05) at a seeded point:
 LSRK(5,4) stages.  `value` is the FP64 ADER throughput in DoF-steps/s with
 the state resident in HBM; the other scheme/precision variants are reported
 beside it.  Also reported: per-kernel roofline (HIP events on the launch
-stream), FP32-split error against FP64, and the CPU FP64 oracle timed on a
-bounded sample of the same workload.
+stream), FP32-split error against FP64, the time to solution at a fixed
+pressure error (1e-6 relative at T = 0.5) against FP64 ADER and FP64 LSRK
+references, and the CPU FP64 oracle timed on a bounded sample of the same
+workload.  Optional: the degree sweep k = 1..8 on the paper's cube sizes,
+measured device ceilings, the batch of 64 point sources, a serving trace.
 
     python bench.py [--steps K] [--warmup W] [--variants ader-fp64,...]
+                    [--no-fixed-error] [--sweep] [--ceilings] [--batched] [--no-serving]
 """
 from __future__ import annotations
 
@@ -121,10 +125,15 @@ def run_variant(scheme, precision, steps, warmup):
     return res, mesh, u
 
 
-def fp32_error(steps=5):
-    """FP32-split vs FP64 after `steps` ADER steps from the same state."""
+def rel_l2(a, b):
+    """Relative difference of two device arrays in the plain coefficient 2-norm."""
     import torch
-    from oracle import norms
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def fp32_error(steps=5):
+    """FP32-split vs FP64 after `steps` steps of each scheme from the same state."""
+    import torch
     out = {}
     for scheme in ("ader", "lsrk"):
         m64, u64, _ = make_c2(1, "fp64")
@@ -133,119 +142,121 @@ def fp32_error(steps=5):
         for m, u in ((m64, u64), (m32, u32)):
             (m.step_ader if scheme == "ader" else m.step_lsrk)(u, 0.0, dt, steps)
         torch.cuda.synchronize()
-        out[scheme] = norms.rel_l2(u32.cpu().numpy(), u64.cpu().numpy())
+        out[scheme] = rel_l2(u32, u64)
     return out
 
 
-def cpu_baseline(target_s=15.0):
-    """The oracle (test infrastructure) timed on a sample of the c2 workload:
-    one ADER step (TCK + operator with its dense per-cell mass solve) on a
-    contiguous block of cells, scaled to DoF-steps/s."""
-    import numpy as np
-    import workloads as W
-    from oracle import Mesh, ader, apply_operator
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
-    wl = W.c2_workload(24, 5, 1805)
-    m = Mesh(3, 5, W.box_nodes(3, 24, 5, 0.05), W.box_neighbors(3, 24), wl["material"], cache=False)
-    U = np.zeros((m.nc, 4, m.np_))
-    U[:] = 1e-3
-    dt = CR["ader"] * 0.01
+def fixed_error(target=1e-6, T=0.5, iters=3, max_run_s=12.0):
+    """Time to solution at a fixed error, against two FP64 references on the
+    same mesh at 1/8 of their steps (0.9 of the critical Courant number):
+    ADER, and LSRK(5,4) (which converges at fourth order to the semi-discrete
+    solution).  For each scheme and precision and each reference, the largest
+    step (at most that Courant number, rounded down to T/n) whose pressure at
+    T differs from the reference by at most `target` (relative, plain
+    coefficient 2-norm over the GL nodes): the step is halved until the
+    target is met, then bisected in log(dt).  Runs are shared between the two
+    searches where the steps coincide; runs longer than `max_run_s` are not
+    started; a search that stops converging reports the smallest error."""
+    from paper_1805_03981_amd import binding as dg
+    refs, out = {}, {"target_rel_l2_p": target, "T": T, "references": {}}
+    for rs in ("ader", "lsrk"):
+        mesh, u0, _ = make_c2(1, "fp64")
+        mesh.autotune(1)
+        u = u0.clone()
+        rep = mesh.solve(u, dg.ADER if rs == "ader" else dg.LSRK54, t_end=T,
+                         dt=CR[rs] * mesh.info.dt_unit / 8, use_graph=True)
+        refs[rs] = u[0, :, 3, :].clone()
+        out["references"][rs] = {"precision": "fp64", "dt": rep.dt, "steps": rep.steps}
+        log(f"[bench] fixed error: {rs} reference, {rep.steps} steps in {rep.wall_s:.2f} s")
+        del mesh, u, u0
+    out["references"]["ader_vs_lsrk_rel_l2_p"] = rel_l2(refs["ader"], refs["lsrk"])
+    for scheme, prec in (("ader", "fp64"), ("lsrk", "fp64"), ("ader", "fp32"), ("lsrk", "fp32")):
+        key = f"{scheme}-{prec}"
+        m, v0, _ = make_c2(1, prec)
+        m.autotune(1)
+        sid = dg.ADER if scheme == "ader" else dg.LSRK54
+        dt_max = CR[scheme] * m.info.dt_unit
+        runs = {}
 
-    def one(cells):
-        ader.level_data(m, cells, 6)  # geometry of the sample (setup, untimed below)
-        t = time.perf_counter()
-        I = np.zeros_like(U)
-        I[cells] = ader.tck(m, U, dt, cells=cells)
-        apply_operator(m, I, cells=cells)
-        return time.perf_counter() - t
+        def run(dt):
+            if dt not in runs:
+                v = v0.clone()
+                r = m.solve(v, sid, t_end=T, dt=dt, use_graph=True)
+                errs = {rs: rel_l2(v[0, :, 3, :], ref) for rs, ref in refs.items()}
+                runs[dt] = (r.dt, r.steps, r.wall_s, r.dof_steps_per_s, errs)
+                log(f"[bench] fixed error {key}: dt {r.dt:.3e} ({r.steps} steps, {r.wall_s:.2f} s): rel L2(p) "
+                    + ", ".join(f"vs {rs} {e:.3e}" for rs, e in errs.items()))
+            return runs[dt]
 
-    probe = np.arange(16)
-    tp = one(probe)
-    ncell = int(min(m.nc, max(16, target_s / tp * len(probe))))
-    cells = np.arange(ncell)
-    t = one(cells)
-    dof = ncell * 4 * m.np_
-    return {"value": dof / t, "unit": "DoF-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"one ADER step (TCK + operator, dense per-cell Cholesky mass solve) on {ncell} of "
-                      f"{m.nc} cells of the 24^3 k=5 workload, {t:.1f} s; geometry of the sample cells "
-                      f"recomputed inside the timed region (the oracle caches nothing at this size)"}
+        sec_per_step = run(dt_max)[2] / run(dt_max)[1]
+        res = {}
+        for rs in refs:
+            err = lambda dt: run(dt)[4][rs]
+            best = dt_max if err(dt_max) <= target else None
+            lo = dt_max
+            while best is None:
+                nxt = lo / 2
+                if T / nxt * sec_per_step > max_run_s:
+                    break
+                if err(nxt) <= target:
+                    best = nxt
+                elif err(nxt) > 0.7 * err(lo):   # no longer converging: an error floor
+                    break
+                lo = nxt
+            if best is not None and best < dt_max:
+                good, bad = best, min(dt_max, 2 * best)
+                for _ in range(iters):
+                    mid = (good * bad) ** 0.5
+                    if err(mid) <= target:
+                        good = best = mid
+                    else:
+                        bad = mid
+            if best is None:
+                res[f"vs_{rs}"] = {"reached": False, "smallest_error": min(r[4][rs] for r in runs.values())}
+            else:
+                rdt, steps, wall, rate, errs = run(best)
+                res[f"vs_{rs}"] = {"reached": True, "dt": rdt, "courant": rdt / m.info.dt_unit, "steps": steps,
+                                   "rel_l2_p": errs[rs], "time_to_solution_s": wall, "dof_steps_per_s": rate,
+                                   "limited_by": "stability" if best == dt_max else "accuracy"}
+        out[key] = res
+        log(f"[bench] fixed error {key}: {res}")
+        del m
+    return out
 
 
-def batched_sources(B=64, steps=500, precision="fp32", ncell=32, k=5, seed=64, use_graph=True):
-    """Many Ricker point sources (peak frequency 8, t0 = 1.2/8, seeded uniform
-    positions) on one 32^3 curved mesh as a batch of B right-hand sides, zero
-    initial state, ADER order k+1, autotuned launch shape, hipGraph-captured
-    steps.  Returns aggregate DoF-steps/s."""
+def degree_sweep(steps=5, warmup=1):
+    """FP64 DoF-steps/s of both schemes against the degree on the paper's
+    cube sizes: 40^3 slightly curved hexes (80^3 for k <= 3), the c2 material
+    and pulse, 0.9 of the critical Courant number."""
     import torch
-    import workloads as W
-    from paper_1805_03981_amd import binding as dg
-    wl = W.c2_workload(ncell, k, 1805)
-    mesh = dg.Mesh(3, k, W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell),
-                   dg.fourier_material_struct(wl["material"]),
-                   precision=dg.FP32_SPLIT if precision == "fp32" else dg.FP64, max_batch=B)
-    src = dg.Sources(mesh, W.random_points(seed, B, 3), frequency=8.0)
-    u = torch.zeros((B,) + mesh.shape, dtype=torch.float64, device="cuda")
-    work = mesh.work(B)
-    dt = CR["ader"] * mesh.info.dt_unit
-    rep = mesh.solve(u, dg.ADER, t_end=steps * dt, dt=dt, sources=src, use_graph=use_graph, autotune=True,
-                     work=work, B=B)
-    e = mesh.energy(u, B=B)
-    out = {"workload": f"{ncell}^3 curved hexes, k={k}, {B} Ricker sources (f=8) as batch members, ADER, "
-                       f"{precision}, hipGraph={bool(use_graph)}, autotuned",
-           "B": B, "steps": int(rep.steps), "wall_s": rep.wall_s, "dof_steps_per_s": rep.dof_steps_per_s,
-           "dofs_total": mesh.info.dofs * B, "energy_member0_end": float(e[0]),
-           "launch_shape": {"operator": mesh.launch_shape(0), "tck": mesh.launch_shape(1)}}
-    del u, work, src, mesh
-    torch.cuda.empty_cache()
+    out = {}
+    for k in range(1, 9):
+        ncell = 80 if k <= 3 else 40
+        mesh, u0, _ = make_c2(1, "fp64", ncell=ncell, k=k)
+        mesh.autotune(1)
+        row = {"ncell": ncell, "dofs": mesh.info.dofs}
+        work = mesh.work(1)
+        for scheme in ("lsrk", "ader"):
+            dt = CR[scheme] * mesh.info.dt_unit
+            u = u0.clone()
+            step = mesh.step_ader if scheme == "ader" else mesh.step_lsrk
+            step(u, 0.0, dt, warmup, work=work)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            step(u, 0.0, dt, steps, work=work)
+            torch.cuda.synchronize()
+            row[scheme] = mesh.info.dofs * steps / (time.perf_counter() - t0)
+        log(f"[bench] sweep k={k}: {row}")
+        out[k] = row
+        del mesh, u0, work, u
+        torch.cuda.empty_cache()
     return out
-
-
-def serving(nreq=24, seed=5, load=0.8, nmin=6, nmax=20, tmin=0.05, tmax=0.2):
-    """A Poisson stream of solve requests: seeded periodic curved boxes with
-    n^3 cells (n log-uniform in [nmin, nmax]), k uniform in 2..8, LSRK or
-    ADER, FP32-split, final time U[tmin, tmax], Cr = 0.8 Cr_crit; arrival
-    rate = `load` x the measured capacity.  Reports p50/p99 latency."""
-    import ctypes as C
-    import numpy as np
-    import workloads as W
-    from paper_1805_03981_amd import binding as dg
-    rng = np.random.default_rng(seed)
-    reqs = []
-    work = []
-    for i in range(nreq):
-        n = int(round(np.exp(rng.uniform(np.log(nmin), np.log(nmax)))))
-        k = int(rng.integers(2, 9))
-        scheme = int(rng.integers(0, 2))
-        t_end = float(rng.uniform(tmin, tmax))
-        r = dg.Request(arrival_s=0.0, dim=3, ncell=n, degree=k, scheme=scheme, precision=1, t_end=t_end,
-                       courant=0.8 * (0.44 if scheme == 0 else 0.18), deform_amp=0.05)
-        r.material = dg.fourier_material_struct(W.FourierMaterial(seed * 1000 + i, dim=3))
-        c = W.random_points(seed * 1000 + i, 1, 3)[0]
-        for a in range(3):
-            r.ic_center[a] = c[a]
-        r.ic_width = 0.1
-        reqs.append(r)
-    # capacity: all requests at once, no arrival process
-    cap, _, _ = dg.serve(reqs, realtime=False, max_live=8)
-    mean_s = cap.wall_s / nreq
-    gaps = rng.exponential(mean_s / load, size=nreq)
-    t = np.cumsum(gaps) - gaps[0]
-    for r, a in zip(reqs, t):
-        r.arrival_s = float(a)
-    rep, res, _ = dg.serve(reqs, realtime=True, max_live=8)
-    return {"workload": f"{nreq} requests, 3D curved periodic boxes n^3, n log-uniform [{nmin},{nmax}], k in 2..8, "
-                        f"LSRK/ADER, FP32-split, T in [{tmin},{tmax}], Poisson arrivals at {load} x capacity",
-            "p50_s": rep.p50_s, "p99_s": rep.p99_s, "dof_steps_per_s": rep.dof_steps_per_s,
-            "max_wait_s": rep.max_wait_s, "n_done": rep.n_done, "n_failed": rep.n_failed,
-            "capacity_dof_steps_per_s": cap.dof_steps_per_s, "wall_s": rep.wall_s}
 
 
 def ceilings():
-    """Measured ceilings: device copy and triad bandwidth, FP64 GEMM rate."""
+    """Measured ceilings: device copy and triad bandwidth, FP64 GEMM rate, LDS
+    read bandwidth (8- and 16-byte lanes, contiguous and at the 48-byte stride
+    of 6-point FP64 lines), vector FMA and matrix-core rates."""
     import torch
     n = (1 << 30) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -265,8 +276,30 @@ def ceilings():
     m = 8192
     A = torch.randn(m, m, dtype=torch.float64, device="cuda")
     tg = timeit(lambda: A @ A, reps=5)
-    return {"copy_GBps": 2 * n * 8 / tc / 1e9, "triad_GBps": 3 * n * 8 / tt / 1e9,
-            "fp64_gemm_TFLOPs": 2 * m ** 3 / tg / 1e12}
+    out = {"copy_GBps": 2 * n * 8 / tc / 1e9, "triad_GBps": 3 * n * 8 / tt / 1e9,
+           "fp64_gemm_TFLOPs": 2 * m ** 3 / tg / 1e12}
+    del a, b, c, A
+    torch.cuda.empty_cache()
+    # LDS, vector FMA and matrix-core rates from the microbenchmark library
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_1805_03981_amd", "libdgw_ceilings.so"))
+    torch.cuda.synchronize()
+
+    def rate(fn, *args):
+        v = C.c_double(0.0)
+        if fn(*args, C.byref(v)) != 0:
+            raise RuntimeError(f"{fn.__name__} failed")
+        return v.value
+
+    for acc, stride, name in ((8, 8, "lds_read_b64_TBps"), (16, 16, "lds_read_b128_TBps"),
+                              (8, 48, "lds_read_b64_stride48B_TBps"), (16, 48, "lds_read_b128_stride48B_TBps"),
+                              (8, 56, "lds_read_b64_stride56B_TBps")):
+        out[name] = rate(lib.dgw_ceiling_lds_read, acc, stride) / 1e12
+    out["fp64_vector_fma_TFLOPs"] = rate(lib.dgw_ceiling_vector_fma, 1) / 1e12
+    out["fp32_vector_fma_TFLOPs"] = rate(lib.dgw_ceiling_vector_fma, 0) / 1e12
+    out["fp64_mfma_TFLOPs"] = rate(lib.dgw_ceiling_mfma, 1) / 1e12
+    out["fp32_mfma_TFLOPs"] = rate(lib.dgw_ceiling_mfma, 0) / 1e12
+    return out
 
 
 def copy_calibration(mib):
@@ -293,7 +326,12 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the small serving trace")
     ap.add_argument("--batched", action="store_true",
                     help="also run the 32^3 k=5 batch of 64 point sources (500 ADER steps)")
-    ap.add_argument("--ceilings", action="store_true", help="also measure copy/triad/DGEMM ceilings")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="also measure copy/triad/DGEMM, LDS, vector FMA and MFMA ceilings")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the degree sweep k = 1..8 on 40^3 (80^3 for k <= 3) curved hexes, FP64")
+    ap.add_argument("--no-fixed-error", action="store_true",
+                    help="skip the time-to-solution at a fixed error (relative L2(p) 1e-6 at T = 0.5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design is "
@@ -346,6 +384,12 @@ def main():
         log("[bench] batched sources")
         extras["batched_sources"] = batched_sources()
         log(f"[bench] batched: {extras['batched_sources']}")
+    if not args.no_fixed_error:
+        log("[bench] time to solution at a fixed error")
+        extras["fixed_error"] = fixed_error()
+    if args.sweep:
+        log("[bench] degree sweep")
+        extras["degree_sweep"] = degree_sweep()
     if args.ceilings:
         extras["ceilings"] = ceilings()
         log(f"[bench] ceilings: {extras['ceilings']}")

@@ -37,6 +37,17 @@ def test_exports_every_declared_symbol(B):
     assert set(names) == set(B.EXPORTED)
 
 
+def test_ceilings_library_exports_its_header():
+    import ctypes
+    text = open(os.path.join(ROOT, "include", "dgw_ceilings.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(dgw_[a-z0-9_]+)\s*\(", text)))
+    assert names == ["dgw_ceiling_lds_read", "dgw_ceiling_mfma", "dgw_ceiling_vector_fma"]
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1805_03981_amd", "libdgw_ceilings.so"))
+    for n in names:
+        assert hasattr(lib, n), n
+
+
 @pytest.mark.parametrize("n", [2, 4, 6, 9])
 def test_basis_tables_match_oracle(B, n):
     xg, wg = basis.gauss(n)

@@ -222,9 +222,12 @@ dgw_status dgw_step_profile(dgw_mesh* mesh, int scheme, int ader_flags, double t
 dgw_status dgw_energy(dgw_mesh* mesh, const double* u, int B, double* host_out, void* stream);
 
 /* Launch shape of the operator (which = 0) or TCK (which = 1) kernels:
- * cells per workgroup and threads per workgroup.  Positive inputs set the
- * shape (threads 64/128/256; the LDS tile must fit 160 KiB); the current
- * shape is returned.  dgw_autotune times the candidates on scratch buffers
+ * cells per workgroup and threads per workgroup.  A positive cells_per_group
+ * selects one of the two compiled shapes (the LDS tile must fit 160 KiB);
+ * threads are fixed by the kernel and the cell size (256; the operator
+ * 1024 for 9^3 points, the TCK 512 for 8^3 and 1024 for 9^3): a positive
+ * input must equal that.  The current shape is
+ * returned.  dgw_autotune times the candidates on scratch buffers
  * for batch size B and keeps the fastest (cached per dim, k, precision, B,
  * mesh size). */
 dgw_status dgw_launch_shape(dgw_mesh* mesh, int which, int* cells_per_group, int* threads);

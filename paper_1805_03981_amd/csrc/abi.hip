@@ -78,7 +78,6 @@ static int ipw(int b, int e) {
 static int64_t state_elems(const dgw_mesh* m) { return m->hs.nc * m->ncomp * m->np; }
 
 static const int64_t kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
-static const int NTH_HOST = 256;              // threads per workgroup of every kernel
 
 static LaunchShape default_shape(const Launchers* L, int lds_per_cell) {
   LaunchShape s;
@@ -657,13 +656,15 @@ dgw_status dgw_launch_shape(dgw_mesh* m, int which, int* cells_per_group, int* t
     int sel = -1;
     for (int c = 0; c < 2; ++c)
       if (m->L->cpw[c] == *cells_per_group && (int64_t)m->L->cpw[c] * per_cell <= kLdsLimit) sel = c;
-    if (sel < 0 || (*threads > 0 && *threads != NTH_HOST))
+    const int nt = which == 0 ? op_threads(m->hs.dim, m->hs.n) : tck_threads(m->hs.dim, m->hs.n);
+    if (sel < 0 || (*threads > 0 && *threads != nt))
       return fail(DGW_EINVAL, "cells_per_group must be one of the compiled shapes (" + std::to_string(m->L->cpw[0]) +
-                                  ", " + std::to_string(m->L->cpw[1]) + ") and fit the LDS; threads must be 256");
+                                  ", " + std::to_string(m->L->cpw[1]) + ") and fit the LDS; threads must be " +
+                                  std::to_string(nt));
     sh.sel = sel;
   }
   *cells_per_group = m->L->cpw[sh.sel];
-  *threads = NTH_HOST;
+  *threads = which == 0 ? op_threads(m->hs.dim, m->hs.n) : tck_threads(m->hs.dim, m->hs.n);
   return DGW_OK;
 }
 

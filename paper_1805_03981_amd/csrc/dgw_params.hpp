@@ -8,7 +8,22 @@
 
 namespace dgw {
 
-constexpr int kMaxLevels = 5;  // Gauss sets of the degree reduction: k+1, k-1, ... (k <= 8)
+constexpr int kMaxLevels = 5;
+
+// Threads per workgroup for dimension d and n points per direction.  The
+// kernels run one cell per workgroup once a cell has more than 256 points;
+// a wider workgroup then gives the cell more waves, which pays only where
+// the LDS already limits a CU to one or two cells and the registers do not
+// cut that further (measured on 40^3 meshes, k = 6..8): the operator sweep
+// widens for 9^3 points, the TCK for 8^3 and 9^3.
+__host__ __device__ constexpr int op_threads(int d, int n) {
+  const int np = d == 2 ? n * n : n * n * n;
+  return np <= 512 ? 256 : 1024;
+}
+__host__ __device__ constexpr int tck_threads(int d, int n) {
+  const int np = d == 2 ? n * n : n * n * n;
+  return np <= 343 ? 256 : (np <= 512 ? 512 : 1024);
+}  // Gauss sets of the degree reduction: k+1, k-1, ... (k <= 8)
 
 // Epilogues of the fused operator sweep.
 enum Epilogue { EPI_STORE = 0, EPI_LSRK = 1, EPI_ADD = 2 };

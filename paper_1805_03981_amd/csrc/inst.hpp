@@ -19,7 +19,7 @@ hipError_t launch_op(const OpParams& p, hipStream_t s) {
   const size_t lds = (size_t)CPW * OpLayout<D, N, T>::per_cell * sizeof(T);
   hipError_t e = ensure_lds(op_kernel<D, N, T, EPI, CPW>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((op_kernel<D, N, T, EPI, CPW>), dim3(p.groups * p.B), dim3(NTH), lds, s, p);
+  hipLaunchKernelGGL((op_kernel<D, N, T, EPI, CPW>), dim3(p.groups * p.B), dim3(op_threads(D, N)), lds, s, p);
   return hipGetLastError();
 }
 
@@ -30,7 +30,7 @@ hipError_t launch_tck(const TckParams& p, hipStream_t s) {
   const size_t lds = (size_t)CPW * TckLayout<D, N, T>::bytes_per_cell(R);
   hipError_t e = ensure_lds(tck_kernel<D, N, T, R, CPW>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((tck_kernel<D, N, T, R, CPW>), dim3(p.groups * p.B), dim3(NTH), lds, s, p);
+  hipLaunchKernelGGL((tck_kernel<D, N, T, R, CPW>), dim3(p.groups * p.B), dim3(tck_threads(D, N)), lds, s, p);
   return hipGetLastError();
 }
 
@@ -39,7 +39,7 @@ hipError_t launch_energy(const EnergyParams& p, hipStream_t s) {
   const size_t lds = (size_t)p.cpw * (D + 1) * ipow(N, D) * sizeof(T);
   hipError_t e = ensure_lds(energy_kernel<D, N, T>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((energy_kernel<D, N, T>), dim3(p.groups * p.B), dim3(NTH), lds, s, p);
+  hipLaunchKernelGGL((energy_kernel<D, N, T>), dim3(p.groups * p.B), dim3(op_threads(D, N)), lds, s, p);
   return hipGetLastError();
 }
 

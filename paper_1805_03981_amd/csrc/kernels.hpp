@@ -27,8 +27,9 @@ namespace dgw {
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 __host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// Every kernel runs 256 threads (four wavefronts) per workgroup.
-constexpr int NTH = 256;
+// Threads per workgroup (op_threads, tck_threads in dgw_params.hpp): 256,
+// wider for the largest 3D cells.  Below, NT is the thread count of the
+// kernel being compiled.
 
 // 1D tables of every degree (layout tab_base / tab_*) in constant memory:
 // uniform reads of the matrix entries go through the scalar cache.  Each
@@ -47,9 +48,10 @@ __device__ __forceinline__ const float* ctab<float>(int n) {
 }
 
 // Cells per workgroup of the two compiled launch shapes: sel 0 gives about
-// one cell point per thread, sel 1 twice as many cells.
+// one cell point per thread of a 256-thread group (one cell for larger
+// cells, whatever the group width), sel 1 twice as many cells.
 __host__ __device__ constexpr int cells_per_group(int d, int n, int sel) {
-  return (NTH / ipow(n, d) > 1 ? NTH / ipow(n, d) : 1) * (sel + 1);
+  return (256 / ipow(n, d) > 1 ? 256 / ipow(n, d) : 1) * (sel + 1);
 }
 
 // Workgroup id -> logical id so that each XCD (workgroups are dispatched round
@@ -128,13 +130,13 @@ __device__ __forceinline__ void contract(const TM* __restrict__ M, const TM (&x)
 // out = M in along DIR, for nslices independent tensors (cells x components).
 // in and out may be the same buffer when MI == MO (each line is read whole
 // before it is written, and lines are disjoint).
-template <int D, int DIR, int MI, int MO, int A0, int A1, int A2, int MODE, typename TM, typename TI,
+template <int NT, int D, int DIR, int MI, int MO, int A0, int A1, int A2, int MODE, typename TM, typename TI,
           typename TO>
 __device__ __forceinline__ void tpass(const TI* in, TO* out, int nslices, const TM* __restrict__ M,
                                       double scale = 1.0) {
   using P = Pass<D, DIR, MI, MO, A0, A1, A2>;
   const int total = nslices * P::NL;
-  for (int w = threadIdx.x; w < total; w += NTH) {
+  for (int w = threadIdx.x; w < total; w += NT) {
     const int s = w / P::NL;
     const int L = w - s * P::NL;
     int bi, bo;
@@ -157,14 +159,14 @@ __device__ __forceinline__ void tpass(const TI* in, TO* out, int nslices, const 
 }
 
 // Apply the same n x n matrix along all D directions in place (square passes).
-template <int D, int N, typename TM, typename TT>
+template <int NT, int D, int N, typename TM, typename TT>
 __device__ __forceinline__ void tensor_apply_inplace(TT* buf, int nslices, const TM* M) {
-  tpass<D, 0, N, N, N, N, N, PM_STORE, TM>(buf, buf, nslices, M);
+  tpass<NT, D, 0, N, N, N, N, N, PM_STORE, TM>(buf, buf, nslices, M);
   __syncthreads();
-  tpass<D, 1, N, N, N, N, N, PM_STORE, TM>(buf, buf, nslices, M);
+  tpass<NT, D, 1, N, N, N, N, N, PM_STORE, TM>(buf, buf, nslices, M);
   __syncthreads();
   if constexpr (D == 3) {
-    tpass<D, 2, N, N, N, N, N, PM_STORE, TM>(buf, buf, nslices, M);
+    tpass<NT, D, 2, N, N, N, N, N, PM_STORE, TM>(buf, buf, nslices, M);
     __syncthreads();
   }
 }
@@ -227,7 +229,8 @@ __device__ __forceinline__ void op_lines(const T* __restrict__ tab, const T* sT,
   const T* Dm = tab + tab_D(N);
   const T* LF0 = tab + tab_LF0(N);
   const T* LF1 = tab + tab_LF1(N);
-  for (int w = threadIdx.x; w < ncl * NC * NF; w += NTH) {
+  constexpr int NT = op_threads(D, N);
+  for (int w = threadIdx.x; w < ncl * NC * NF; w += NT) {
     const int sl = w / NF;  // c * NC + v
     const int L = w - sl * NF;
     const int c = sl / NC, v = sl - c * NC;
@@ -260,10 +263,10 @@ __device__ __forceinline__ void op_lines(const T* __restrict__ tab, const T* sT,
 // F_{v_a} = G_{ba} p, F_p = sum_a G_{ba} v_a, with G = w det J J^-1.
 template <int D, int N, typename T, int PS, int DIR>
 __device__ __forceinline__ void op_points(const double (&g)[PS][D * D + 2], const T* sU, T* sT, int ncl) {
-  constexpr int NC = D + 1, NP = ipow(N, D);
+  constexpr int NC = D + 1, NP = ipow(N, D), NT = op_threads(D, N);
 #pragma unroll
   for (int s = 0; s < PS; ++s) {
-    const int i = threadIdx.x + s * NTH;
+    const int i = threadIdx.x + s * NT;
     if (i < ncl * NP) {
       const int c = i / NP, q = i - c * NP;
       const T* su = sU + c * NC * NP + q;
@@ -282,13 +285,14 @@ __device__ __forceinline__ void op_points(const double (&g)[PS][D * D + 2], cons
 }
 
 template <int D, int N, typename T, int EPI, int CPW>
-__global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
+__global__ void __launch_bounds__(op_threads(D, N)) op_kernel(OpParams p) {
   using Lay = OpLayout<D, N, T>;
   constexpr int NC = Lay::NC, NP = Lay::NP, NF = Lay::NF, NFACE = Lay::NFACE, G2 = D * D + 2;
-  constexpr int PS = cdiv(CPW * NP, NTH);             // cell points per thread
-  constexpr int FS = cdiv(CPW * NFACE * NF, NTH);     // face points per thread
-  constexpr int ES = cdiv(CPW * NC * NP, NTH);        // tile elements per thread
-  constexpr int NS = cdiv(CPW * NFACE * NC * NF, NTH);  // neighbour trace values per thread
+  constexpr int NT = op_threads(D, N);
+  constexpr int PS = cdiv(CPW * NP, NT);             // cell points per thread
+  constexpr int FS = cdiv(CPW * NFACE * NF, NT);     // face points per thread
+  constexpr int ES = cdiv(CPW * NC * NP, NT);        // tile elements per thread
+  constexpr int NS = cdiv(CPW * NFACE * NC * NF, NT);  // neighbour trace values per thread
   extern __shared__ __align__(16) unsigned char smem[];
   T* sU = reinterpret_cast<T*>(smem);
   T* sR = sU + CPW * NC * NP;
@@ -310,7 +314,7 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
   int nbi[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const int i = tid + s * NTH;
+    const int i = tid + s * NT;
     nbi[s] = 0;
     if (i < ncl * NFACE * NC * NF) {
       const int cf = i / (NC * NF);  // c * NFACE + f
@@ -320,13 +324,13 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
   double ev[ES];
 #pragma unroll
   for (int s = 0; s < ES; ++s) {
-    const int i = tid + s * NTH;
+    const int i = tid + s * NT;
     ev[s] = i < nel ? p.u[gofs + i] : 0.0;
   }
   double nv[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const int i = tid + s * NTH;
+    const int i = tid + s * NT;
     nv[s] = 0.0;
     if (i < ncl * NFACE * NC * NF) {
       const int t = i % NF;
@@ -342,7 +346,7 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
   double g[PS][G2];
 #pragma unroll
   for (int s = 0; s < PS; ++s) {
-    const int i = tid + s * NTH;
+    const int i = tid + s * NT;
     const int c = i / NP, q = i - (i / NP) * NP;
     const double* gp = p.geo_cell + (cell0 + c) * (int64_t)(G2 * NP) + q;
 #pragma unroll
@@ -351,7 +355,7 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
   double fg[FS][D + 2];
 #pragma unroll
   for (int s = 0; s < FS; ++s) {
-    const int i = tid + s * NTH;
+    const int i = tid + s * NT;
     const int cf = i / NF, t = i - (i / NF) * NF;  // cf = c * NFACE + f
     const double* fp = p.geo_face + (cell0 * NFACE + cf) * (int64_t)((D + 2) * NF) + t;
 #pragma unroll
@@ -360,7 +364,7 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
   double eb[ES];
 #pragma unroll
   for (int s = 0; s < ES; ++s) {
-    const int i = tid + s * NTH;
+    const int i = tid + s * NT;
     eb[s] = 0.0;
     if constexpr (EPI == EPI_ADD)
       if (i < nel) eb[s] = p.u_base[gofs + i];
@@ -369,12 +373,12 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
   }
 #pragma unroll
   for (int s = 0; s < ES; ++s) {
-    const int i = tid + s * NTH;
+    const int i = tid + s * NT;
     if (i < nel) sU[i] = (T)ev[s];
   }
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const int i = tid + s * NTH;
+    const int i = tid + s * NT;
     if (i < ncl * NFACE * NC * NF) sN[i] = (T)nv[s];
   }
   __syncthreads();
@@ -382,15 +386,15 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
   // ---- B: GL -> G of the cell tiles; tangential GL -> G of the neighbour traces
   {
     const T* S = tab + tab_S(N);
-    tpass<D, 0, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
-    if constexpr (D == 2) tpass<1, 0, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
-    if constexpr (D == 3) tpass<2, 0, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
+    tpass<NT, D, 0, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
+    if constexpr (D == 2) tpass<NT, 1, 0, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
+    if constexpr (D == 3) tpass<NT, 2, 0, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
     __syncthreads();
-    tpass<D, 1, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
-    if constexpr (D == 3) tpass<2, 1, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
+    tpass<NT, D, 1, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
+    if constexpr (D == 3) tpass<NT, 2, 1, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
     __syncthreads();
     if constexpr (D == 3) {
-      tpass<D, 2, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
+      tpass<NT, D, 2, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
       __syncthreads();
     }
   }
@@ -404,7 +408,7 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
     }
 #pragma unroll
     for (int s = 0; s < FS; ++s) {
-      const int i = tid + s * NTH;
+      const int i = tid + s * NT;
       if (i < ncl * NFACE * NF) {
         const int cf = i / NF, t = i - (i / NF) * NF;
         const int c = cf / NFACE, f = cf - c * NFACE;
@@ -465,7 +469,7 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
   // ---- D: inverse mass (pointwise FP64 factors), G -> GL
 #pragma unroll
   for (int s = 0; s < PS; ++s) {
-    const int i = tid + s * NTH;
+    const int i = tid + s * NT;
     if (i < ncl * NP) {
       const int c = i / NP, q = i - c * NP;
       T* r = sR + c * NC * NP + q;
@@ -474,7 +478,7 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
     }
   }
   __syncthreads();
-  tensor_apply_inplace<D, N, T>(sR, ncl * NC, tab + tab_Sinv(N));
+  tensor_apply_inplace<NT, D, N, T>(sR, ncl * NC, tab + tab_Sinv(N));
   // ---- E: epilogue (coalesced, operands prefetched in A)
   {
     int scell = -1;
@@ -488,7 +492,7 @@ __global__ void __launch_bounds__(NTH) op_kernel(OpParams p) {
     }
 #pragma unroll
     for (int s = 0; s < ES; ++s) {
-      const int i = tid + s * NTH;
+      const int i = tid + s * NT;
       if (i >= nel) continue;
       const double val = (double)sR[i];
       const int64_t gi = gofs + i;
@@ -541,7 +545,8 @@ template <int D, int N, int CPW, bool REDUCE>
 struct TckRegs {
   static constexpr int G2 = D * D + 2, NC = D + 1;
   static constexpr int NLV = REDUCE ? (N + 1) / 2 : 1;
-  static constexpr int PS0 = cdiv(CPW * ipow(N, D), NTH);
+  static constexpr int NT = tck_threads(D, N);
+  static constexpr int PS0 = cdiv(CPW * ipow(N, D), NT);
   double g[PS0][G2];        // metric and mass factors of the current level
   double A[NLV][PS0][NC];   // Taylor sums per level (FP64)
 };
@@ -551,11 +556,11 @@ struct TckRegs {
 template <int D, int N, int CPW, bool REDUCE, int L>
 __device__ __forceinline__ void tck_load_geo(TckRegs<D, N, CPW, REDUCE>& R, const TckParams& p, int64_t cell0,
                                              int ncl) {
-  constexpr int G2 = D * D + 2, NPL = ipow(N - 2 * L, D);
-  constexpr int PSL = cdiv(CPW * NPL, NTH);
+  constexpr int G2 = D * D + 2, NPL = ipow(N - 2 * L, D), NT = tck_threads(D, N);
+  constexpr int PSL = cdiv(CPW * NPL, NT);
 #pragma unroll
   for (int s = 0; s < PSL; ++s) {
-    const int i = threadIdx.x + s * NTH;
+    const int i = threadIdx.x + s * NT;
     const int c = i / NPL, q = i - c * NPL;
     const double* gp = p.geo_lev[L] + (cell0 + c) * (int64_t)(G2 * NPL) + q;
 #pragma unroll
@@ -565,7 +570,7 @@ __device__ __forceinline__ void tck_load_geo(TckRegs<D, N, CPW, REDUCE>& R, cons
 
 template <int D, int N, typename T, bool REDUCE, int CPW>
 struct Tck {
-  static constexpr int NC = D + 1, NP = ipow(N, D), G2 = D * D + 2;
+  static constexpr int NC = D + 1, NP = ipow(N, D), G2 = D * D + 2, NT = tck_threads(D, N);
   using Regs = TckRegs<D, N, CPW, REDUCE>;
 
   static constexpr double inv_fact(int m) {  // 1/(m+1)!
@@ -577,7 +582,7 @@ struct Tck {
 
   // metric entry e of the s-th point of this thread on the current level
   __device__ static __forceinline__ double geo(const Regs& R, int s, int e) { return R.g[s][e]; }
-  static constexpr int psl(int L) { return cdiv(CPW * npl(L), NTH); }
+  static constexpr int psl(int L) { return cdiv(CPW * npl(L), NT); }
 
   // derivative of every component along every direction at level NL: C -> Db
   // (the d derivative tiles are contiguous, TILE elements apart)
@@ -586,10 +591,10 @@ struct Tck {
     constexpr int NLL = ipow(NL, D - 1);
     constexpr int TILE = CPW * NC * NP;
     constexpr int PER_DIR = CPW * NC * NLL;  // compile-time: no runtime division
-    constexpr int ITERS = cdiv(D * PER_DIR, NTH);
+    constexpr int ITERS = cdiv(D * PER_DIR, NT);
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) {
-      const int wi = threadIdx.x + it * NTH;
+      const int wi = threadIdx.x + it * NT;
       if (wi >= D * PER_DIR) break;
       const int dir = wi / PER_DIR;
       const int r = wi - dir * PER_DIR;
@@ -617,7 +622,7 @@ struct Tck {
   __device__ static __forceinline__ void pass(const TI* in, TO* out, int ncl, const T* __restrict__ Mx) {
     constexpr int MI = DIR == 0 ? E0 : (DIR == 1 ? E1 : E2);
     using P = Pass<D, DIR, MI, MO, E0, E1, E2>;
-    for (int wi = threadIdx.x; wi < ncl * NC * P::NL; wi += NTH) {
+    for (int wi = threadIdx.x; wi < ncl * NC * P::NL; wi += NT) {
       const int s = wi / P::NL;
       const int L = wi - s * P::NL;
       int bi, bo;
@@ -658,7 +663,7 @@ struct Tck {
     constexpr int NL = N - 2 * L;
     if constexpr (M <= N && NL >= 1) {
       constexpr int NPL = ipow(NL, D);
-      constexpr int PSL = cdiv(CPW * NPL, NTH);
+      constexpr int PSL = cdiv(CPW * NPL, NT);
       constexpr bool PROJECT = REDUCE && (M % 2 == 0);
       const T* tab = ctab<T>(N);
       double dtp = 1.0;
@@ -676,7 +681,7 @@ struct Tck {
       if (scell >= cell0 && scell < cell0 + ncl) sd = ricker_deriv(p.src.wave + 3 * member, p.time.tn(), M - 1);
 #pragma unroll
       for (int s = 0; s < PSL; ++s) {
-        const int i = threadIdx.x + s * NTH;
+        const int i = threadIdx.x + s * NT;
         if (i < ncl * NPL) {
           const int c = i / NPL, q = i - c * NPL;
           double w[NC];
@@ -713,10 +718,10 @@ struct Tck {
         constexpr int NR = NL - 2;
         if constexpr (NR >= 1) {
           tensor_map<NL, NR>(C, Db[0], Db[1], ncl, tab + tab_level_P(N, L + 1));
-          constexpr int PSR = cdiv(CPW * ipow(NR, D), NTH);
+          constexpr int PSR = cdiv(CPW * ipow(NR, D), NT);
 #pragma unroll
           for (int s = 0; s < PSR; ++s) {
-            const int i = threadIdx.x + s * NTH;
+            const int i = threadIdx.x + s * NT;
             if (i < ncl * ipow(NR, D)) {
               const int c = i / ipow(NR, D), q = i - c * ipow(NR, D);
 #pragma unroll
@@ -741,7 +746,7 @@ struct Tck {
       // tile <- A_L (+ the embedded sum of the coarser levels already in C)
 #pragma unroll
       for (int s = 0; s < psl(L); ++s) {
-        const int i = threadIdx.x + s * NTH;
+        const int i = threadIdx.x + s * NT;
         if (i < ncl * NPL) {
           const int c = i / NPL, q = i - c * NPL;
 #pragma unroll
@@ -768,18 +773,18 @@ struct Tck {
 // several metric sets and no budget is imposed (it would spill).
 template <int D, int N, typename T, int CPW>
 constexpr int tck_waves_per_simd() {
-  if (cdiv(CPW * ipow(N, D), NTH) > 1) return 1;
+  if (tck_threads(D, N) != 256 || cdiv(CPW * ipow(N, D), 256) > 1) return 1;
   const int wg = (160 * 1024) / (CPW * TckLayout<D, N, T>::bytes_per_cell(true));
   return wg < 1 ? 1 : (wg > 5 ? 5 : wg);
 }
 
 template <int D, int N, typename T, bool REDUCE, int CPW>
-__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW>())))
-tck_kernel(TckParams p) {
+__global__ void __launch_bounds__(tck_threads(D, N))
+__attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW>()))) tck_kernel(TckParams p) {
   using K = Tck<D, N, T, REDUCE, CPW>;
-  constexpr int NC = D + 1, NP = ipow(N, D);
-  constexpr int ES = cdiv(CPW * NC * NP, NTH);
-  constexpr int PS0 = cdiv(CPW * NP, NTH);
+  constexpr int NC = D + 1, NP = ipow(N, D), NT = tck_threads(D, N);
+  constexpr int ES = cdiv(CPW * NC * NP, NT);
+  constexpr int PS0 = cdiv(CPW * NP, NT);
   extern __shared__ __align__(16) unsigned char smem[];
   T* C = reinterpret_cast<T*>(smem);
   T* Db[3] = {C + CPW * NC * NP, C + 2 * CPW * NC * NP, C + 3 * CPW * NC * NP};
@@ -796,7 +801,7 @@ tck_kernel(TckParams p) {
   double ev[ES];
 #pragma unroll
   for (int s = 0; s < ES; ++s) {
-    const int i = threadIdx.x + s * NTH;
+    const int i = threadIdx.x + s * NT;
     ev[s] = i < nel ? p.u[gofs + i] : 0.0;
   }
   TckRegs<D, N, CPW, REDUCE> R;
@@ -809,15 +814,15 @@ tck_kernel(TckParams p) {
       for (int v = 0; v < NC; ++v) R.A[l][s][v] = 0.0;
 #pragma unroll
   for (int s = 0; s < ES; ++s) {
-    const int i = threadIdx.x + s * NTH;
+    const int i = threadIdx.x + s * NT;
     if (i < nel) C[i] = (T)ev[s];
   }
   __syncthreads();
-  tensor_apply_inplace<D, N, T>(C, ncl * NC, tab + tab_S(N));
+  tensor_apply_inplace<NT, D, N, T>(C, ncl * NC, tab + tab_S(N));
   // m = 0 term: dt u_G
 #pragma unroll
   for (int s = 0; s < PS0; ++s) {
-    const int i = threadIdx.x + s * NTH;
+    const int i = threadIdx.x + s * NT;
     if (i < ncl * NP) {
       const int c = i / NP, q = i - c * NP;
 #pragma unroll
@@ -831,7 +836,7 @@ tck_kernel(TckParams p) {
   double* sI = reinterpret_cast<double*>(Db[0]);  // FP64 tile over the derivative tiles
 #pragma unroll
   for (int s = 0; s < PS0; ++s) {
-    const int i = threadIdx.x + s * NTH;
+    const int i = threadIdx.x + s * NT;
     if (i < ncl * NP) {
       const int c = i / NP, q = i - c * NP;
 #pragma unroll
@@ -842,19 +847,19 @@ tck_kernel(TckParams p) {
     }
   }
   __syncthreads();
-  tensor_apply_inplace<D, N, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
-  for (int i = threadIdx.x; i < nel; i += NTH) p.I[gofs + i] = sI[i];
+  tensor_apply_inplace<NT, D, N, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
+  for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i];
 }
 
 // ------------------------------------------------------------------------
 // Energy sum_q |v|^2 / mu_v + p^2 / mu_p at the Gauss points (per group).
 // ------------------------------------------------------------------------
 template <int D, int N, typename T>
-__global__ void __launch_bounds__(NTH) energy_kernel(EnergyParams p) {
-  constexpr int NC = D + 1, NP = ipow(N, D);
+__global__ void __launch_bounds__(op_threads(D, N)) energy_kernel(EnergyParams p) {
+  constexpr int NC = D + 1, NP = ipow(N, D), NT = op_threads(D, N);
   extern __shared__ __align__(16) unsigned char smem[];
   T* sU = reinterpret_cast<T*>(smem);
-  __shared__ double red[NTH];
+  __shared__ double red[NT];
   const T* tab = ctab<T>(N);
   const int logical = blockIdx.x;
   const int member = logical % p.B;
@@ -862,11 +867,11 @@ __global__ void __launch_bounds__(NTH) energy_kernel(EnergyParams p) {
   const int64_t cell0 = (int64_t)group * p.cpw;
   const int ncl = (int)min((int64_t)p.cpw, p.nc - cell0);
   const int64_t gofs = (int64_t)member * p.nc * NC * NP + cell0 * NC * NP;
-  for (int i = threadIdx.x; i < ncl * NC * NP; i += NTH) sU[i] = (T)p.u[gofs + i];
+  for (int i = threadIdx.x; i < ncl * NC * NP; i += NT) sU[i] = (T)p.u[gofs + i];
   __syncthreads();
-  tensor_apply_inplace<D, N, T>(sU, ncl * NC, tab + tab_S(N));
+  tensor_apply_inplace<NT, D, N, T>(sU, ncl * NC, tab + tab_S(N));
   double acc = 0.0;
-  for (int i = threadIdx.x; i < ncl * NC * NP; i += NTH) {
+  for (int i = threadIdx.x; i < ncl * NC * NP; i += NT) {
     const int q = i % NP;
     const int r = i / NP;
     const int v = r % NC;
@@ -877,7 +882,7 @@ __global__ void __launch_bounds__(NTH) energy_kernel(EnergyParams p) {
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = NTH / 2; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }

@@ -22,12 +22,19 @@ import numpy as np
 from . import basis
 
 
+# Boundary codes of the neighbour table: rigid (sound-hard) wall, first-order
+# absorbing boundary.
+BC_WALL, BC_ABSORBING = -1, -2
+
+
 class Mesh:
     """A mesh of curved quads (d=2) or hexes (d=3) with degree-k DG fields.
 
     geo_nodes: float64[Nc][(q+1)^d][d]; neighbors: int64[Nc][2d] in face order
-    -x,+x,-y,+y,-z,+z (standard orientation, no boundary); material:
-    callable x[...,d] -> (rho, c).
+    -x,+x,-y,+y,-z,+z (standard orientation); a negative entry marks a face on
+    the domain boundary with its condition (BC_WALL, BC_ABSORBING; the paper
+    leaves the boundary conditions open, Sec. 2); material: callable
+    x[...,d] -> (rho, c).
     """
 
     def __init__(self, dim, k, geo_nodes, neighbors, material, cache=True):
@@ -36,6 +43,8 @@ class Mesh:
         self.n = self.k + 1
         self.geo_nodes = np.ascontiguousarray(geo_nodes, dtype=np.float64)
         self.neighbors = np.ascontiguousarray(neighbors, dtype=np.int64)
+        if np.any((self.neighbors < 0) & (self.neighbors != BC_WALL) & (self.neighbors != BC_ABSORBING)):
+            raise ValueError("negative neighbour entries must be BC_WALL or BC_ABSORBING")
         self.material = material
         self.nc = self.geo_nodes.shape[0]
         ng = self.geo_nodes.shape[1]
@@ -124,7 +133,8 @@ class Mesh:
     def _face_data(self, cells, f):
         """Area vectors a[C][Qf][d] (face weight folded in), own and neighbour
         impedance Z = rho c at the face points (each side samples the material
-        at its own mapped point)."""
+        at its own mapped point; on a boundary face the exterior impedance is
+        the own one)."""
         x, J = self.map_points(cells, self.face_ref[f])
         detJ = np.linalg.det(J)
         if np.any(detJ <= 0.0):
@@ -133,10 +143,14 @@ class Mesh:
         a = self.face_w[None, :, None] * detJ[..., None] * (JinvT @ self.face_normal_ref(f))
         rho, c = self.material(x)
         nbc = self.neighbors[cells, f]
-        xn, _ = self.map_points(nbc, self.face_ref[f ^ 1])
-        rhon, cn = self.material(xn)
-        return dict(a=a, x=x, Zm=np.asarray(rho * c, dtype=np.float64),
-                    Zp=np.asarray(rhon * cn, dtype=np.float64), nb=nbc)
+        Zm = np.asarray(rho * c, dtype=np.float64)
+        Zp = Zm.copy()
+        inner = nbc >= 0
+        if np.any(inner):
+            xn, _ = self.map_points(nbc[inner], self.face_ref[f ^ 1])
+            rhon, cn = self.material(xn)
+            Zp[inner] = rhon * cn
+        return dict(a=a, x=x, Zm=Zm, Zp=Zp, nb=nbc)
 
     def node_points(self, cells=None):
         """Physical positions of the GL nodes, float64[C][n^d][d] (for interpolating

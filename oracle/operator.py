@@ -26,6 +26,13 @@ For Z- = Z+ the upwind flux is p* = {p} + Z/2 [v_n], v*_n = {v_n} + [p]/(2Z),
 the paper's HDG flux with tau = 1/(c rho) once its rows are divided by the
 coefficients that the paper keeps inside S.
 
+Boundary faces (the paper asks for boundary conditions without fixing any,
+Sec. 2; reading): the exterior state is built from the own trace and goes
+through the same flux with Z+ = Z-.  Rigid wall (v.n = 0): the mirror state
+p+ = p-, v+ = v- - 2 (v-.n) n, so that v*_n = 0 for both fluxes.  First-order
+absorbing boundary: p+ = 0, v+ = 0, so that the upwind flux keeps only the
+outgoing characteristic (p- + Z v-.n)/2.
+
 The operator is evaluated with the full d-dimensional GL basis tables at the
 quadrature points (no sum factorization) and the dense per-cell mass matrices
 M_v = sum_q w detJ rho phi_i phi_j, M_p = sum_q w detJ/(rho c^2) phi_i phi_j
@@ -36,6 +43,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import basis
+from .mesh import BC_WALL
 
 
 class Tables:
@@ -69,6 +77,20 @@ def numerical_flux(pm, pp, vnm, vnp, Zm, Zp, flux):
     return ps, vs
 
 
+def exterior_state(um, nrm, nb, d):
+    """Neighbour trace float64[C][d+1][Qf] of boundary faces from the own
+    trace um and the unit normals nrm[C][Qf][d] (rows with nb >= 0 are left
+    zero for the caller to fill)."""
+    up = np.zeros_like(um)
+    wall = nb == BC_WALL
+    if np.any(wall):
+        vn = np.einsum("cqa,caq->cq", nrm[wall], um[wall, :d, :])
+        up[wall, :d, :] = um[wall, :d, :] - 2.0 * vn[:, None, :] * np.moveaxis(nrm[wall], -1, 1)
+        up[wall, d, :] = um[wall, d, :]
+    # BC_ABSORBING: zero exterior state
+    return up
+
+
 def residual(mesh, U, cells, flux="upwind"):
     """Right-hand side r = -K U restricted to `cells`, float64[C][d+1][np] (GL test functions)."""
     d = mesh.dim
@@ -88,10 +110,14 @@ def residual(mesh, U, cells, flux="upwind"):
     for f in range(mesh.nface):
         fd = mesh.face_data(cells, f)
         um = np.einsum("qi,cvi->cvq", T.phif[f], Uc)
-        up = np.einsum("qi,cvi->cvq", T.phif[f ^ 1], U[fd["nb"]])
         a = fd["a"]                                     # [C][Qf][d]
         area = np.sqrt(np.sum(a * a, axis=-1))
         nrm = a / area[..., None]
+        nb = fd["nb"]
+        inner = nb >= 0
+        up = exterior_state(um, nrm, nb, d)
+        if np.any(inner):
+            up[inner] = np.einsum("qi,cvi->cvq", T.phif[f ^ 1], U[nb[inner]])
         vnm = np.einsum("cqa,caq->cq", nrm, um[:, :d, :])
         vnp = np.einsum("cqa,caq->cq", nrm, up[:, :d, :])
         ps, vs = numerical_flux(um[:, d], up[:, d], vnm, vnp, fd["Zm"], fd["Zp"], flux)

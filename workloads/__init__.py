@@ -1,7 +1,8 @@
 """Seeded synthetic inputs shared by the product path, the tests and the oracle.
 
-This package holds input recipes only: mesh node positions of the periodic
-box, the neighbour table, material fields, initial conditions, random states
+This package holds input recipes only: mesh node positions of the unit box,
+the neighbour table (periodic, or with wall / absorbing boundary codes),
+material fields, initial conditions and closed-form solutions, random states
 and source positions.  It contains none of the discontinuous Galerkin
 arithmetic (no quadrature, no basis, no operator); both the HIP library and
 the oracle compute everything else from these inputs on their own.
@@ -9,11 +10,15 @@ the oracle compute everything else from these inputs on their own.
 from .generators import (  # noqa: F401
     box_nodes,
     box_neighbors,
+    BC_WALL,
+    BC_ABSORBING,
     FourierMaterial,
     ConstantMaterial,
     standing_wave_2d,
     plane_wave_3d,
     gaussian_pulse,
+    membrane_mode,
+    travelling_pulse_x,
     random_state,
     random_points,
     c2_workload,

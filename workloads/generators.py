@@ -24,8 +24,22 @@ def _cell_index(idx, n):
     return out
 
 
-def box_neighbors(dim: int, ncell: int) -> np.ndarray:
-    """Periodic neighbour table int64[n^dim][2*dim] (faces -x,+x,-y,+y,-z,+z)."""
+# Boundary codes in a neighbour table (a face on the domain boundary): a rigid
+# (sound-hard) wall and a first-order absorbing boundary.
+BC_WALL, BC_ABSORBING = -1, -2
+
+
+def box_neighbors(dim: int, ncell: int, bc=None) -> np.ndarray:
+    """Neighbour table int64[n^dim][2*dim] of the unit box (faces -x,+x,-y,+y,-z,+z).
+
+    bc: None (periodic in every direction) or one entry per direction, each
+    "periodic", "wall" or "absorbing": the faces of that direction on the box
+    boundary get BC_WALL / BC_ABSORBING instead of the periodic neighbour.
+    """
+    bc = ["periodic"] * dim if bc is None else list(bc)
+    if len(bc) != dim or any(b not in ("periodic", "wall", "absorbing") for b in bc):
+        raise ValueError("bc: one of periodic / wall / absorbing per direction")
+    code = {"wall": BC_WALL, "absorbing": BC_ABSORBING}
     nc = ncell ** dim
     nb = np.empty((nc, 2 * dim), dtype=np.int64)
     grid = np.indices((ncell,) * dim).reshape(dim, -1)[::-1]  # grid[0] = x index (fastest)
@@ -35,7 +49,10 @@ def box_neighbors(dim: int, ncell: int) -> np.ndarray:
             for s, off in ((0, -1), (1, +1)):
                 j = list(idx)
                 j[a] += off
-                nb[e, 2 * a + s] = _cell_index(j, ncell)
+                if bc[a] != "periodic" and not 0 <= j[a] < ncell:
+                    nb[e, 2 * a + s] = code[bc[a]]
+                else:
+                    nb[e, 2 * a + s] = _cell_index(j, ncell)
     return nb
 
 
@@ -133,6 +150,38 @@ def plane_wave_3d(x: np.ndarray, t: float = 0.0) -> np.ndarray:
     out = np.empty(x.shape[:-1] + (4,))
     out[..., :3] = p[..., None] / np.sqrt(3.0)
     out[..., 3] = p
+    return out
+
+
+def membrane_mode(x: np.ndarray, t: float = 0.0, m=None) -> np.ndarray:
+    """Standing mode of the unit box with rigid walls, rho = c = 1:
+    p = cos(omega t) prod_j cos(pi m_j x_j), omega = pi |m|,
+    v_a = sin(omega t) (pi m_a / omega) sin(pi m_a x_a) prod_{j != a} cos(pi m_j x_j)
+    (v.n = 0 on every wall).  m: mode numbers per direction (default all 1)."""
+    x = np.asarray(x, dtype=np.float64)
+    dim = x.shape[-1]
+    m = np.ones(dim) if m is None else np.asarray(m, dtype=np.float64)
+    om = np.pi * np.sqrt(np.sum(m * m))
+    cs = np.cos(np.pi * m * x)
+    sn = np.sin(np.pi * m * x)
+    out = np.empty(x.shape[:-1] + (dim + 1,))
+    out[..., dim] = np.cos(om * t) * np.prod(cs, axis=-1)
+    for a in range(dim):
+        others = np.prod(np.delete(cs, a, axis=-1), axis=-1) if dim > 1 else 1.0
+        out[..., a] = np.sin(om * t) * (np.pi * m[a] / om) * sn[..., a] * others
+    return out
+
+
+def travelling_pulse_x(x: np.ndarray, t: float = 0.0, x0: float = 0.6, width: float = 0.05) -> np.ndarray:
+    """Right-going plane pulse along x, rho = c = 1: p = v_x = g(x - x0 - t) with
+    g a Gaussian of the given width, other velocity components 0.  Exact in the
+    box with absorbing x faces while the pulse enters nowhere (g ~ 0 at x = 0)."""
+    x = np.asarray(x, dtype=np.float64)
+    dim = x.shape[-1]
+    g = np.exp(-((x[..., 0] - x0 - t) ** 2) / (2.0 * width * width))
+    out = np.zeros(x.shape[:-1] + (dim + 1,))
+    out[..., 0] = g
+    out[..., dim] = g
     return out
 
 

@@ -17,7 +17,7 @@ workload.  Optional: the degree sweep k = 1..8 on the paper's cube sizes,
 measured device ceilings, the batch of 64 point sources, a serving trace.
 
     python bench.py [--steps K] [--warmup W] [--variants ader-fp64,...]
-                    [--no-fixed-error] [--sweep] [--ceilings] [--batched] [--no-serving]
+                    [--no-fixed-error] [--ablations] [--c3] [--sweep] [--ceilings] [--batched] [--no-serving]
 """
 from __future__ import annotations
 
@@ -224,6 +224,77 @@ def fixed_error(target=1e-6, T=0.5, iters=3, max_run_s=12.0):
     return out
 
 
+def c3_plane_wave(T=0.5, ncell=48, k=7):
+    """48^3 curved hexes (amplitude 0.05), k = 7 (2.27e8 DoF), rho = c = 1,
+    periodic plane wave p = cos(2 pi (x+y+z) - 2 pi sqrt3 t): both schemes
+    and precisions to T at 0.9 of the critical Courant number; error against
+    the closed form at the GL nodes (relative, plain 2-norm over all
+    components) and throughput."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1805_03981_amd import binding as dg
+    out = {"ncell": ncell, "k": k, "T": T}
+    for prec in ("fp64", "fp32"):
+        mesh = dg.Mesh(3, k, W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell), W.ConstantMaterial(),
+                       precision=dg.FP32_SPLIT if prec == "fp32" else dg.FP64)
+        mesh.autotune(1)
+        x = mesh.get(dg.GET_NODE_COORDS)
+        u0 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(W.plane_wave_3d(x, 0.0), -1, 1))).to("cuda")[None]
+        exact = None
+        for scheme in ("ader", "lsrk"):
+            u = u0.clone()
+            rep = mesh.solve(u, dg.ADER if scheme == "ader" else dg.LSRK54, t_end=T,
+                             dt=CR[scheme] * mesh.info.dt_unit, use_graph=True)
+            if exact is None or exact[0] != rep.steps * rep.dt:
+                ex = np.ascontiguousarray(np.moveaxis(W.plane_wave_3d(x, rep.steps * rep.dt), -1, 1))
+                exact = (rep.steps * rep.dt, torch.from_numpy(ex).to("cuda")[None])
+            err = rel_l2(u, exact[1])
+            out[f"{scheme}-{prec}"] = {"dofs": mesh.info.dofs, "steps": rep.steps, "dt": rep.dt,
+                                       "wall_s": rep.wall_s, "dof_steps_per_s": rep.dof_steps_per_s,
+                                       "rel_l2_error_vs_closed_form": err}
+            log(f"[bench] c3 {scheme}-{prec}: {out[f'{scheme}-{prec}']}")
+        del mesh, u0, u, exact
+        torch.cuda.empty_cache()
+    return out
+
+
+def ablations(steps=10, warmup=2):
+    """The paper's ablations on the c2 workload, FP64: LSRK(5,4) with the
+    vector update fused into the operator sweep, merged into one separate pass
+    (the paper's optimized updater) or as three BLAS-1 passes (its standard
+    one); ADER with and without the degree reduction.  Per variant: ms per
+    step and the mean duration of each component."""
+    import torch
+    from paper_1805_03981_amd import binding as dg
+    mesh, u0, _ = make_c2(1, "fp64")
+    mesh.autotune(1)
+    work = mesh.work(1)
+    out = {}
+    variants = [("lsrk_fused", dg.LSRK54, None), ("lsrk_merged_vu", dg.LSRK54_MERGED_VU, None),
+                ("lsrk_standard_vu", dg.LSRK54_STANDARD_VU, None), ("ader_reduce", dg.ADER, dg.ADER_REDUCE),
+                ("ader_noreduce", dg.ADER, dg.ADER_NOREDUCE)]
+    for name, scheme, flags in variants:
+        dt = CR["ader" if scheme == dg.ADER else "lsrk"] * mesh.info.dt_unit
+        u = u0.clone()
+        if scheme == dg.ADER:
+            step = lambda n: mesh.step_ader(u, 0.0, dt, n, work=work, flags=flags)
+        else:
+            step = lambda n: mesh.step_lsrk(u, 0.0, dt, n, work=work, scheme=scheme)
+        step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(steps)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        prof = mesh.profile(u0.clone(), scheme, 0.0, dt, 3, work=work, ader_flags=flags or 0)
+        out[name] = {"ms_per_step": ms, "dof_steps_per_s": mesh.info.dofs / (ms * 1e-3),
+                     "components_ms": {k: v[0] for k, v in prof.items()},
+                     "launches_per_step": {k: v[1] / 3 for k, v in prof.items()}}
+        log(f"[bench] ablation {name}: {out[name]}")
+    return out
+
+
 def degree_sweep(steps=5, warmup=1):
     """FP64 DoF-steps/s of both schemes against the degree on the paper's
     cube sizes: 40^3 slightly curved hexes (80^3 for k <= 3), the c2 material
@@ -328,6 +399,10 @@ def main():
                     help="also run the 32^3 k=5 batch of 64 point sources (500 ADER steps)")
     ap.add_argument("--ceilings", action="store_true",
                     help="also measure copy/triad/DGEMM, LDS, vector FMA and MFMA ceilings")
+    ap.add_argument("--ablations", action="store_true",
+                    help="also run the fused / merged / standard LSRK vector updates and ADER without reduction")
+    ap.add_argument("--c3", action="store_true",
+                    help="also run 48^3 k=7 curved hexes, c = 1 plane wave to T = 0.5: error and throughput")
     ap.add_argument("--sweep", action="store_true",
                     help="also run the degree sweep k = 1..8 on 40^3 (80^3 for k <= 3) curved hexes, FP64")
     ap.add_argument("--no-fixed-error", action="store_true",
@@ -387,6 +462,12 @@ def main():
     if not args.no_fixed_error:
         log("[bench] time to solution at a fixed error")
         extras["fixed_error"] = fixed_error()
+    if args.ablations:
+        log("[bench] ablations")
+        extras["ablations"] = ablations()
+    if args.c3:
+        log("[bench] 48^3 k=7 plane wave")
+        extras["c3_plane_wave"] = c3_plane_wave()
     if args.sweep:
         log("[bench] degree sweep")
         extras["degree_sweep"] = degree_sweep()

@@ -57,9 +57,25 @@ enum { DGW_FLUX_UPWIND = 0, DGW_FLUX_CENTRAL = 1 };
  * inverse mass factors in FP64. */
 enum { DGW_FP64 = 0, DGW_FP32_SPLIT = 1 };
 enum { DGW_SCHEME_LSRK54 = 0, DGW_SCHEME_ADER = 1 };
+/* Unfused LSRK(5,4) variants, for the ablation of the fused vector update
+ * (Sec. 4.3): the operator sweep stores L u and a separate pass updates the
+ * registers, merged into one pass over du, L u and u (the paper's optimized
+ * updater) or as three BLAS-1 passes (its standard one).  dgw_step_lsrk and
+ * dgw_step_profile only; no sources. */
+enum { DGW_SCHEME_LSRK54_MERGED_VU = 2, DGW_SCHEME_LSRK54_STANDARD_VU = 3 };
 /* ADER flags: DGW_ADER_NOREDUCE evaluates every time derivative at k+1
  * points per direction (Alg. 2 without the degree reduction of Sec. 3.3). */
 enum { DGW_ADER_REDUCE = 0, DGW_ADER_NOREDUCE = 1 };
+/* Boundary codes of the neighbour table.  The paper leaves the boundary
+ * conditions open (Sec. 2); the exterior state of a boundary face is built
+ * from the own trace and goes through the interior flux with the own
+ * impedance: DGW_BC_WALL is a rigid (sound-hard) wall, mirror state
+ * p+ = p-, v+ = v- - 2 (v-.n) n (so v*.n = 0); DGW_BC_ABSORBING a first-order
+ * absorbing face, zero exterior state (with the upwind flux only the outgoing
+ * characteristic passes).  Both are linear in the trace, so the ADER update
+ * applies them to the time-integrated Taylor sum unchanged. */
+#define DGW_BC_WALL (-1)
+#define DGW_BC_ABSORBING (-2)
 /* device = DGW_DEVICE_NONE builds the host-side setup only (no device
  * memory): the mesh can be inspected with dgw_mesh_get but not stepped. */
 #define DGW_DEVICE_NONE (-1)
@@ -79,8 +95,8 @@ typedef struct dgw_mesh_desc {
   int64_t n_cells;           /* >= 1                                            */
   int geo_degree;            /* q, 1..8; 0 = k                                  */
   const double* geo_nodes;   /* host [n_cells][(q+1)^dim][dim]; copied          */
-  const int64_t* neighbors;  /* host [n_cells][2*dim]; -1 (boundary) gives      */
-                             /* DGW_EUNSUPPORTED (periodic / interior only)     */
+  const int64_t* neighbors;  /* host [n_cells][2*dim]; a negative entry marks a */
+                             /* boundary face: DGW_BC_WALL or DGW_BC_ABSORBING  */
   const int* face_orient;    /* must be NULL (standard orientation)             */
   dgw_material_fn material;  /* required                                        */
   void* material_ctx;
@@ -183,8 +199,9 @@ void dgw_sources_destroy(dgw_sources* src);
 /* ---------------------------------------------------------------- b4 ---- */
 /* nsteps steps of the five-stage fourth-order 2N-storage Runge-Kutta scheme
  * (Sec. 2.2, LSRK4(5); Carpenter-Kennedy coefficients) from t0 with step dt:
- * du <- A_i du + dt (L u + s(t + c_i dt) g); u <- u + B_i du.  The vector
- * update is fused into the operator sweep (one launch per stage).  u advances
+ * du <- A_i du + dt (L u + s(t + c_i dt) g); u <- u + B_i du.  scheme
+ * DGW_SCHEME_LSRK54: the vector update is fused into the operator sweep (one
+ * launch per stage); the unfused variants above: see there.  u advances
  * in place; work: device buffer of B * lsrk_work_bytes (stage register and
  * the ping-pong copy that keeps neighbours reading the old stage).  src may
  * be NULL (else src->n >= B).  dt <= 0 or non-finite: DGW_EINVAL. */
@@ -205,8 +222,9 @@ dgw_status dgw_step_ader(dgw_mesh* mesh, int flags, double t0, double dt, int ns
  * Table 3): like dgw_step_lsrk / dgw_step_ader, with a HIP event pair on
  * `stream` around every launch.  out->ms[i] is the mean duration of one launch
  * of component i, out->launches[i] the number of launches; components:
- * LSRK: 0 = fused operator + vector update; ADER: 0 = TCK sweep, 1 = fused
- * operator + update.  Synchronous. */
+ * LSRK: 0 = fused operator + vector update; unfused LSRK: 0 = operator
+ * sweep, 1 = the stage's vector update pass(es); ADER: 0 = TCK sweep, 1 =
+ * fused operator + update.  Synchronous. */
 typedef struct dgw_profile {
   int n;
   double ms[4];

@@ -23,6 +23,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EUNSTABLE, EBUSY = 0, -1, -2, -3, -4,
 FLUX_UPWIND, FLUX_CENTRAL = 0, 1
 FP64, FP32_SPLIT = 0, 1
 LSRK54, ADER = 0, 1
+LSRK54_MERGED_VU, LSRK54_STANDARD_VU = 2, 3   # unfused LSRK variants (ablation)
 ADER_REDUCE, ADER_NOREDUCE = 0, 1
 DEVICE_NONE = -1
 GET_NODE_COORDS, GET_CELL_METRIC, GET_FACE, GET_LEVEL0 = 0, 1, 2, 16
@@ -268,10 +269,10 @@ class Mesh:
         check(lib.dgw_operator_apply(self.h, _tptr(u), _tptr(out), B, _stream(stream)), "dgw_operator_apply")
         return out
 
-    def step_lsrk(self, u, t0, dt, nsteps, work=None, sources=None, B=None, stream=None):
+    def step_lsrk(self, u, t0, dt, nsteps, work=None, sources=None, B=None, stream=None, scheme=LSRK54):
         B = B or (u.shape[0] if u.dim() == 4 else 1)
         work = self.work(B) if work is None else work
-        check(lib.dgw_step_lsrk(self.h, LSRK54, t0, dt, nsteps, _tptr(u), _tptr(work), B,
+        check(lib.dgw_step_lsrk(self.h, scheme, t0, dt, nsteps, _tptr(u), _tptr(work), B,
                                 sources.h if sources else None, _stream(stream)), "dgw_step_lsrk")
         return u
 

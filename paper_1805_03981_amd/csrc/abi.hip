@@ -185,6 +185,44 @@ static dgw_status lsrk_step(dgw_mesh* m, int B, const dgw_sources* src, double t
   return DGW_OK;
 }
 
+// Vector updates of an LSRK stage outside the operator sweep (the unfused
+// variants, Sec. 4.3): merged, one pass over du, r = L u and u (the paper's
+// optimized updater); standard, three BLAS-1 passes.  A stage coefficient
+// A_i = 0 means du is not read (the work buffer may hold anything).
+__global__ void __launch_bounds__(256) vu_merged(double* __restrict__ u, double* __restrict__ du,
+                                                 const double* __restrict__ r, double a, double dt, double b,
+                                                 int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (a != 0.0 ? a * du[i] : 0.0) + dt * r[i];
+    du[i] = d;
+    u[i] += b * d;
+  }
+}
+__global__ void __launch_bounds__(256) vu_scale(double* __restrict__ x, double a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = a != 0.0 ? a * x[i] : 0.0;
+}
+__global__ void __launch_bounds__(256) vu_axpy(double* __restrict__ y, const double* __restrict__ x, double a,
+                                               int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
+static dgw_status lsrk_vector_update(int scheme, int stage, double dt, double* u, double* du, const double* r,
+                                     int64_t n, hipStream_t s) {
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 16384);
+  const double a = kLsrk.A[stage], b = kLsrk.B[stage];
+  if (scheme == DGW_SCHEME_LSRK54_MERGED_VU) {
+    hipLaunchKernelGGL(vu_merged, dim3(blocks), dim3(256), 0, s, u, du, r, a, dt, b, n);
+  } else {
+    hipLaunchKernelGGL(vu_scale, dim3(blocks), dim3(256), 0, s, du, a, n);
+    hipLaunchKernelGGL(vu_axpy, dim3(blocks), dim3(256), 0, s, du, r, dt, n);
+    hipLaunchKernelGGL(vu_axpy, dim3(blocks), dim3(256), 0, s, u, du, b, n);
+  }
+  DGW_HIP(hipGetLastError());
+  return DGW_OK;
+}
+
 static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* src, double t0, double dt,
                             int step_add, const long long* ctr, double*& cur, double*& oth, double* I,
                             hipStream_t s) {
@@ -533,12 +571,30 @@ static dgw_status check_step(dgw_mesh* m, double dt, int nsteps, double* u, doub
 
 dgw_status dgw_step_lsrk(dgw_mesh* m, int scheme, double t0, double dt, int nsteps, double* u, double* work,
                          int B, const dgw_sources* src, void* stream) {
-  if (scheme != DGW_SCHEME_LSRK54) return fail(DGW_EUNSUPPORTED, "only DGW_SCHEME_LSRK54");
+  if (scheme != DGW_SCHEME_LSRK54 && scheme != DGW_SCHEME_LSRK54_MERGED_VU &&
+      scheme != DGW_SCHEME_LSRK54_STANDARD_VU)
+    return fail(DGW_EUNSUPPORTED, "scheme must be one of the DGW_SCHEME_LSRK54 variants");
+  if (scheme != DGW_SCHEME_LSRK54 && src) return fail(DGW_EUNSUPPORTED, "the unfused LSRK variants take no sources");
   dgw_status st = check_step(m, dt, nsteps, u, work, B, src);
   if (st) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
   hipStream_t s = (hipStream_t)stream;
+  if (scheme != DGW_SCHEME_LSRK54) {
+    // operator sweep stores r = L u into the second work register; the
+    // vector update then advances u in place
+    double* du = work;
+    double* r = work + state_elems(m) * B;
+    OpParams p = op_params(m, B, nullptr);
+    p.u = u;
+    p.out = r;
+    for (int k = 0; k < nsteps; ++k)
+      for (int i = 0; i < 5; ++i) {
+        DGW_HIP(m->L->op[EPI_STORE][m->op_shape.sel](p, s));
+        if ((st = lsrk_vector_update(scheme, i, dt, u, du, r, state_elems(m) * B, s))) return st;
+      }
+    return DGW_OK;
+  }
   double* du = work;
   double* cur = u;
   double* oth = work + state_elems(m) * B;
@@ -568,38 +624,63 @@ dgw_status dgw_step_ader(dgw_mesh* m, int flags, double t0, double dt, int nstep
 dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, double dt, int nsteps, double* u,
                             double* work, int B, const dgw_sources* src, void* stream, dgw_profile* out) {
   if (!out) return fail(DGW_EINVAL, "out is NULL");
-  if (scheme != DGW_SCHEME_LSRK54 && scheme != DGW_SCHEME_ADER) return fail(DGW_EINVAL, "bad scheme");
+  const bool unfused = scheme == DGW_SCHEME_LSRK54_MERGED_VU || scheme == DGW_SCHEME_LSRK54_STANDARD_VU;
+  if (scheme != DGW_SCHEME_LSRK54 && scheme != DGW_SCHEME_ADER && !unfused) return fail(DGW_EINVAL, "bad scheme");
+  if (unfused && src) return fail(DGW_EUNSUPPORTED, "the unfused LSRK variants take no sources");
   dgw_status st = check_step(m, dt, nsteps, u, work, B, src);
   if (st) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
   hipStream_t s = (hipStream_t)stream;
   std::memset(out, 0, sizeof(*out));
-  const int ncomp = scheme == DGW_SCHEME_ADER ? 2 : 1;
-  out->n = ncomp;
-  std::snprintf(out->names[0], 32, "%s", scheme == DGW_SCHEME_ADER ? "tck" : "operator_lsrk");
-  if (ncomp > 1) std::snprintf(out->names[1], 32, "%s", "operator_ader_update");
-  const int per_step = scheme == DGW_SCHEME_ADER ? 2 : 5;
-  std::vector<hipEvent_t> ev((size_t)2 * per_step * std::max(nsteps, 1));
-  for (auto& e : ev) DGW_HIP(hipEventCreate(&e));
+  const char* names[2] = {"operator_lsrk", nullptr};
+  if (scheme == DGW_SCHEME_ADER) names[0] = "tck", names[1] = "operator_ader_update";
+  if (unfused) names[0] = "operator_store", names[1] = "vector_update";
+  out->n = names[1] ? 2 : 1;
+  for (int c = 0; c < out->n; ++c) std::snprintf(out->names[c], 32, "%s", names[c]);
+  // (component, start event, end event) of every timed launch group
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> rec;
+  auto timed = [&](int c, auto&& launch) -> dgw_status {
+    hipEvent_t a, b;
+    DGW_HIP(hipEventCreate(&a));
+    DGW_HIP(hipEventCreate(&b));
+    rec.push_back({c, {a, b}});
+    DGW_HIP(hipEventRecord(a, s));
+    dgw_status e = launch();
+    if (e) return e;
+    DGW_HIP(hipEventRecord(b, s));
+    return DGW_OK;
+  };
   double* cur = u;
   double* oth = work + state_elems(m) * B;
   double* aux = work;
-  for (int k = 0; k < nsteps; ++k) {
-    if (scheme == DGW_SCHEME_LSRK54) {
+  for (int k = 0; k < nsteps && !st; ++k) {
+    if (unfused) {
+      OpParams p = op_params(m, B, nullptr);
+      p.u = u;
+      p.out = oth;
+      for (int i = 0; i < 5 && !st; ++i) {
+        st = timed(0, [&]() -> dgw_status {
+          DGW_HIP(m->L->op[EPI_STORE][m->op_shape.sel](p, s));
+          return DGW_OK;
+        });
+        if (!st) st = timed(1, [&] { return lsrk_vector_update(scheme, i, dt, u, aux, oth, state_elems(m) * B, s); });
+      }
+    } else if (scheme == DGW_SCHEME_LSRK54) {
       OpParams p = op_params(m, B, src);
       p.dt = dt;
       p.du = aux;
       p.time = StepTime{nullptr, t0, dt, k, 0.0};
-      for (int i = 0; i < 5; ++i) {
+      for (int i = 0; i < 5 && !st; ++i) {
         p.u = cur;
         p.u_next = oth;
         p.acoef = kLsrk.A[i];
         p.bcoef = kLsrk.B[i];
         p.time.t_off = kLsrk.C[i] * dt;
-        DGW_HIP(hipEventRecord(ev[(size_t)2 * (k * 5 + i)], s));
-        DGW_HIP(m->L->op[EPI_LSRK][m->op_shape.sel](p, s));
-        DGW_HIP(hipEventRecord(ev[(size_t)2 * (k * 5 + i) + 1], s));
+        st = timed(0, [&]() -> dgw_status {
+          DGW_HIP(m->L->op[EPI_LSRK][m->op_shape.sel](p, s));
+          return DGW_OK;
+        });
         std::swap(cur, oth);
       }
     } else {
@@ -608,32 +689,36 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
       tp.I = aux;
       tp.dt = dt;
       tp.time = StepTime{nullptr, t0, dt, k, 0.0};
-      DGW_HIP(hipEventRecord(ev[(size_t)4 * k], s));
-      DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0][m->tck_shape.sel](tp, s));
-      DGW_HIP(hipEventRecord(ev[(size_t)4 * k + 1], s));
+      st = timed(0, [&]() -> dgw_status {
+        DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0][m->tck_shape.sel](tp, s));
+        return DGW_OK;
+      });
       OpParams p = op_params(m, B, src);
       p.u = aux;
       p.u_base = cur;
       p.u_next = oth;
       p.time = StepTime{nullptr, t0, dt, k, 0.0};
-      DGW_HIP(hipEventRecord(ev[(size_t)4 * k + 2], s));
-      DGW_HIP(m->L->op[EPI_ADD][m->op_shape.sel](p, s));
-      DGW_HIP(hipEventRecord(ev[(size_t)4 * k + 3], s));
+      if (!st)
+        st = timed(1, [&]() -> dgw_status {
+          DGW_HIP(m->L->op[EPI_ADD][m->op_shape.sel](p, s));
+          return DGW_OK;
+        });
       std::swap(cur, oth);
     }
   }
-  DGW_HIP(hipStreamSynchronize(s));
-  for (int k = 0; k < nsteps; ++k)
-    for (int i = 0; i < per_step; ++i) {
-      float ms = 0;
-      DGW_HIP(hipEventElapsedTime(&ms, ev[(size_t)2 * (k * per_step + i)], ev[(size_t)2 * (k * per_step + i) + 1]));
-      const int c = scheme == DGW_SCHEME_ADER ? i : 0;
-      out->ms[c] += ms;
-      out->launches[c] += 1;
+  if (!st && hipStreamSynchronize(s) != hipSuccess) st = fail(DGW_EDEVICE, "stream synchronize failed");
+  for (auto& r : rec) {
+    float ms = 0;
+    if (!st && hipEventElapsedTime(&ms, r.second.first, r.second.second) == hipSuccess) {
+      out->ms[r.first] += ms;
+      out->launches[r.first] += 1;
     }
-  for (int c = 0; c < ncomp; ++c)
+    (void)hipEventDestroy(r.second.first);
+    (void)hipEventDestroy(r.second.second);
+  }
+  if (st) return st;
+  for (int c = 0; c < out->n; ++c)
     if (out->launches[c]) out->ms[c] /= (double)out->launches[c];
-  for (auto& e : ev) (void)hipEventDestroy(e);
   if (cur != u) DGW_HIP(hipMemcpyAsync(u, cur, state_elems(m) * 8 * B, hipMemcpyDeviceToDevice, s));
   DGW_HIP(hipStreamSynchronize(s));
   return DGW_OK;

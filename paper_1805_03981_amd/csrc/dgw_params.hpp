@@ -10,6 +10,9 @@ namespace dgw {
 
 constexpr int kMaxLevels = 5;
 
+// Boundary codes of the neighbour table (DGW_BC_WALL, DGW_BC_ABSORBING).
+constexpr int kBcWall = -1, kBcAbsorbing = -2;
+
 // Threads per workgroup for dimension d and n points per direction.  The
 // kernels run one cell per workgroup once a cell has more than 256 points;
 // a wider workgroup then gives the cell more waves, which pays only where

@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(op_threads(D, N)) op_kernel(OpParams p) {
   for (int s = 0; s < NS; ++s) {
     const int i = tid + s * NT;
     nv[s] = 0.0;
-    if (i < ncl * NFACE * NC * NF) {
+    if (i < ncl * NFACE * NC * NF && nbi[s] >= 0) {  // boundary faces: exterior state built in F
       const int t = i % NF;
       const int r = i / NF;
       const int v = r % NC;
@@ -351,6 +351,13 @@ __global__ void __launch_bounds__(op_threads(D, N)) op_kernel(OpParams p) {
     const double* gp = p.geo_cell + (cell0 + c) * (int64_t)(G2 * NP) + q;
 #pragma unroll
     for (int e = 0; e < G2; ++e) g[s][e] = i < ncl * NP ? gp[e * NP] : 0.0;
+  }
+  int fnb[FS];  // neighbour (or boundary code) of the face of each face point
+#pragma unroll
+  for (int s = 0; s < FS; ++s) {
+    const int i = tid + s * NT;
+    fnb[s] = 0;
+    if (i < ncl * NFACE * NF) fnb[s] = p.nb[cell0 * NFACE + i / NF];
   }
   double fg[FS][D + 2];
 #pragma unroll
@@ -434,15 +441,20 @@ __global__ void __launch_bounds__(op_threads(D, N)) op_kernel(OpParams p) {
         const double area = sqrt(area2), inv_area = 1.0 / area;
         vnm *= inv_area;
         vnp *= inv_area;
+        double pp = up[D];
+        if (fnb[s] < 0) {  // boundary: mirror state (wall) or zero state (absorbing)
+          pp = fnb[s] == kBcWall ? um[D] : 0.0;
+          vnp = fnb[s] == kBcWall ? -vnm : 0.0;
+        }
         double ps, vs;
         if (p.central) {
-          ps = 0.5 * (um[D] + up[D]);
+          ps = 0.5 * (um[D] + pp);
           vs = 0.5 * (vnm + vnp);
         } else {
           const double Zm = fg[s][D], Zp = fg[s][D + 1];
           const double inv = 1.0 / (Zm + Zp);
-          ps = (Zp * um[D] + Zm * up[D] + Zm * Zp * (vnm - vnp)) * inv;
-          vs = (Zm * vnm + Zp * vnp + um[D] - up[D]) * inv;
+          ps = (Zp * um[D] + Zm * pp + Zm * Zp * (vnm - vnp)) * inv;
+          vs = (Zm * vnm + Zp * vnp + um[D] - pp) * inv;
         }
 #pragma unroll
         for (int e = 0; e < D; ++e) sN[(cf * NC + e) * NF + t] = (T)(-fg[s][e] * ps);

@@ -13,6 +13,8 @@
 
 #include "dgw_host.hpp"
 
+static_assert(DGW_BC_WALL == dgw::kBcWall && DGW_BC_ABSORBING == dgw::kBcAbsorbing, "boundary codes");
+
 namespace dgw {
 
 using ld = long double;
@@ -339,19 +341,22 @@ dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs) {
   const int64_t nc = desc.n_cells;
   const int np = ipw(n, d), nf = ipw(n, d - 1), ng = ipw(q + 1, d), nface = 2 * d;
   const int ncomp_geo = d * d + 2;
-  // neighbours: conforming, periodic/interior only
+  // neighbours: conforming; negative entries are boundary codes
   hs.nb.resize(nc * nface);
   for (int64_t c = 0; c < nc; ++c)
     for (int f = 0; f < nface; ++f) {
       const int64_t o = desc.neighbors[c * nface + f];
-      if (o < 0) return fail(DGW_EUNSUPPORTED, "boundary faces (neighbor -1) are not supported");
+      if (o < 0 && o != DGW_BC_WALL && o != DGW_BC_ABSORBING)
+        return fail(DGW_EINVAL, "negative neighbor entries must be DGW_BC_WALL or DGW_BC_ABSORBING");
       if (o >= nc) return fail(DGW_EINVAL, "neighbor index out of range");
       hs.nb[c * nface + f] = (int32_t)o;
     }
   for (int64_t c = 0; c < nc; ++c)
-    for (int f = 0; f < nface; ++f)
-      if (desc.neighbors[desc.neighbors[c * nface + f] * nface + (f ^ 1)] != c)
+    for (int f = 0; f < nface; ++f) {
+      const int64_t o = desc.neighbors[c * nface + f];
+      if (o >= 0 && desc.neighbors[o * nface + (f ^ 1)] != c)
         return fail(DGW_EINVAL, "neighbor table is not conforming (nb[nb[c][f]][f^1] != c)");
+    }
   hs.geo_nodes.assign(desc.geo_nodes, desc.geo_nodes + nc * ng * d);
 
   const Rule g = gauss_rule(n);
@@ -483,12 +488,14 @@ dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs) {
     });
     if (!err.empty()) return fail(DGW_EINVAL, err);
   }
-  // impedance of the neighbour at the shared face point (its own sample)
+  // impedance of the neighbour at the shared face point (its own sample);
+  // on a boundary face the exterior impedance is the own one
   for (int64_t c = 0; c < nc; ++c)
     for (int f = 0; f < nface; ++f) {
       const int64_t o = hs.nb[c * nface + f];
       double* F = hs.face.data() + ((size_t)c * nface + f) * (d + 2) * nf;
-      const double* Zo = Zown.data() + ((size_t)o * nface + (f ^ 1)) * nf;
+      const double* Zo = o >= 0 ? Zown.data() + ((size_t)o * nface + (f ^ 1)) * nf
+                                : Zown.data() + ((size_t)c * nface + f) * nf;
       for (int p = 0; p < nf; ++p) F[(d + 1) * nf + p] = Zo[p];
     }
   double dtu = 1e300, hmin = 1e300, cmax = 0;

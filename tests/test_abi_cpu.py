@@ -59,10 +59,12 @@ def test_basis_tables_match_oracle(B, n):
     assert np.allclose(B.basis_1d(n, 6), basis.lagrange_deriv(xg, xg), atol=1e-12 * n * n)
 
 
-@pytest.mark.parametrize("dim,nc,k,amp", [(2, 3, 3, 0.05), (3, 2, 4, 0.05), (3, 2, 2, 0.0)])
-def test_host_setup_matches_oracle_geometry(B, dim, nc, k, amp):
+@pytest.mark.parametrize("dim,nc,k,amp,bc", [(2, 3, 3, 0.05, None), (3, 2, 4, 0.05, None), (3, 2, 2, 0.0, None),
+                                             (2, 3, 3, 0.05, ("wall", "absorbing")),
+                                             (3, 3, 2, 0.05, ("absorbing", "periodic", "wall"))])
+def test_host_setup_matches_oracle_geometry(B, dim, nc, k, amp, bc):
     mat = W.FourierMaterial(3, dim=dim)
-    nodes, nb = W.box_nodes(dim, nc, k, amp), W.box_neighbors(dim, nc)
+    nodes, nb = W.box_nodes(dim, nc, k, amp), W.box_neighbors(dim, nc, bc)
     gm = B.Mesh(dim, k, nodes, nb, mat, device=B.DEVICE_NONE)
     om = OMesh(dim, k, nodes, nb, mat)
     cd = om.cell_data(np.arange(om.nc))
@@ -120,10 +122,15 @@ def test_footprint_and_validation(B):
         B.Mesh(2, 2, W.box_nodes(2, 3, 2, 0.0), nb, mat, device=B.DEVICE_NONE)
     assert e.value.status == B.EINVAL
     nb = W.box_neighbors(2, 3)
-    nb[4, 2] = -1
+    nb[4, 2] = W.BC_WALL      # boundary on one side of an interior face: not conforming
     with pytest.raises(B.DgwError) as e:
         B.Mesh(2, 2, W.box_nodes(2, 3, 2, 0.0), nb, mat, device=B.DEVICE_NONE)
-    assert e.value.status == B.EUNSUPPORTED
+    assert e.value.status == B.EINVAL
+    nb = W.box_neighbors(2, 3, ("wall", "periodic"))
+    nb[nb == W.BC_WALL] = -3  # not a boundary code
+    with pytest.raises(B.DgwError) as e:
+        B.Mesh(2, 2, W.box_nodes(2, 3, 2, 0.0), nb, mat, device=B.DEVICE_NONE)
+    assert e.value.status == B.EINVAL
     # a folded cell (negative Jacobian)
     nodes = W.box_nodes(2, 3, 2, 0.0)
     nodes[0] = nodes[0].reshape(3, 3, 2)[:, ::-1].reshape(9, 2)  # mirror x: det J < 0

@@ -51,6 +51,31 @@ def test_standing_wave_2d_against_closed_form(gpu_lib):
 
 
 @pytest.mark.parametrize("scheme", [0, 1])
+def test_membrane_mode_in_wall_box(gpu_lib, scheme):
+    """2D unit box with rigid walls, 8x8 curved quads, k = 3, rho = c = 1: the
+    (1, 1) membrane mode to T = 0.3 against its closed form, and against the
+    oracle's run of the same steps."""
+    say("membrane", scheme)
+    B = gpu_lib
+    k, nc = 3, 8
+    nodes, nb = W.box_nodes(2, nc, k, 0.05), W.box_neighbors(2, nc, ("wall", "wall"))
+    gm = B.Mesh(2, k, nodes, nb, W.ConstantMaterial())
+    om = OMesh(2, k, nodes, nb, W.ConstantMaterial())
+    U0 = om.interpolate(lambda x: W.membrane_mode(x, 0.0))
+    u = to_dev(U0)[None]
+    rep = gm.solve(u, scheme, t_end=0.3, courant=0.2 if scheme == 0 else 0.1)
+    got = u[0].cpu().numpy()
+    ep, ev = norms.l2_error(om, got, W.membrane_mode, rep.steps * rep.dt)
+    say(f"membrane scheme {scheme}: {rep.steps} steps, L2(p) {ep:.3e} L2(v) {ev:.3e}")
+    assert ep < 3e-5 and ev < 4e-5
+    want = U0
+    for s in range(rep.steps):
+        want = (ts.lsrk_step(lambda x, t: apply_operator(om, x), want, s * rep.dt, rep.dt) if scheme == 0
+                else ader.ader_step(om, want, rep.dt))
+    assert norms.rel_l2(got, want) < 1e-11
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
 def test_graph_replay_equals_eager(gpu_lib, scheme):
     """dgw_solve_batch with a captured two-step hipGraph replayed many times
     gives bitwise the eager result (sources included: the step counter lives

@@ -113,6 +113,21 @@ def level_data(mesh, cells, n):
     return compute(cells)
 
 
+def minus_s_local(mesh, cells, ut, n, T):
+    """-S_loc ut at the level's n^d Gauss points: collocation derivatives of
+    the level-n Lagrange interpolant, J^-1, rho and c at those points."""
+    d = mesh.dim
+    ld = level_data(mesh, cells, n)
+    Jinv = ld["Jinv"]                                    # [C][Q][b][a]
+    grads = [np.einsum("qj,cvj->cvq", T.D[n][b], ut) for b in range(d)]  # d/dxi_b of each comp
+    w = np.empty_like(ut)
+    for a in range(d):
+        w[:, a] = -(1.0 / ld["rho"]) * sum(Jinv[:, :, b, a] * grads[b][:, d] for b in range(d))
+    div = sum(Jinv[:, :, b, a] * grads[b][:, a] for a in range(d) for b in range(d))
+    w[:, d] = -ld["rho"] * ld["c"] ** 2 * div
+    return w
+
+
 def tck(mesh, U, dt, cells=None, reduce=True, source_terms=None):
     """Time-integrated Taylor sum I (GL coefficients, float64[C][d+1][np]).
 
@@ -131,14 +146,7 @@ def tck(mesh, U, dt, cells=None, reduce=True, source_terms=None):
         n = lev[m - 1]
         if n <= 0:
             break
-        ld = level_data(mesh, cells, n)
-        Jinv = ld["Jinv"]                                    # [C][Q][b][a]
-        grads = [np.einsum("qj,cvj->cvq", T.D[n][b], ut) for b in range(d)]  # d/dxi_b of each comp
-        w = np.empty_like(ut)
-        for a in range(d):
-            w[:, a] = -(1.0 / ld["rho"]) * sum(Jinv[:, :, b, a] * grads[b][:, d] for b in range(d))
-        div = sum(Jinv[:, :, b, a] * grads[b][:, a] for a in range(d) for b in range(d))
-        w[:, d] = -ld["rho"] * ld["c"] ** 2 * div
+        w = minus_s_local(mesh, cells, ut, n, T)
         if source_terms is not None:
             w[:, d] += source_terms(cells, m, n)
         if reduce and m % 2 == 0:
@@ -162,3 +170,45 @@ def ader_step(mesh, U, dt, flux="upwind", reduce=True, source=None, t=0.0):
     if source is not None:
         out = out + source.integral(t, t + dt) * source.vector_full(mesh)
     return out
+
+
+def hdg_tck(mesh, U, W, dt, cells=None, reduce=True):
+    """Time-integrated sum of the HDG-ADER variant (Sec. 2.4, eq. hdg-ader),
+    GL coefficients float64[C][d+1][np]:
+
+        I = dt U + sum_{j=1}^{k+1} dt^{j+1}/(j+1)! (-S)^(j-1) W,   W = L_h U,
+
+    i.e. the first element-local derivative of the TCK sum is replaced by the
+    DG derivative W (faces included); the later ones are element-local as in
+    tck, with the degree of the j-th derivative k - 2 floor(j/2) (W is the
+    first derivative and keeps the k+1 points)."""
+    d, k = mesh.dim, mesh.k
+    T = ader_tables(mesh, reduce)
+    Tb = tables(mesh)
+    cells = np.arange(mesh.nc) if cells is None else np.atleast_1d(np.asarray(cells, dtype=np.int64))
+    u0 = np.einsum("qi,cvi->cvq", Tb.phi, np.asarray(U)[cells])
+    ut = np.einsum("qi,cvi->cvq", Tb.phi, np.asarray(W)[cells])   # derivative order 1
+    lev = T.levels
+    I = dt * u0 + dt ** 2 / 2.0 * np.einsum("pq,cvq->cvp", T.E[lev[1]], ut)
+    for m in range(2, k + 2):
+        n = lev[m - 1]
+        if n <= 0:
+            break
+        w = minus_s_local(mesh, cells, ut, n, T)
+        if reduce and m % 2 == 0:
+            if n - 2 < 1:
+                break
+            ut = np.einsum("rq,cvq->cvr", T.P[n], w)
+        else:
+            ut = w
+        I += dt ** (m + 1) / math.factorial(m + 1) * np.einsum("pq,cvq->cvp", T.E[lev[m]], ut)
+    Ig = np.linalg.solve(Tb.phi[None, :, :], np.swapaxes(I, -1, -2))
+    return np.ascontiguousarray(np.swapaxes(Ig, -1, -2))
+
+
+def hdg_ader_step(mesh, U, dt, flux="upwind", reduce=True):
+    """One HDG-ADER step (Sec. 2.4, eq. hdg-ader): two applications of the DG
+    operator, u + L_h(hdg_tck(u, L_h u))."""
+    U = np.asarray(U, dtype=np.float64)
+    W = apply_operator(mesh, U, flux=flux)
+    return U + apply_operator(mesh, hdg_tck(mesh, U, W, dt, reduce=reduce), flux=flux)

@@ -64,8 +64,14 @@ enum { DGW_SCHEME_LSRK54 = 0, DGW_SCHEME_ADER = 1 };
  * dgw_step_profile only; no sources. */
 enum { DGW_SCHEME_LSRK54_MERGED_VU = 2, DGW_SCHEME_LSRK54_STANDARD_VU = 3 };
 /* ADER flags: DGW_ADER_NOREDUCE evaluates every time derivative at k+1
- * points per direction (Alg. 2 without the degree reduction of Sec. 3.3). */
-enum { DGW_ADER_REDUCE = 0, DGW_ADER_NOREDUCE = 1 };
+ * points per direction (Alg. 2 without the degree reduction of Sec. 3.3).
+ * DGW_ADER_HDG selects the HDG-ADER variant (Sec. 2.4, eq. hdg-ader): the
+ * first element-local derivative of the Taylor sum is replaced by the DG
+ * operator, u <- u + L(dt u + sum_{j>=1} dt^{j+1}/(j+1)! (-S)^{j-1} L u),
+ * two operator sweeps and one TCK sweep per step; with the degree reduction
+ * only (DGW_ADER_HDG | DGW_ADER_NOREDUCE: DGW_EUNSUPPORTED) and without
+ * sources (DGW_EUNSUPPORTED). */
+enum { DGW_ADER_REDUCE = 0, DGW_ADER_NOREDUCE = 1, DGW_ADER_HDG = 2 };
 /* Boundary codes of the neighbour table.  The paper leaves the boundary
  * conditions open (Sec. 2); the exterior state of a boundary face is built
  * from the own trace and goes through the interior flux with the own
@@ -224,7 +230,8 @@ dgw_status dgw_step_ader(dgw_mesh* mesh, int flags, double t0, double dt, int ns
  * of component i, out->launches[i] the number of launches; components:
  * LSRK: 0 = fused operator + vector update; unfused LSRK: 0 = operator
  * sweep, 1 = the stage's vector update pass(es); ADER: 0 = TCK sweep, 1 =
- * fused operator + update.  Synchronous. */
+ * fused operator + update, and for DGW_ADER_HDG 2 = the operator sweep that
+ * stores L u.  Synchronous. */
 typedef struct dgw_profile {
   int n;
   double ms[4];

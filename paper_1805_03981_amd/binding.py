@@ -24,7 +24,7 @@ FLUX_UPWIND, FLUX_CENTRAL = 0, 1
 FP64, FP32_SPLIT = 0, 1
 LSRK54, ADER = 0, 1
 LSRK54_MERGED_VU, LSRK54_STANDARD_VU = 2, 3   # unfused LSRK variants (ablation)
-ADER_REDUCE, ADER_NOREDUCE = 0, 1
+ADER_REDUCE, ADER_NOREDUCE, ADER_HDG = 0, 1, 2
 DEVICE_NONE = -1
 GET_NODE_COORDS, GET_CELL_METRIC, GET_FACE, GET_LEVEL0 = 0, 1, 2, 16
 

@@ -223,6 +223,14 @@ static dgw_status lsrk_vector_update(int scheme, int stage, double dt, double* u
   return DGW_OK;
 }
 
+static dgw_status check_ader_flags(int flags, const dgw_sources* src) {
+  if (flags & ~(DGW_ADER_NOREDUCE | DGW_ADER_HDG)) return fail(DGW_EINVAL, "unknown ADER flags");
+  if ((flags & DGW_ADER_HDG) && (flags & DGW_ADER_NOREDUCE))
+    return fail(DGW_EUNSUPPORTED, "HDG-ADER is built with the degree reduction only");
+  if ((flags & DGW_ADER_HDG) && src) return fail(DGW_EUNSUPPORTED, "HDG-ADER takes no sources");
+  return DGW_OK;
+}
+
 static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* src, double t0, double dt,
                             int step_add, const long long* ctr, double*& cur, double*& oth, double* I,
                             hipStream_t s) {
@@ -231,7 +239,19 @@ static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* sr
   tp.I = I;
   tp.dt = dt;
   tp.time = StepTime{ctr, t0, dt, step_add, 0.0};
-  DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0][m->tck_shape.sel](tp, s));
+  if (flags & DGW_ADER_HDG) {
+    // W = L u into I, then the TCK sweep in place on I (each workgroup reads
+    // only its own cells before it writes them)
+    OpParams w = op_params(m, B, nullptr);
+    w.u = cur;
+    w.out = I;
+    DGW_HIP(m->L->op[EPI_STORE][m->op_shape.sel](w, s));
+    tp.u = I;
+    tp.u_base = cur;
+    DGW_HIP(m->L->tck_hdg[m->tck_shape.sel](tp, s));
+  } else {
+    DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0][m->tck_shape.sel](tp, s));
+  }
   OpParams p = op_params(m, B, src);
   p.u = I;
   p.u_base = cur;
@@ -606,9 +626,9 @@ dgw_status dgw_step_lsrk(dgw_mesh* m, int scheme, double t0, double dt, int nste
 
 dgw_status dgw_step_ader(dgw_mesh* m, int flags, double t0, double dt, int nsteps, double* u, double* work, int B,
                          const dgw_sources* src, void* stream) {
-  if (flags & ~DGW_ADER_NOREDUCE) return fail(DGW_EINVAL, "unknown ADER flags");
-  dgw_status st = check_step(m, dt, nsteps, u, work, B, src);
+  dgw_status st = check_ader_flags(flags, src);
   if (st) return st;
+  if ((st = check_step(m, dt, nsteps, u, work, B, src))) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -627,16 +647,22 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
   const bool unfused = scheme == DGW_SCHEME_LSRK54_MERGED_VU || scheme == DGW_SCHEME_LSRK54_STANDARD_VU;
   if (scheme != DGW_SCHEME_LSRK54 && scheme != DGW_SCHEME_ADER && !unfused) return fail(DGW_EINVAL, "bad scheme");
   if (unfused && src) return fail(DGW_EUNSUPPORTED, "the unfused LSRK variants take no sources");
+  const bool hdg = scheme == DGW_SCHEME_ADER && (flags & DGW_ADER_HDG);
+  if (scheme == DGW_SCHEME_ADER) {
+    dgw_status fs = check_ader_flags(flags, src);
+    if (fs) return fs;
+  }
   dgw_status st = check_step(m, dt, nsteps, u, work, B, src);
   if (st) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
   hipStream_t s = (hipStream_t)stream;
   std::memset(out, 0, sizeof(*out));
-  const char* names[2] = {"operator_lsrk", nullptr};
+  const char* names[3] = {"operator_lsrk", nullptr, nullptr};
   if (scheme == DGW_SCHEME_ADER) names[0] = "tck", names[1] = "operator_ader_update";
+  if (hdg) names[2] = "operator_store";
   if (unfused) names[0] = "operator_store", names[1] = "vector_update";
-  out->n = names[1] ? 2 : 1;
+  out->n = names[2] ? 3 : (names[1] ? 2 : 1);
   for (int c = 0; c < out->n; ++c) std::snprintf(out->names[c], 32, "%s", names[c]);
   // (component, start event, end event) of every timed launch group
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> rec;
@@ -689,10 +715,25 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
       tp.I = aux;
       tp.dt = dt;
       tp.time = StepTime{nullptr, t0, dt, k, 0.0};
-      st = timed(0, [&]() -> dgw_status {
-        DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0][m->tck_shape.sel](tp, s));
-        return DGW_OK;
-      });
+      if (hdg) {
+        OpParams w = op_params(m, B, nullptr);
+        w.u = cur;
+        w.out = aux;
+        st = timed(2, [&]() -> dgw_status {
+          DGW_HIP(m->L->op[EPI_STORE][m->op_shape.sel](w, s));
+          return DGW_OK;
+        });
+        tp.u = aux;
+        tp.u_base = cur;
+      }
+      if (!st)
+        st = timed(0, [&]() -> dgw_status {
+          if (hdg)
+            DGW_HIP(m->L->tck_hdg[m->tck_shape.sel](tp, s));
+          else
+            DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0][m->tck_shape.sel](tp, s));
+          return DGW_OK;
+        });
       OpParams p = op_params(m, B, src);
       p.u = aux;
       p.u_base = cur;
@@ -940,6 +981,7 @@ dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, d
   dgw_status st = check_mesh(m);
   if (st) return st;
   if (desc->scheme != DGW_SCHEME_LSRK54 && desc->scheme != DGW_SCHEME_ADER) return fail(DGW_EINVAL, "bad scheme");
+  if (desc->scheme == DGW_SCHEME_ADER && (st = check_ader_flags(desc->ader_flags, desc->sources))) return st;
   const double span = desc->t_end - desc->t0;
   if (!(span > 0) || !std::isfinite(span)) return fail(DGW_EINVAL, "t_end must exceed t0");
   double dt = desc->dt > 0 ? desc->dt : desc->courant * m->hs.dt_unit;

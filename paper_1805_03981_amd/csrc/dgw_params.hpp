@@ -58,8 +58,9 @@ struct OpParams {
 };
 
 struct TckParams {
-  const double* u;        // [B][nc][d+1][np] GL
+  const double* u;        // [B][nc][d+1][np] GL (HDG-ADER: W = L u, may alias I)
   double* I;              // [B][nc][d+1][np] GL, time-integrated Taylor sum
+  const double* u_base;   // HDG-ADER only: u, for the dt u term of I
   const double* geo_lev[kMaxLevels];  // level 0 = geo_cell; [nc][d*d+2][m_l^d]
   int64_t nc;
   int cpw, groups, B;
@@ -85,6 +86,7 @@ using EnergyLaunch = hipError_t (*)(const EnergyParams&, hipStream_t);
 struct Launchers {
   OpLaunch op[3][2];      // [Epilogue][sel]
   TckLaunch tck[2][2];    // [0 reduction, 1 no reduction][sel]
+  TckLaunch tck_hdg[2];   // HDG-ADER variant (with reduction) [sel]
   EnergyLaunch energy;
   int cpw[2];
   int op_lds_per_cell;    // bytes of LDS per cell

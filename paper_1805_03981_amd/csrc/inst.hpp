@@ -23,14 +23,14 @@ hipError_t launch_op(const OpParams& p, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int D, int N, typename T, bool R, int SEL>
+template <int D, int N, typename T, bool R, int SEL, bool HDG = false>
 hipError_t launch_tck(const TckParams& p, hipStream_t s) {
   constexpr int CPW = cells_per_group(D, N, SEL);
   if (p.cpw != CPW) return hipErrorInvalidValue;
   const size_t lds = (size_t)CPW * TckLayout<D, N, T>::bytes_per_cell(R);
-  hipError_t e = ensure_lds(tck_kernel<D, N, T, R, CPW>, lds);
+  hipError_t e = ensure_lds(tck_kernel<D, N, T, R, CPW, HDG>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((tck_kernel<D, N, T, R, CPW>), dim3(p.groups * p.B), dim3(tck_threads(D, N)), lds, s, p);
+  hipLaunchKernelGGL((tck_kernel<D, N, T, R, CPW, HDG>), dim3(p.groups * p.B), dim3(tck_threads(D, N)), lds, s, p);
   return hipGetLastError();
 }
 
@@ -51,6 +51,7 @@ const Launchers* make_launchers() {
        {launch_op<D, N, T, EPI_ADD, 0>, launch_op<D, N, T, EPI_ADD, 1>}},
       {{launch_tck<D, N, T, true, 0>, launch_tck<D, N, T, true, 1>},
        {launch_tck<D, N, T, false, 0>, launch_tck<D, N, T, false, 1>}},
+      {launch_tck<D, N, T, true, 0, true>, launch_tck<D, N, T, true, 1, true>},
       launch_energy<D, N, T>,
       {cells_per_group(D, N, 0), cells_per_group(D, N, 1)},
       (int)(OpLayout<D, N, T>::per_cell * sizeof(T)),

@@ -790,7 +790,11 @@ constexpr int tck_waves_per_simd() {
   return wg < 1 ? 1 : (wg > 5 ? 5 : wg);
 }
 
-template <int D, int N, typename T, bool REDUCE, int CPW>
+// HDG = true: the HDG-ADER variant (Sec. 2.4, eq. hdg-ader).  p.u holds the
+// DG derivative W = L u (the first time derivative), the recursion starts at
+// the second derivative, and I = dt u + sum_{m>=1} dt^{m+1}/(m+1)! ut^m with
+// the dt u term added in the GL basis from p.u_base.
+template <int D, int N, typename T, bool REDUCE, int CPW, bool HDG = false>
 __global__ void __launch_bounds__(tck_threads(D, N))
 __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW>()))) tck_kernel(TckParams p) {
   using K = Tck<D, N, T, REDUCE, CPW>;
@@ -831,17 +835,21 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW>()))) tck_ker
   }
   __syncthreads();
   tensor_apply_inplace<NT, D, N, T>(C, ncl * NC, tab + tab_S(N));
-  // m = 0 term: dt u_G
+  // first term of the sum: dt u_G (ADER), dt^2/2 W_G (HDG-ADER)
+  const double c0 = HDG ? 0.5 * p.dt * p.dt : p.dt;
 #pragma unroll
   for (int s = 0; s < PS0; ++s) {
     const int i = threadIdx.x + s * NT;
     if (i < ncl * NP) {
       const int c = i / NP, q = i - c * NP;
 #pragma unroll
-      for (int v = 0; v < NC; ++v) R.A[0][s][v] = p.dt * (double)C[(c * NC + v) * NP + q];
+      for (int v = 0; v < NC; ++v) R.A[0][s][v] = c0 * (double)C[(c * NC + v) * NP + q];
     }
   }
-  K::template step<1, 0>(p, C, Db, R, cell0, ncl, member);
+  if constexpr (HDG)
+    K::template step<2, 0>(p, C, Db, R, cell0, ncl, member);
+  else
+    K::template step<1, 0>(p, C, Db, R, cell0, ncl, member);
   __syncthreads();  // the last accumulation may still read C
   // collapse the coarser levels into level 0, add A_0 in FP64, then G -> GL in FP64
   K::template collapse<TckRegs<D, N, CPW, REDUCE>::NLV - 1>(p, C, Db, R, ncl);
@@ -860,7 +868,11 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW>()))) tck_ker
   }
   __syncthreads();
   tensor_apply_inplace<NT, D, N, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
-  for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i];
+  if constexpr (HDG) {
+    for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i] + p.dt * p.u_base[gofs + i];
+  } else {
+    for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i];
+  }
 }
 
 // ------------------------------------------------------------------------

@@ -152,6 +152,42 @@ def test_ader_step_fp64(gpu_lib, dim, nc, k, reduce):
     assert rel(u[0].cpu().numpy(), want) < TOL
 
 
+@pytest.mark.parametrize("dim,nc,k,bc", [(2, 4, 3, None), (3, 3, 3, None), (3, 2, 5, ("wall", "periodic", "absorbing")),
+                                       (2, 3, 8, None)])
+def test_hdg_ader_step_fp64(gpu_lib, dim, nc, k, bc):
+    """HDG-ADER (Sec. 2.4): operator sweep, TCK from the DG derivative, update."""
+    say("hdg ader", dim, nc, k, bc)
+    gm, om = build(gpu_lib, dim, nc, k, 0.05, bc=bc)
+    U = om.interpolate(lambda x: W.gaussian_pulse(x, [0.6] * dim, 0.15))
+    U = U + 0.01 * W.random_state(18, U.shape)
+    dt = 0.2 * gm.info.dt_unit
+    u = to_dev(U)[None]
+    gm.step_ader(u, 0.0, dt, 2, flags=gpu_lib.ADER_HDG)
+    want = U
+    for s in range(2):
+        want = ader.hdg_ader_step(om, want, dt)
+    assert rel(u[0].cpu().numpy(), want) < TOL
+    # and it is not the plain ADER step
+    v = to_dev(U)[None]
+    gm.step_ader(v, 0.0, dt, 2)
+    assert rel(v[0].cpu().numpy(), u[0].cpu().numpy()) > 1e-9
+
+
+def test_hdg_ader_rejects_unsupported(gpu_lib):
+    say("hdg ader unsupported")
+    gm, om = build(gpu_lib, 3, 2, 3, 0.05)
+    u = to_dev(np.zeros((1,) + gm.shape))
+    with pytest.raises(gpu_lib.DgwError) as e:
+        gm.step_ader(u, 0.0, 1e-3, 1, flags=gpu_lib.ADER_HDG | gpu_lib.ADER_NOREDUCE)
+    assert e.value.status == gpu_lib.EUNSUPPORTED
+    src = gpu_lib.Sources(gm, W.random_points(3, 1, 3), frequency=4.0)
+    with pytest.raises(gpu_lib.DgwError) as e:
+        gm.step_ader(u, 0.0, 1e-3, 1, flags=gpu_lib.ADER_HDG, sources=src)
+    assert e.value.status == gpu_lib.EUNSUPPORTED
+    prof = gm.profile(u, gpu_lib.ADER, 0.0, 1e-3, 2, ader_flags=gpu_lib.ADER_HDG)
+    assert set(prof) == {"tck", "operator_ader_update", "operator_store"}
+
+
 def test_batch_members_equal_solo_runs(gpu_lib):
     say("batch")
     dim, nc, k, Bn = 3, 3, 3, 3

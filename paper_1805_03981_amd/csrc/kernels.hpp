@@ -209,6 +209,18 @@ struct OpLayout {
   static constexpr int per_cell = 3 * NC * NP + NFACE * NC * NF;  // elements of T
 };
 
+// Register budget of the operator sweep with the plain store epilogue, as
+// for the TCK below: with one cell point per thread of a 256-thread group,
+// compiled for the waves per SIMD its LDS allows (at most 5); measured 7 %
+// faster at k = 5.  The LSRK and ADER epilogues keep their state operands
+// in registers across the sweep and would spill under that budget.
+template <int D, int N, typename T, int EPI, int CPW>
+constexpr int op_waves_per_simd() {
+  if (EPI != EPI_STORE || op_threads(D, N) != 256 || cdiv(CPW * ipow(N, D), 256) > 1) return 1;
+  const int wg = (160 * 1024) / (CPW * OpLayout<D, N, T>::per_cell * (int)sizeof(T));
+  return wg < 1 ? 1 : (wg > 5 ? 5 : wg);
+}
+
 __device__ __forceinline__ int dir_stride(int n, int dir) { return dir == 0 ? 1 : (dir == 1 ? n : n * n); }
 
 // Offset of the start of the line along `dir` through tangential face index
@@ -285,7 +297,8 @@ __device__ __forceinline__ void op_points(const double (&g)[PS][D * D + 2], cons
 }
 
 template <int D, int N, typename T, int EPI, int CPW>
-__global__ void __launch_bounds__(op_threads(D, N)) op_kernel(OpParams p) {
+__global__ void __launch_bounds__(op_threads(D, N))
+__attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_kernel(OpParams p) {
   using Lay = OpLayout<D, N, T>;
   constexpr int NC = Lay::NC, NP = Lay::NP, NF = Lay::NF, NFACE = Lay::NFACE, G2 = D * D + 2;
   constexpr int NT = op_threads(D, N);

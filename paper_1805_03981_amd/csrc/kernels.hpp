@@ -681,12 +681,14 @@ struct Tck {
     }
   }
 
-  // time derivative M at level index L (NL = N - 2L points), current in C
+  // time derivative M at level index L (NL = N - 2L points), current in C.
+  // A derivative that would be projected below one point per direction is
+  // zero (and so is every later one): the recursion stops before it.
   template <int M, int L>
   __device__ static __forceinline__ void step(const TckParams& p, T* C, T* const* Db, Regs& R, int64_t cell0,
                                               int ncl, int member) {
     constexpr int NL = N - 2 * L;
-    if constexpr (M <= N && NL >= 1) {
+    if constexpr (M <= N && NL >= 1 && !(REDUCE && M % 2 == 0 && NL - 2 < 1)) {
       constexpr int NPL = ipow(NL, D);
       constexpr int PSL = cdiv(CPW * NPL, NT);
       constexpr bool PROJECT = REDUCE && (M % 2 == 0);

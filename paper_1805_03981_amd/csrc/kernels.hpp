@@ -795,14 +795,18 @@ struct Tck {
 // Register budget of the TCK: with one point per thread the kernel is
 // compiled for the waves per SIMD that the LDS of one workgroup allows (a
 // 256-thread group puts one wave on each SIMD; 160 KiB of LDS per CU),
-// capped at 5 (at most 102 VGPRs), so that the registers never limit
-// occupancy below the LDS.  With more points per thread the registers hold
-// several metric sets and no budget is imposed (it would spill).
+// capped at 5 (at most 96 VGPRs) in FP64 and 6 (80 VGPRs) with FP32 tiles,
+// so that the registers limit occupancy as little as they can without
+// spilling much (FP32 at 6 waves spills 12 bytes per lane and still runs 8 %
+// faster at k = 5; 8 waves spills 72 and runs 30 % slower).  With more
+// points per thread the registers hold several metric sets and no budget is
+// imposed (it would spill).
 template <int D, int N, typename T, int CPW>
 constexpr int tck_waves_per_simd() {
   if (tck_threads(D, N) != 256 || cdiv(CPW * ipow(N, D), 256) > 1) return 1;
   const int wg = (160 * 1024) / (CPW * TckLayout<D, N, T>::bytes_per_cell(true));
-  return wg < 1 ? 1 : (wg > 5 ? 5 : wg);
+  const int cap = sizeof(T) == 4 ? 6 : 5;
+  return wg < 1 ? 1 : (wg > cap ? cap : wg);
 }
 
 // HDG = true: the HDG-ADER variant (Sec. 2.4, eq. hdg-ader).  p.u holds the

@@ -24,6 +24,12 @@ interpolant at the k+1 Gauss points.  A projection to fewer than one point
 per direction (and every later term) is zero.  With `reduce=False`
 (Alg. 2 only) every level has k+1 points and nothing is projected.
 
+Reduction period (the ablation of Sec. 3.3): the text first describes a
+projection P_{k-i+1}^{k-i} after every derivative and then proposes every
+second one (Alg. 3).  With period R the derivative m is projected by R
+points when m is a multiple of R, so deg ut^m = k - R floor(m/R): R = 1 is
+the every-step variant (deg k - m), R = 2 Alg. 3, R = 3 every third.
+
 Everything is built from dense d-dimensional tables evaluated directly.
 """
 from __future__ import annotations
@@ -36,24 +42,24 @@ from . import basis
 from .operator import apply_operator, tables
 
 
-def levels(k, reduce=True):
+def levels(k, reduce=True, period=2):
     """Points per direction n_m of the time derivatives m = 0..k+1 (0 = vanished)."""
     out = [k + 1]
     for m in range(1, k + 2):
         n = out[-1]
-        if reduce and m % 2 == 0:
-            n = n - 2
+        if reduce and m % period == 0:
+            n = n - period
         out.append(max(n, 0))
     return out
 
 
-def projection_table(n, d):
+def projection_table(n, d, drop=2):
     """Dense L2 projection (reference cell, unit weight) from Q_{n-1} (values at the
-    n^d Gauss points) onto Q_{n-3} (values at the (n-2)^d Gauss points):
+    n^d Gauss points) onto Q_{n-1-drop} (values at the (n-drop)^d Gauss points):
     solve the normal equations with mass matrix int l_a l_b and right-hand side
     int l_a l_j, both by an over-integrating Gauss rule."""
     xs, _ = basis.gauss(n)
-    xr, _ = basis.gauss(n - 2)
+    xr, _ = basis.gauss(n - drop)
     xo, wo = basis.gauss(n + 2)
     pts = basis.tensor_points(xo, d)
     w = basis.tensor_weights(wo, d)
@@ -65,10 +71,11 @@ def projection_table(n, d):
 
 
 class AderTables:
-    def __init__(self, mesh, reduce=True):
+    def __init__(self, mesh, reduce=True, period=2):
         d, k = mesh.dim, mesh.k
-        self.levels = levels(k, reduce)
+        self.levels = levels(k, reduce, period)
         self.reduce = reduce
+        self.period = period
         self.pts = {}
         self.D = {}
         self.E = {}
@@ -80,14 +87,14 @@ class AderTables:
             self.D[n] = basis.tensor_basis_grad(x, p) if n > 1 else [np.zeros((1, 1))] * d
             self.E[n] = basis.tensor_basis(x, mesh.cell_ref)          # level n -> k+1 Gauss points
             self.from_gl[n] = basis.tensor_basis(mesh.xgl, p)           # GL coefficients -> level points
-        self.P = {n: projection_table(n, d) for n in self.pts if n - 2 >= 1}
+        self.P = {n: projection_table(n, d, period) for n in self.pts if n - period >= 1}
 
 
-def ader_tables(mesh, reduce=True):
-    key = ("ader", reduce)
+def ader_tables(mesh, reduce=True, period=2):
+    key = ("ader", reduce, period)
     t = mesh._cache.get(key)
     if t is None:
-        t = AderTables(mesh, reduce)
+        t = AderTables(mesh, reduce, period)
         mesh._cache[key] = t
     return t
 
@@ -128,15 +135,16 @@ def minus_s_local(mesh, cells, ut, n, T):
     return w
 
 
-def tck(mesh, U, dt, cells=None, reduce=True, source_terms=None):
+def tck(mesh, U, dt, cells=None, reduce=True, source_terms=None, period=2):
     """Time-integrated Taylor sum I (GL coefficients, float64[C][d+1][np]).
 
     source_terms: optional callable (cells, m, n) -> additive p-values at the
     level-n points of the (m-1)-th recursion step, float64[C][n^d] (the
-    point-source injection); None for no source.
+    point-source injection); None for no source.  period: the reduction
+    period (module docstring).
     """
     d, k = mesh.dim, mesh.k
-    T = ader_tables(mesh, reduce)
+    T = ader_tables(mesh, reduce, period)
     Tb = tables(mesh)
     cells = np.arange(mesh.nc) if cells is None else np.atleast_1d(np.asarray(cells, dtype=np.int64))
     ut = np.einsum("qi,cvi->cvq", Tb.phi, np.asarray(U)[cells])   # ut^0 at the k+1 Gauss points
@@ -149,8 +157,8 @@ def tck(mesh, U, dt, cells=None, reduce=True, source_terms=None):
         w = minus_s_local(mesh, cells, ut, n, T)
         if source_terms is not None:
             w[:, d] += source_terms(cells, m, n)
-        if reduce and m % 2 == 0:
-            if n - 2 < 1:
+        if reduce and m % period == 0:
+            if n - period < 1:
                 break
             ut = np.einsum("rq,cvq->cvr", T.P[n], w)
         else:
@@ -162,10 +170,10 @@ def tck(mesh, U, dt, cells=None, reduce=True, source_terms=None):
     return np.ascontiguousarray(np.swapaxes(Ig, -1, -2))
 
 
-def ader_step(mesh, U, dt, flux="upwind", reduce=True, source=None, t=0.0):
+def ader_step(mesh, U, dt, flux="upwind", reduce=True, source=None, t=0.0, period=2):
     """One ADER step u + L_h(I) (+ the exact time integral of the source)."""
     st = None if source is None else source.tck_terms(mesh, t)
-    I = tck(mesh, U, dt, reduce=reduce, source_terms=st)
+    I = tck(mesh, U, dt, reduce=reduce, source_terms=st, period=period)
     out = np.asarray(U, dtype=np.float64) + apply_operator(mesh, I, flux=flux)
     if source is not None:
         out = out + source.integral(t, t + dt) * source.vector_full(mesh)

@@ -105,8 +105,10 @@ def _pad(cf, shape):
     return out
 
 
-@pytest.mark.parametrize("dim,k,reduce", [(2, 3, True), (2, 4, True), (2, 4, False), (3, 2, True), (3, 3, False)])
-def test_tck_exact_on_polynomials(dim, k, reduce):
+@pytest.mark.parametrize("dim,k,reduce,period", [(2, 3, True, 2), (2, 4, True, 2), (2, 4, False, 2), (3, 2, True, 2),
+                                                (3, 3, False, 2), (2, 4, True, 1), (3, 3, True, 1), (2, 5, True, 3),
+                                                (3, 4, True, 3)])
+def test_tck_exact_on_polynomials(dim, k, reduce, period):
     """Affine cells, constant rho, c: for a total-degree-k polynomial state the
     m-th derivative has total degree k-m, so neither the collocated evaluation
     nor the projections lose anything and I must equal the exact Taylor
@@ -118,7 +120,7 @@ def test_tck_exact_on_polynomials(dim, k, reduce):
     xn = m.node_points()
     U = np.stack([_polyval(cf, xn) for cf in st], axis=1)
     dt = 0.37
-    I = ader.tck(m, U, dt, reduce=reduce)
+    I = ader.tck(m, U, dt, reduce=reduce, period=period)
     want = np.zeros_like(U)
     cur = st
     for j in range(k + 2):
@@ -135,6 +137,9 @@ def test_tck_reduction_changes_general_states():
     a = ader.tck(m, U, 0.05, reduce=True)
     b = ader.tck(m, U, 0.05, reduce=False)
     assert norms.rel_l2(a, b) > 1e-8
+    for period in (1, 3):
+        c = ader.tck(m, U, 0.05, reduce=True, period=period)
+        assert norms.rel_l2(c, a) > 1e-8 and norms.rel_l2(c, b) > 1e-8
 
 
 def test_ader_levels():
@@ -142,34 +147,38 @@ def test_ader_levels():
     assert ader.levels(4) == [5, 5, 3, 3, 1, 1]
     assert ader.levels(7) == [8, 8, 6, 6, 4, 4, 2, 2, 0]
     assert ader.levels(3, reduce=False) == [4] * 5
+    assert ader.levels(5, period=1) == [6, 5, 4, 3, 2, 1, 0]
+    assert ader.levels(5, period=3) == [6, 6, 6, 3, 3, 3, 0]
+    assert ader.levels(7, period=3) == [8, 8, 8, 5, 5, 5, 2, 2, 2]
 
 
-def test_projection_is_legendre_truncation():
-    """P_{n->n-2} keeps Legendre modes below n-2 and removes the two highest (1D and 2D)."""
+@pytest.mark.parametrize("drop", [1, 2, 3])
+def test_projection_is_legendre_truncation(drop):
+    """P_{n->n-drop} keeps Legendre modes below n-drop and removes the highest ones (2D)."""
     n = 6
     xs = basis.gauss(n)[0]
-    xr = basis.gauss(n - 2)[0]
+    xr = basis.gauss(n - drop)[0]
     from numpy.polynomial import legendre as Lg
     rng = np.random.default_rng(0)
     coef = rng.standard_normal((n, n))
     f = Lg.legval2d(2 * basis.tensor_points(xs, 2)[:, 0] - 1, 2 * basis.tensor_points(xs, 2)[:, 1] - 1, coef)
     tr = coef.copy()
-    tr[n - 2:, :] = 0
-    tr[:, n - 2:] = 0
+    tr[n - drop:, :] = 0
+    tr[:, n - drop:] = 0
     g = Lg.legval2d(2 * basis.tensor_points(xr, 2)[:, 0] - 1, 2 * basis.tensor_points(xr, 2)[:, 1] - 1, tr)
-    got = ader.projection_table(n, 2) @ f
+    got = ader.projection_table(n, 2, drop) @ f
     assert np.allclose(got, g, atol=1e-12)
 
 
-@pytest.mark.parametrize("k", [2, 3])
-def test_ader_joint_convergence(k):
+@pytest.mark.parametrize("k,period", [(2, 2), (3, 2), (3, 1), (3, 3)])
+def test_ader_joint_convergence(k, period):
     errs = []
     for nc in (4, 8):
         m = Mesh(2, k, W.box_nodes(2, nc, k, 0.0), W.box_neighbors(2, nc), W.ConstantMaterial())
         U = m.interpolate(lambda x: W.standing_wave_2d(x, 0.0))
         dt, ns = ts.dt_from_courant(m, 0.1, 0.2)
         for s in range(ns):
-            U = ader.ader_step(m, U, dt)
+            U = ader.ader_step(m, U, dt, period=period)
         errs.append(norms.l2_error(m, U, W.standing_wave_2d, 0.2)[0])
     assert np.log2(errs[0] / errs[1]) > k + 1 - 0.3
 

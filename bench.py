@@ -263,8 +263,9 @@ def ablations(steps=10, warmup=2):
     """The paper's ablations on the c2 workload, FP64: LSRK(5,4) with the
     vector update fused into the operator sweep, merged into one separate pass
     (the paper's optimized updater) or as three BLAS-1 passes (its standard
-    one); ADER with and without the degree reduction, and the HDG-ADER
-    variant (one more operator sweep per step).  Per variant: ms per step
+    one); ADER with the degree reduction every second derivative (Alg. 3),
+    every derivative, every third and without, and the HDG-ADER variant (one
+    more operator sweep per step).  Per variant: ms per step
     and the mean duration of each component."""
     import torch
     from paper_1805_03981_amd import binding as dg
@@ -274,7 +275,9 @@ def ablations(steps=10, warmup=2):
     out = {}
     variants = [("lsrk_fused", dg.LSRK54, None), ("lsrk_merged_vu", dg.LSRK54_MERGED_VU, None),
                 ("lsrk_standard_vu", dg.LSRK54_STANDARD_VU, None), ("ader_reduce", dg.ADER, dg.ADER_REDUCE),
-                ("ader_noreduce", dg.ADER, dg.ADER_NOREDUCE), ("ader_hdg", dg.ADER, dg.ADER_HDG)]
+                ("ader_noreduce", dg.ADER, dg.ADER_NOREDUCE),
+                ("ader_reduce_every_step", dg.ADER, dg.ADER_REDUCE_EVERY_STEP),
+                ("ader_reduce_every_third", dg.ADER, dg.ADER_REDUCE_EVERY_THIRD), ("ader_hdg", dg.ADER, dg.ADER_HDG)]
     for name, scheme, flags in variants:
         dt = CR["ader" if scheme == dg.ADER else "lsrk"] * mesh.info.dt_unit
         u = u0.clone()

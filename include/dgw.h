@@ -72,6 +72,15 @@ enum { DGW_SCHEME_LSRK54_MERGED_VU = 2, DGW_SCHEME_LSRK54_STANDARD_VU = 3 };
  * only (DGW_ADER_HDG | DGW_ADER_NOREDUCE: DGW_EUNSUPPORTED) and without
  * sources (DGW_EUNSUPPORTED). */
 enum { DGW_ADER_REDUCE = 0, DGW_ADER_NOREDUCE = 1, DGW_ADER_HDG = 2 };
+/* Reduction period of the TCK for the ablation of Sec. 3.3 (at most one of
+ * these and DGW_ADER_NOREDUCE): DGW_ADER_REDUCE_EVERY_STEP projects every
+ * time derivative by one point per direction (the variant the section
+ * starts from), DGW_ADER_REDUCE_EVERY_THIRD every third derivative by three;
+ * the default projects every second by two (Alg. 3).  The metric of those
+ * reduced Gauss sets is built on the host at the first step that needs it
+ * (the mesh's material callback and context must still be valid then), and
+ * kept with the mesh.  No sources, no HDG-ADER (DGW_EUNSUPPORTED). */
+enum { DGW_ADER_REDUCE_EVERY_STEP = 4, DGW_ADER_REDUCE_EVERY_THIRD = 8 };
 /* Boundary codes of the neighbour table.  The paper leaves the boundary
  * conditions open (Sec. 2); the exterior state of a boundary face is built
  * from the own trace and goes through the interior flux with the own

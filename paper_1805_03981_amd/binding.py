@@ -25,6 +25,7 @@ FP64, FP32_SPLIT = 0, 1
 LSRK54, ADER = 0, 1
 LSRK54_MERGED_VU, LSRK54_STANDARD_VU = 2, 3   # unfused LSRK variants (ablation)
 ADER_REDUCE, ADER_NOREDUCE, ADER_HDG = 0, 1, 2
+ADER_REDUCE_EVERY_STEP, ADER_REDUCE_EVERY_THIRD = 4, 8
 DEVICE_NONE = -1
 GET_NODE_COORDS, GET_CELL_METRIC, GET_FACE, GET_LEVEL0 = 0, 1, 2, 16
 

@@ -141,11 +141,20 @@ static OpParams op_params(const dgw_mesh* m, int B, const dgw_sources* src) {
   return p;
 }
 
-static TckParams tck_params(const dgw_mesh* m, int B, const dgw_sources* src) {
+// Device metric of the m^d Gauss set: a level of the mesh's own reduction
+// (period 2, built with the mesh) or one built for another period.
+static const double* level_metric(const dgw_mesh* m, int pts) {
+  const int n = m->hs.n;
+  if (pts == n) return m->d_cell;
+  if ((n - pts) % 2 == 0 && m->d_level[(n - pts) / 2]) return m->d_level[(n - pts) / 2];
+  return m->d_level_pts[pts];
+}
+
+static TckParams tck_params(const dgw_mesh* m, int B, const dgw_sources* src, int period = 2) {
   TckParams p;
   std::memset(&p, 0, sizeof(p));
-  p.geo_lev[0] = m->d_cell;
-  for (int l = 1; l < kMaxLevels; ++l) p.geo_lev[l] = m->d_level[l];
+  for (int l = 0; l < num_levels_r(m->hs.n, period) && l < kMaxLevels; ++l)
+    p.geo_lev[l] = level_metric(m, m->hs.n - period * l);
   p.nc = m->hs.nc;
   p.cpw = m->L->cpw[m->tck_shape.sel];
   p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
@@ -224,17 +233,64 @@ static dgw_status lsrk_vector_update(int scheme, int stage, double dt, double* u
 }
 
 static dgw_status check_ader_flags(int flags, const dgw_sources* src) {
-  if (flags & ~(DGW_ADER_NOREDUCE | DGW_ADER_HDG)) return fail(DGW_EINVAL, "unknown ADER flags");
-  if ((flags & DGW_ADER_HDG) && (flags & DGW_ADER_NOREDUCE))
-    return fail(DGW_EUNSUPPORTED, "HDG-ADER is built with the degree reduction only");
+  const int periods = DGW_ADER_NOREDUCE | DGW_ADER_REDUCE_EVERY_STEP | DGW_ADER_REDUCE_EVERY_THIRD;
+  if (flags & ~(periods | DGW_ADER_HDG)) return fail(DGW_EINVAL, "unknown ADER flags");
+  const int pf = flags & periods;
+  if (pf & (pf - 1)) return fail(DGW_EINVAL, "at most one of the reduction flags");
+  if ((flags & DGW_ADER_HDG) && pf)
+    return fail(DGW_EUNSUPPORTED, "HDG-ADER is built with the reduction every second derivative only");
   if ((flags & DGW_ADER_HDG) && src) return fail(DGW_EUNSUPPORTED, "HDG-ADER takes no sources");
+  if ((flags & (DGW_ADER_REDUCE_EVERY_STEP | DGW_ADER_REDUCE_EVERY_THIRD)) && src)
+    return fail(DGW_EUNSUPPORTED, "sources need the reduction every second derivative (or none)");
   return DGW_OK;
+}
+
+// reduction period of the TCK selected by the ADER flags
+static int ader_period(int flags) {
+  if (flags & DGW_ADER_NOREDUCE) return 0;
+  if (flags & DGW_ADER_REDUCE_EVERY_STEP) return 1;
+  if (flags & DGW_ADER_REDUCE_EVERY_THIRD) return 3;
+  return 2;
+}
+
+// Builds (once) the metric of the reduced levels of a period other than the
+// mesh's own (host evaluation of the map and the material, then upload).
+static dgw_status ensure_period_levels(dgw_mesh* m, int period) {
+  const int n = m->hs.n;
+  for (int l = 1; l < num_levels_r(n, period); ++l) {
+    const int pts = n - period * l;
+    if (level_metric(m, pts)) continue;
+    std::vector<double> host;
+    dgw_status st = build_level_metric(m->hs, pts, host);
+    if (st) return st;
+    double* d = nullptr;
+    DGW_HIP(hipMalloc(&d, host.size() * sizeof(double)));
+    const hipError_t e = hipMemcpy(d, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return fail(DGW_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    m->d_level_pts[pts] = d;
+    m->device_bytes += (int64_t)(host.size() * sizeof(double));
+  }
+  return DGW_OK;
+}
+
+// launch shape of the TCK for a period: the tuned one unless its LDS (the
+// every-derivative sums live there) does not fit
+static int tck_sel(const dgw_mesh* m, int period) {
+  const int sel = m->tck_shape.sel;
+  return (int64_t)m->L->cpw[sel] * m->L->tck_lds_per_cell[period] <= kLdsLimit ? sel : 0;
 }
 
 static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* src, double t0, double dt,
                             int step_add, const long long* ctr, double*& cur, double*& oth, double* I,
                             hipStream_t s) {
-  TckParams tp = tck_params(m, B, src);
+  const int period = ader_period(flags);
+  TckParams tp = tck_params(m, B, src, period);
+  const int sel = tck_sel(m, period);
+  tp.cpw = m->L->cpw[sel];
+  tp.groups = (int)((m->hs.nc + tp.cpw - 1) / tp.cpw);
   tp.u = cur;
   tp.I = I;
   tp.dt = dt;
@@ -248,9 +304,9 @@ static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* sr
     DGW_HIP(m->L->op[EPI_STORE][m->op_shape.sel](w, s));
     tp.u = I;
     tp.u_base = cur;
-    DGW_HIP(m->L->tck_hdg[m->tck_shape.sel](tp, s));
+    DGW_HIP(m->L->tck_hdg[sel](tp, s));
   } else {
-    DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0][m->tck_shape.sel](tp, s));
+    DGW_HIP(m->L->tck[period][sel](tp, s));
   }
   OpParams p = op_params(m, B, src);
   p.u = I;
@@ -340,14 +396,14 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
         best_op.sel = sel;
       }
     }
-    if ((int64_t)cpw * m->L->tck_lds_per_cell <= lds_limit) {
+    if ((int64_t)cpw * m->L->tck_lds_per_cell[2] <= lds_limit) {
       TckParams p = tck_params(m, B, nullptr);
       p.cpw = cpw;
       p.groups = (int)((m->hs.nc + cpw - 1) / cpw);
       p.u = a;
       p.I = b;
       p.dt = 1e-3;
-      const float t = time_it([&]() { return m->L->tck[0][sel](p, s); });
+      const float t = time_it([&]() { return m->L->tck[2][sel](p, s); });
       if (t < t_tck) {
         t_tck = t;
         best_tck.sel = sel;
@@ -403,6 +459,7 @@ static void release(dgw_mesh* m) {
     (void)hipFree(m->d_face);
     (void)hipFree(m->d_nb);
     for (auto* p : m->d_level) (void)hipFree(p);
+    for (auto* p : m->d_level_pts) (void)hipFree(p);
     (void)hipFree(m->d_partial);
   }
   delete m;
@@ -480,7 +537,7 @@ dgw_status dgw_mesh_create(const dgw_mesh_desc* desc, dgw_mesh** out) {
     return fail(DGW_ENOMEM, "host allocation during setup");
   }
   m->op_shape = default_shape(m->L, m->L->op_lds_per_cell);
-  m->tck_shape = default_shape(m->L, m->L->tck_lds_per_cell);
+  m->tck_shape = default_shape(m->L, m->L->tck_lds_per_cell[2]);
   if (m->device >= 0) {
     if (hipSetDevice(m->device) != hipSuccess) return fail(DGW_EDEVICE, "hipSetDevice failed");
     dgw_status st = upload(m.get());
@@ -631,6 +688,7 @@ dgw_status dgw_step_ader(dgw_mesh* m, int flags, double t0, double dt, int nstep
   if ((st = check_step(m, dt, nsteps, u, work, B, src))) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
+  if ((st = ensure_period_levels(m, ader_period(flags)))) return st;
   hipStream_t s = (hipStream_t)stream;
   double* I = work;
   double* cur = u;
@@ -656,6 +714,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
   if (st) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
+  if (scheme == DGW_SCHEME_ADER && (st = ensure_period_levels(m, ader_period(flags)))) return st;
   hipStream_t s = (hipStream_t)stream;
   std::memset(out, 0, sizeof(*out));
   const char* names[3] = {"operator_lsrk", nullptr, nullptr};
@@ -710,7 +769,11 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
         std::swap(cur, oth);
       }
     } else {
-      TckParams tp = tck_params(m, B, src);
+      const int period = ader_period(flags);
+      const int sel = tck_sel(m, period);
+      TckParams tp = tck_params(m, B, src, period);
+      tp.cpw = m->L->cpw[sel];
+      tp.groups = (int)((m->hs.nc + tp.cpw - 1) / tp.cpw);
       tp.u = cur;
       tp.I = aux;
       tp.dt = dt;
@@ -729,9 +792,9 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
       if (!st)
         st = timed(0, [&]() -> dgw_status {
           if (hdg)
-            DGW_HIP(m->L->tck_hdg[m->tck_shape.sel](tp, s));
+            DGW_HIP(m->L->tck_hdg[sel](tp, s));
           else
-            DGW_HIP(m->L->tck[(flags & DGW_ADER_NOREDUCE) ? 1 : 0][m->tck_shape.sel](tp, s));
+            DGW_HIP(m->L->tck[period][sel](tp, s));
           return DGW_OK;
         });
       OpParams p = op_params(m, B, src);
@@ -778,7 +841,7 @@ dgw_status dgw_launch_shape(dgw_mesh* m, int which, int* cells_per_group, int* t
   if (!m || !cells_per_group || !threads || (which != 0 && which != 1)) return fail(DGW_EINVAL, "bad argument");
   LaunchShape& sh = which == 0 ? m->op_shape : m->tck_shape;
   if (*cells_per_group > 0) {
-    const int per_cell = which == 0 ? m->L->op_lds_per_cell : m->L->tck_lds_per_cell;
+    const int per_cell = which == 0 ? m->L->op_lds_per_cell : m->L->tck_lds_per_cell[2];
     int sel = -1;
     for (int c = 0; c < 2; ++c)
       if (m->L->cpw[c] == *cells_per_group && (int64_t)m->L->cpw[c] * per_cell <= kLdsLimit) sel = c;
@@ -994,6 +1057,7 @@ dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, d
   hipStream_t s = (hipStream_t)desc->stream;
   if (desc->autotune && !m->tuned)
     if ((st = autotune(m, B, s))) return st;
+  if (desc->scheme == DGW_SCHEME_ADER && (st = ensure_period_levels(m, ader_period(desc->ader_flags)))) return st;
   const int64_t ne = state_elems(m) * B;
   double* cur = u;
   double* oth = work + ne;

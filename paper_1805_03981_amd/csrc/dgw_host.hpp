@@ -48,6 +48,9 @@ struct HostSetup {
   void* material_ctx = nullptr;
 };
 dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs);
+// Metric and mass factors at the m^d Gauss points of every cell (layout of
+// HostSetup::level), for the reduced TCK levels of another period.
+dgw_status build_level_metric(const HostSetup& hs, int m, std::vector<double>& out);
 // Physical coordinates of the GL nodes, [nc][np][d].
 void node_coords(const HostSetup& hs, std::vector<double>& out);
 // Evaluate the map of one cell at a reference point: x[d], J[d][d].
@@ -69,7 +72,8 @@ struct dgw_mesh {
   // device memory owned by the mesh
   double* d_cell = nullptr;
   double* d_face = nullptr;
-  double* d_level[dgw::kMaxLevels] = {};
+  double* d_level[dgw::kMaxLevels] = {};     // reduced levels of period 2 (n - 2l points)
+  double* d_level_pts[dgw::kMaxLevels + 1] = {};  // other periods' levels, by points per direction
   int32_t* d_nb = nullptr;
   double* d_partial = nullptr;  // energy partial sums [max_batch][groups]
   int64_t device_bytes = 0;

@@ -8,7 +8,7 @@
 
 namespace dgw {
 
-constexpr int kMaxLevels = 5;
+constexpr int kMaxLevels = 9;  // TCK levels: up to k+1 with the reduction every derivative
 
 // Boundary codes of the neighbour table (DGW_BC_WALL, DGW_BC_ABSORBING).
 constexpr int kBcWall = -1, kBcAbsorbing = -2;
@@ -85,12 +85,12 @@ using EnergyLaunch = hipError_t (*)(const EnergyParams&, hipStream_t);
 // cpw[sel]); p.cpw must equal cpw[sel] of the launcher that is called.
 struct Launchers {
   OpLaunch op[3][2];      // [Epilogue][sel]
-  TckLaunch tck[2][2];    // [0 reduction, 1 no reduction][sel]
+  TckLaunch tck[4][2];    // [reduction period 0 (none), 1, 2 (Alg. 3), 3][sel]
   TckLaunch tck_hdg[2];   // HDG-ADER variant (with reduction) [sel]
   EnergyLaunch energy;
   int cpw[2];
   int op_lds_per_cell;    // bytes of LDS per cell
-  int tck_lds_per_cell;
+  int tck_lds_per_cell[4];  // per reduction period
   int energy_lds_per_cell;
 };
 
@@ -98,36 +98,51 @@ struct Launchers {
 const Launchers* launchers(int dim, int n, int precision);
 
 // Table layout (element offsets) of the 1D matrices for n = k+1 nodes.
-// S (n x n), S^-1 (n x n), D (n x n), LF0 (n), LF1 (n); then per reduced
-// level l = 1.. with m = n - 2l points and mp = n - 2(l-1):
-// D_l (m x m) collocation derivative, P_l (m x mp) projection from level
-// l-1, E_l (mp x m) interpolation back to level l-1, F_l (m x n) evaluation
-// of a level-0 Gauss polynomial at the level-l points.
+// S (n x n), S^-1 (n x n), D (n x n), LF0 (n), LF1 (n); then, for each
+// reduction period r of the TCK (r = 2 first, then 1 and 3), per reduced
+// level l = 1.. with m = n - r l >= 1 points and mp = m + r: D_l (m x m)
+// collocation derivative, P_l (m x mp) projection from level l-1, E_l
+// (mp x m) interpolation back to level l-1, F_l (m x n) evaluation of a
+// level-0 Gauss polynomial at the level-l points.
 __host__ __device__ constexpr int tab_S(int) { return 0; }
 __host__ __device__ constexpr int tab_Sinv(int n) { return n * n; }
 __host__ __device__ constexpr int tab_D(int n) { return 2 * n * n; }
 __host__ __device__ constexpr int tab_LF0(int n) { return 3 * n * n; }
 __host__ __device__ constexpr int tab_LF1(int n) { return 3 * n * n + n; }
-__host__ __device__ constexpr int tab_level(int n, int l) {
-  int off = 3 * n * n + 2 * n;
+// levels l = 0.. of period r with n - r l >= 1 points (r = 0: no reduction)
+__host__ __device__ constexpr int num_levels_r(int n, int r) { return r == 0 ? 1 : (n - 1) / r + 1; }
+__host__ __device__ constexpr int levels_block(int n, int r) {
+  int sz = 0;
+  for (int l = 1; l < num_levels_r(n, r); ++l) {
+    const int m = n - r * l, mp = m + r;
+    sz += m * m + m * mp + mp * m + m * n;
+  }
+  return sz;
+}
+__host__ __device__ constexpr int tab_levels_start(int n, int r) {
+  const int base = 3 * n * n + 2 * n;
+  return r == 2 ? base : (r == 1 ? base + levels_block(n, 2) : base + levels_block(n, 2) + levels_block(n, 1));
+}
+__host__ __device__ constexpr int tab_level(int n, int l, int r = 2) {
+  int off = tab_levels_start(n, r);
   for (int j = 1; j < l; ++j) {
-    const int m = n - 2 * j, mp = n - 2 * (j - 1);
+    const int m = n - r * j, mp = m + r;
     off += m * m + m * mp + mp * m + m * n;
   }
   return off;
 }
-__host__ __device__ constexpr int tab_level_D(int n, int l) { return tab_level(n, l); }
-__host__ __device__ constexpr int tab_level_P(int n, int l) {
-  return tab_level(n, l) + (n - 2 * l) * (n - 2 * l);
+__host__ __device__ constexpr int tab_level_D(int n, int l, int r = 2) { return tab_level(n, l, r); }
+__host__ __device__ constexpr int tab_level_P(int n, int l, int r = 2) {
+  return tab_level(n, l, r) + (n - r * l) * (n - r * l);
 }
-__host__ __device__ constexpr int tab_level_E(int n, int l) {
-  return tab_level_P(n, l) + (n - 2 * l) * (n - 2 * (l - 1));
+__host__ __device__ constexpr int tab_level_E(int n, int l, int r = 2) {
+  return tab_level_P(n, l, r) + (n - r * l) * (n - r * (l - 1));
 }
-__host__ __device__ constexpr int tab_level_F(int n, int l) {
-  return tab_level_E(n, l) + (n - 2 * (l - 1)) * (n - 2 * l);
+__host__ __device__ constexpr int tab_level_F(int n, int l, int r = 2) {
+  return tab_level_E(n, l, r) + (n - r * (l - 1)) * (n - r * l);
 }
-__host__ __device__ constexpr int num_levels(int n) { return (n + 1) / 2; }  // n, n-2, ... >= 1
-__host__ __device__ constexpr int tab_size(int n) { return tab_level(n, num_levels(n)); }
+__host__ __device__ constexpr int num_levels(int n) { return num_levels_r(n, 2); }  // n, n-2, ... >= 1
+__host__ __device__ constexpr int tab_size(int n) { return tab_levels_start(n, 3) + levels_block(n, 3); }
 // All degrees share one constant-memory table: n = 2..9 back to back.
 constexpr int kMinN = 2, kMaxN = 9;
 __host__ __device__ constexpr int tab_base(int n) {

@@ -23,7 +23,7 @@ hipError_t launch_op(const OpParams& p, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int D, int N, typename T, bool R, int SEL, bool HDG = false>
+template <int D, int N, typename T, int R, int SEL, bool HDG = false>
 hipError_t launch_tck(const TckParams& p, hipStream_t s) {
   constexpr int CPW = cells_per_group(D, N, SEL);
   if (p.cpw != CPW) return hipErrorInvalidValue;
@@ -49,13 +49,16 @@ const Launchers* make_launchers() {
       {{launch_op<D, N, T, EPI_STORE, 0>, launch_op<D, N, T, EPI_STORE, 1>},
        {launch_op<D, N, T, EPI_LSRK, 0>, launch_op<D, N, T, EPI_LSRK, 1>},
        {launch_op<D, N, T, EPI_ADD, 0>, launch_op<D, N, T, EPI_ADD, 1>}},
-      {{launch_tck<D, N, T, true, 0>, launch_tck<D, N, T, true, 1>},
-       {launch_tck<D, N, T, false, 0>, launch_tck<D, N, T, false, 1>}},
-      {launch_tck<D, N, T, true, 0, true>, launch_tck<D, N, T, true, 1, true>},
+      {{launch_tck<D, N, T, 0, 0>, launch_tck<D, N, T, 0, 1>},
+       {launch_tck<D, N, T, 1, 0>, launch_tck<D, N, T, 1, 1>},
+       {launch_tck<D, N, T, 2, 0>, launch_tck<D, N, T, 2, 1>},
+       {launch_tck<D, N, T, 3, 0>, launch_tck<D, N, T, 3, 1>}},
+      {launch_tck<D, N, T, 2, 0, true>, launch_tck<D, N, T, 2, 1, true>},
       launch_energy<D, N, T>,
       {cells_per_group(D, N, 0), cells_per_group(D, N, 1)},
       (int)(OpLayout<D, N, T>::per_cell * sizeof(T)),
-      TckLayout<D, N, T>::bytes_per_cell(true),
+      {TckLayout<D, N, T>::bytes_per_cell(0), TckLayout<D, N, T>::bytes_per_cell(1),
+       TckLayout<D, N, T>::bytes_per_cell(2), TckLayout<D, N, T>::bytes_per_cell(3)},
       (int)((D + 1) * ipow(N, D) * sizeof(T))};
   return &L;
 }

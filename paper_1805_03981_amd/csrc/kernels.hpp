@@ -563,25 +563,38 @@ template <int D, int N, typename T>
 struct TckLayout {
   static constexpr int NC = D + 1, NP = ipow(N, D), G2 = D * D + 2;
   static constexpr int tiles = 1 + D;  // C and the d derivative tiles (an FP64 tile fits in Db)
-  static constexpr int bytes_per_cell(bool /*reduce*/) { return tiles * NC * NP * (int)sizeof(T); }
+  // FP64 Taylor sums of the reduced levels kept in LDS (reduction every
+  // derivative: up to N levels, too many for registers), per cell
+  static constexpr int acc_elems(int rp) {
+    int e = 0;
+    if (rp == 1)
+      for (int l = 1; N - l >= 1; ++l) e += NC * ipow(N - l, D);
+    return e;
+  }
+  static constexpr int bytes_per_cell(int rp) { return tiles * NC * NP * (int)sizeof(T) + 8 * acc_elems(rp); }
 };
 
-template <int D, int N, int CPW, bool REDUCE>
+// RP: reduction period of the TCK (0: none, Alg. 2; 2: every second
+// derivative, Alg. 3; 1 and 3: every derivative / every third, the
+// ablation of Sec. 3.3); level L has N - RP L points per direction.
+template <int D, int N, int CPW, int RP>
 struct TckRegs {
   static constexpr int G2 = D * D + 2, NC = D + 1;
-  static constexpr int NLV = REDUCE ? (N + 1) / 2 : 1;
+  static constexpr int NLV = num_levels_r(N, RP);
+  static constexpr bool ACC_LDS = RP == 1;  // sums of levels >= 1 in LDS
   static constexpr int NT = tck_threads(D, N);
   static constexpr int PS0 = cdiv(CPW * ipow(N, D), NT);
-  double g[PS0][G2];        // metric and mass factors of the current level
-  double A[NLV][PS0][NC];   // Taylor sums per level (FP64)
+  double g[PS0][G2];                       // metric and mass factors of the current level
+  double A[ACC_LDS ? 1 : NLV][PS0][NC];    // Taylor sums per level (FP64)
+  double* acc;                             // LDS: sums of levels >= 1 when ACC_LDS
 };
 
-// metric and mass factors of level L (N - 2L points per direction) of the
+// metric and mass factors of level L (N - RP L points per direction) of the
 // group's cells into the registers of the threads that own the points
-template <int D, int N, int CPW, bool REDUCE, int L>
-__device__ __forceinline__ void tck_load_geo(TckRegs<D, N, CPW, REDUCE>& R, const TckParams& p, int64_t cell0,
+template <int D, int N, int CPW, int RP, int L>
+__device__ __forceinline__ void tck_load_geo(TckRegs<D, N, CPW, RP>& R, const TckParams& p, int64_t cell0,
                                              int ncl) {
-  constexpr int G2 = D * D + 2, NPL = ipow(N - 2 * L, D), NT = tck_threads(D, N);
+  constexpr int G2 = D * D + 2, NPL = ipow(N - RP * L, D), NT = tck_threads(D, N);
   constexpr int PSL = cdiv(CPW * NPL, NT);
 #pragma unroll
   for (int s = 0; s < PSL; ++s) {
@@ -593,17 +606,31 @@ __device__ __forceinline__ void tck_load_geo(TckRegs<D, N, CPW, REDUCE>& R, cons
   }
 }
 
-template <int D, int N, typename T, bool REDUCE, int CPW>
+template <int D, int N, typename T, int RP, int CPW>
 struct Tck {
   static constexpr int NC = D + 1, NP = ipow(N, D), G2 = D * D + 2, NT = tck_threads(D, N);
-  using Regs = TckRegs<D, N, CPW, REDUCE>;
+  using Regs = TckRegs<D, N, CPW, RP>;
 
   static constexpr double inv_fact(int m) {  // 1/(m+1)!
     double f = 1.0;
     for (int j = 2; j <= m + 1; ++j) f *= j;
     return 1.0 / f;
   }
-  static constexpr int npl(int L) { return ipow(N - 2 * L, D); }
+  static constexpr int npl(int L) { return ipow(N - RP * L, D); }
+  // offset of level L >= 1 in the LDS sums (elements per cell and component)
+  static constexpr int acc_before(int L) {
+    int e = 0;
+    for (int j = 1; j < L; ++j) e += npl(j);
+    return e;
+  }
+  // FP64 Taylor sum of level L at the s-th point (cell c, point q) of this thread
+  template <int L>
+  __device__ static __forceinline__ double& accum(Regs& R, int s, int c, int q, int v) {
+    if constexpr (L == 0 || !Regs::ACC_LDS)
+      return R.A[L][s][v];
+    else
+      return R.acc[CPW * NC * acc_before(L) + (c * NC + v) * npl(L) + q];
+  }
 
   // metric entry e of the s-th point of this thread on the current level
   __device__ static __forceinline__ double geo(const Regs& R, int s, int e) { return R.g[s][e]; }
@@ -687,18 +714,18 @@ struct Tck {
   template <int M, int L>
   __device__ static __forceinline__ void step(const TckParams& p, T* C, T* const* Db, Regs& R, int64_t cell0,
                                               int ncl, int member) {
-    constexpr int NL = N - 2 * L;
-    if constexpr (M <= N && NL >= 1 && !(REDUCE && M % 2 == 0 && NL - 2 < 1)) {
+    constexpr int NL = N - RP * L;
+    constexpr bool PROJECT = RP > 0 && M % (RP > 0 ? RP : 1) == 0;
+    if constexpr (M <= N && NL >= 1 && !(PROJECT && NL - RP < 1)) {
       constexpr int NPL = ipow(NL, D);
       constexpr int PSL = cdiv(CPW * NPL, NT);
-      constexpr bool PROJECT = REDUCE && (M % 2 == 0);
       const T* tab = ctab<T>(N);
       double dtp = 1.0;
 #pragma unroll
       for (int j = 0; j <= M; ++j) dtp *= p.dt;
       const double coef = inv_fact(M) * dtp;
       if constexpr (NL > 1) {
-        lines<NL>(C, Db[0], tab + (L == 0 ? tab_D(N) : tab_level_D(N, L)), ncl);
+        lines<NL>(C, Db[0], tab + (L == 0 ? tab_D(N) : tab_level_D(N, L, RP)), ncl);
         __syncthreads();
       }
       // point phase: ut^M = -mu * metric(derivatives) + s^(M-1)(t) g, into C
@@ -734,17 +761,17 @@ struct Tck {
           for (int v = 0; v < NC; ++v) {
             const T wt = (T)w[v];
             C[(c * NC + v) * NP + q] = wt;
-            if constexpr (!PROJECT) R.A[L][s][v] += coef * (double)wt;
+            if constexpr (!PROJECT) accum<L>(R, s, c, q, v) += coef * (double)wt;
           }
         }
       }
       // the last use of this level's metric: request the next level's
-      if constexpr (PROJECT && NL - 2 >= 1) tck_load_geo<D, N, CPW, REDUCE, L + 1>(R, p, cell0, ncl);
+      if constexpr (PROJECT && NL - RP >= 1) tck_load_geo<D, N, CPW, RP, L + 1>(R, p, cell0, ncl);
       __syncthreads();
       if constexpr (PROJECT) {
-        constexpr int NR = NL - 2;
+        constexpr int NR = NL - RP;
         if constexpr (NR >= 1) {
-          tensor_map<NL, NR>(C, Db[0], Db[1], ncl, tab + tab_level_P(N, L + 1));
+          tensor_map<NL, NR>(C, Db[0], Db[1], ncl, tab + tab_level_P(N, L + 1, RP));
           constexpr int PSR = cdiv(CPW * ipow(NR, D), NT);
 #pragma unroll
           for (int s = 0; s < PSR; ++s) {
@@ -752,7 +779,7 @@ struct Tck {
             if (i < ncl * ipow(NR, D)) {
               const int c = i / ipow(NR, D), q = i - c * ipow(NR, D);
 #pragma unroll
-              for (int v = 0; v < NC; ++v) R.A[L + 1][s][v] += coef * (double)C[(c * NC + v) * NP + q];
+              for (int v = 0; v < NC; ++v) accum<L + 1>(R, s, c, q, v) += coef * (double)C[(c * NC + v) * NP + q];
             }
           }
           step<M + 1, L + 1>(p, C, Db, R, cell0, ncl, member);
@@ -780,13 +807,13 @@ struct Tck {
           for (int v = 0; v < NC; ++v) {
             T* x = C + (c * NC + v) * NP + q;
             const double prev = (L == NLV - 1) ? 0.0 : (double)*x;
-            *x = (T)(prev + R.A[L][s][v]);
+            *x = (T)(prev + accum<L>(R, s, c, q, v));
           }
         }
       }
       __syncthreads();
       const T* tab = ctab<T>(N);
-      tensor_map<N - 2 * L, N - 2 * (L - 1)>(C, Db[0], Db[1], ncl, tab + tab_level_E(N, L));
+      tensor_map<N - RP * L, N - RP * (L - 1)>(C, Db[0], Db[1], ncl, tab + tab_level_E(N, L, RP));
       collapse<L - 1>(p, C, Db, R, ncl);
     }
   }
@@ -801,10 +828,10 @@ struct Tck {
 // faster at k = 5; 8 waves spills 72 and runs 30 % slower).  With more
 // points per thread the registers hold several metric sets and no budget is
 // imposed (it would spill).
-template <int D, int N, typename T, int CPW>
+template <int D, int N, typename T, int CPW, int RP>
 constexpr int tck_waves_per_simd() {
   if (tck_threads(D, N) != 256 || cdiv(CPW * ipow(N, D), 256) > 1) return 1;
-  const int wg = (160 * 1024) / (CPW * TckLayout<D, N, T>::bytes_per_cell(true));
+  const int wg = (160 * 1024) / (CPW * TckLayout<D, N, T>::bytes_per_cell(RP));
   const int cap = sizeof(T) == 4 ? 6 : 5;
   return wg < 1 ? 1 : (wg > cap ? cap : wg);
 }
@@ -813,10 +840,11 @@ constexpr int tck_waves_per_simd() {
 // DG derivative W = L u (the first time derivative), the recursion starts at
 // the second derivative, and I = dt u + sum_{m>=1} dt^{m+1}/(m+1)! ut^m with
 // the dt u term added in the GL basis from p.u_base.
-template <int D, int N, typename T, bool REDUCE, int CPW, bool HDG = false>
+template <int D, int N, typename T, int RP, int CPW, bool HDG = false>
 __global__ void __launch_bounds__(tck_threads(D, N))
-__attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW>()))) tck_kernel(TckParams p) {
-  using K = Tck<D, N, T, REDUCE, CPW>;
+__attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck_kernel(TckParams p) {
+  using K = Tck<D, N, T, RP, CPW>;
+  using Regs = TckRegs<D, N, CPW, RP>;
   constexpr int NC = D + 1, NP = ipow(N, D), NT = tck_threads(D, N);
   constexpr int ES = cdiv(CPW * NC * NP, NT);
   constexpr int PS0 = cdiv(CPW * NP, NT);
@@ -839,14 +867,17 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW>()))) tck_ker
     const int i = threadIdx.x + s * NT;
     ev[s] = i < nel ? p.u[gofs + i] : 0.0;
   }
-  TckRegs<D, N, CPW, REDUCE> R;
-  tck_load_geo<D, N, CPW, REDUCE, 0>(R, p, cell0, ncl);
+  Regs R;
+  tck_load_geo<D, N, CPW, RP, 0>(R, p, cell0, ncl);
 #pragma unroll
-  for (int l = 0; l < TckRegs<D, N, CPW, REDUCE>::NLV; ++l)
+  for (int l = 0; l < (Regs::ACC_LDS ? 1 : Regs::NLV); ++l)
 #pragma unroll
     for (int s = 0; s < PS0; ++s)
 #pragma unroll
       for (int v = 0; v < NC; ++v) R.A[l][s][v] = 0.0;
+  R.acc = reinterpret_cast<double*>(C + (1 + D) * CPW * NC * NP);  // after the tiles (8-byte aligned)
+  if constexpr (Regs::ACC_LDS)
+    for (int i = threadIdx.x; i < CPW * TckLayout<D, N, T>::acc_elems(RP); i += NT) R.acc[i] = 0.0;
 #pragma unroll
   for (int s = 0; s < ES; ++s) {
     const int i = threadIdx.x + s * NT;
@@ -871,7 +902,7 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW>()))) tck_ker
     K::template step<1, 0>(p, C, Db, R, cell0, ncl, member);
   __syncthreads();  // the last accumulation may still read C
   // collapse the coarser levels into level 0, add A_0 in FP64, then G -> GL in FP64
-  K::template collapse<TckRegs<D, N, CPW, REDUCE>::NLV - 1>(p, C, Db, R, ncl);
+  K::template collapse<Regs::NLV - 1>(p, C, Db, R, ncl);
   double* sI = reinterpret_cast<double*>(Db[0]);  // FP64 tile over the derivative tiles
 #pragma unroll
   for (int s = 0; s < PS0; ++s) {
@@ -880,7 +911,7 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW>()))) tck_ker
       const int c = i / NP, q = i - c * NP;
 #pragma unroll
       for (int v = 0; v < NC; ++v) {
-        const double lower = TckRegs<D, N, CPW, REDUCE>::NLV > 1 ? (double)C[(c * NC + v) * NP + q] : 0.0;
+        const double lower = Regs::NLV > 1 ? (double)C[(c * NC + v) * NP + q] : 0.0;
         sI[(c * NC + v) * NP + q] = R.A[0][s][v] + lower;
       }
     }

@@ -123,21 +123,23 @@ std::vector<double> build_tables(int n) {
     t[tab_LF0(n) + j] = (double)lagrange_value(g.x, j, 0.0L);
     t[tab_LF1(n) + j] = (double)lagrange_value(g.x, j, 1.0L);
   }
-  for (int l = 1; l < num_levels(n); ++l) {
-    const int m = n - 2 * l, mp = n - 2 * (l - 1);
-    const Rule rm = gauss_rule(m), rp = gauss_rule(mp);
-    for (int q = 0; q < m; ++q)
-      for (int j = 0; j < m; ++j)
-        t[tab_level_D(n, l) + q * m + j] = m > 1 ? (double)lagrange_deriv(rm.x, j, rm.x[q]) : 0.0;
-    // unweighted L2 projection on the reference element, collocated form
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < mp; ++b)
-        t[tab_level_P(n, l) + a * mp + b] = (double)(rp.w[b] * lagrange_value(rm.x, a, rp.x[b]) / rm.w[a]);
-    for (int q = 0; q < mp; ++q)
-      for (int a = 0; a < m; ++a) t[tab_level_E(n, l) + q * m + a] = (double)lagrange_value(rm.x, a, rp.x[q]);
-    for (int q = 0; q < m; ++q)
-      for (int j = 0; j < n; ++j) t[tab_level_F(n, l) + q * n + j] = (double)lagrange_value(g.x, j, rm.x[q]);
-  }
+  for (int r = 1; r <= 3; ++r)
+    for (int l = 1; l < num_levels_r(n, r); ++l) {
+      const int m = n - r * l, mp = m + r;
+      const Rule rm = gauss_rule(m), rp = gauss_rule(mp);
+      for (int q = 0; q < m; ++q)
+        for (int j = 0; j < m; ++j)
+          t[tab_level_D(n, l, r) + q * m + j] = m > 1 ? (double)lagrange_deriv(rm.x, j, rm.x[q]) : 0.0;
+      // unweighted L2 projection on the reference element, collocated form
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < mp; ++b)
+          t[tab_level_P(n, l, r) + a * mp + b] = (double)(rp.w[b] * lagrange_value(rm.x, a, rp.x[b]) / rm.w[a]);
+      for (int q = 0; q < mp; ++q)
+        for (int a = 0; a < m; ++a)
+          t[tab_level_E(n, l, r) + q * m + a] = (double)lagrange_value(rm.x, a, rp.x[q]);
+      for (int q = 0; q < m; ++q)
+        for (int j = 0; j < n; ++j) t[tab_level_F(n, l, r) + q * n + j] = (double)lagrange_value(g.x, j, rm.x[q]);
+    }
   return t;
 }
 
@@ -507,6 +509,68 @@ dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs) {
   hs.dt_unit = dtu / std::pow((double)k, 1.5);
   hs.h_min = hmin;
   hs.c_max = cmax;
+  return DGW_OK;
+}
+
+// Metric and mass factors at the m^d tensor Gauss points of every cell, in
+// the layout of hs.level: [nc][d*d+2][m^d] (w detJ J^-1 at b*d+a, then
+// 1/(w detJ rho), rho c^2/(w detJ)).  For the reduced TCK levels of another
+// reduction period than the one built with the mesh; evaluates the map and
+// the material callback again.
+dgw_status build_level_metric(const HostSetup& hs, int m, std::vector<double>& out) {
+  const int d = hs.dim, q = hs.q, ng = ipw(q + 1, d), P = ipw(m, d), ncomp = d * d + 2;
+  const int64_t nc = hs.nc;
+  const Rule r = gauss_rule(m);
+  const GeoMats gm = geo_mats(q, r.x);
+  std::vector<const GeoMats*> mats(d, &gm);
+  std::vector<double> w(P, 1.0);
+  for (int p = 0; p < P; ++p) {
+    int t = p;
+    long double acc = 1;
+    for (int e = 0; e < d; ++e) {
+      acc *= r.w[t % m];
+      t /= m;
+    }
+    w[p] = (double)acc;
+  }
+  out.assign((size_t)nc * ncomp * P, 0.0);
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nc, (64ll << 20) / (8ll * P * (d + d * d))));
+  std::vector<double> X, Jb, rho, cc;
+  std::string err;
+  std::mutex err_mtx;
+  for (int64_t c0 = 0; c0 < nc; c0 += chunk) {
+    const int64_t cn = std::min(chunk, nc - c0);
+    X.resize((size_t)cn * P * d);
+    Jb.resize((size_t)cn * P * d * d);
+    parallel_for(cn, [&](int64_t i) {
+      std::vector<double> comp, res, t1, t2;
+      eval_map(d, q, hs.geo_nodes.data() + (c0 + i) * ng * d, mats, X.data() + (size_t)i * P * d,
+               Jb.data() + (size_t)i * P * d * d, comp, res, t1, t2);
+    });
+    rho.resize((size_t)cn * P);
+    cc.resize((size_t)cn * P);
+    hs.material(X.data(), cn * P, d, rho.data(), cc.data(), hs.material_ctx);
+    parallel_for(cn, [&](int64_t i) {
+      double Ji[9];
+      double* G = out.data() + (size_t)(c0 + i) * ncomp * P;
+      for (int p = 0; p < P; ++p) {
+        const size_t pp = (size_t)i * P + p;
+        const double det = det_inv(d, Jb.data() + pp * d * d, Ji);
+        const double rr = rho[pp], c = cc[pp];
+        if (!(det > 0) || !(rr > 0) || !(c > 0)) {
+          std::lock_guard<std::mutex> lk(err_mtx);
+          if (err.empty()) err = "non-positive Jacobian, rho or c in cell " + std::to_string(c0 + i);
+          return;
+        }
+        const double wd = w[p] * det;
+        for (int b = 0; b < d; ++b)
+          for (int a = 0; a < d; ++a) G[(b * d + a) * P + p] = wd * Ji[b * d + a];
+        G[(d * d) * P + p] = 1.0 / (wd * rr);
+        G[(d * d + 1) * P + p] = rr * c * c / wd;
+      }
+    });
+    if (!err.empty()) return fail(DGW_EINVAL, err);
+  }
   return DGW_OK;
 }
 

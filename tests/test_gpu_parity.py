@@ -173,6 +173,45 @@ def test_hdg_ader_step_fp64(gpu_lib, dim, nc, k, bc):
     assert rel(v[0].cpu().numpy(), u[0].cpu().numpy()) > 1e-9
 
 
+@pytest.mark.parametrize("dim,nc,k,period", [(2, 4, 3, 1), (3, 3, 5, 1), (3, 2, 8, 1), (3, 2, 7, 1),
+                                           (2, 3, 5, 3), (3, 3, 5, 3), (3, 2, 8, 3)])
+def test_ader_reduction_period_fp64(gpu_lib, dim, nc, k, period):
+    """TCK with the reduction every derivative / every third (ablation of Sec. 3.3)."""
+    say("ader period", dim, nc, k, period)
+    B = gpu_lib
+    gm, om = build(B, dim, nc, k, 0.05)
+    U = om.interpolate(lambda x: W.gaussian_pulse(x, [0.6] * dim, 0.15))
+    U = U + 0.01 * W.random_state(19, U.shape)
+    dt = 0.2 * gm.info.dt_unit
+    flag = B.ADER_REDUCE_EVERY_STEP if period == 1 else B.ADER_REDUCE_EVERY_THIRD
+    u = to_dev(U)[None]
+    gm.step_ader(u, 0.0, dt, 2, flags=flag)
+    want = U
+    for s in range(2):
+        want = ader.ader_step(om, want, dt, period=period)
+    assert rel(u[0].cpu().numpy(), want) < TOL
+    v = to_dev(U)[None]
+    gm.step_ader(v, 0.0, dt, 2)
+    assert rel(v[0].cpu().numpy(), u[0].cpu().numpy()) > 1e-10
+
+
+def test_ader_reduction_flags_rejected(gpu_lib):
+    say("ader period flags")
+    B = gpu_lib
+    gm, om = build(B, 3, 2, 3, 0.05)
+    u = to_dev(np.zeros((1,) + gm.shape))
+    for flags, code in ((B.ADER_REDUCE_EVERY_STEP | B.ADER_NOREDUCE, B.EINVAL),
+                        (B.ADER_REDUCE_EVERY_STEP | B.ADER_REDUCE_EVERY_THIRD, B.EINVAL),
+                        (B.ADER_REDUCE_EVERY_THIRD | B.ADER_HDG, B.EUNSUPPORTED), (16, B.EINVAL)):
+        with pytest.raises(B.DgwError) as e:
+            gm.step_ader(u, 0.0, 1e-3, 1, flags=flags)
+        assert e.value.status == code, flags
+    src = B.Sources(gm, W.random_points(3, 1, 3), frequency=4.0)
+    with pytest.raises(B.DgwError) as e:
+        gm.step_ader(u, 0.0, 1e-3, 1, flags=B.ADER_REDUCE_EVERY_STEP, sources=src)
+    assert e.value.status == B.EUNSUPPORTED
+
+
 def test_hdg_ader_rejects_unsupported(gpu_lib):
     say("hdg ader unsupported")
     gm, om = build(gpu_lib, 3, 2, 3, 0.05)

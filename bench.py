@@ -146,6 +146,113 @@ def fp32_error(steps=5):
     return out
 
 
+def cpu_baseline(target_s=15.0):
+    """The oracle (test infrastructure) timed on a sample of the c2 workload:
+    one ADER step (TCK + operator with its dense per-cell mass solve) on a
+    contiguous block of cells, scaled to DoF-steps/s."""
+    import numpy as np
+    import workloads as W
+    from oracle import Mesh, ader, apply_operator
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    wl = W.c2_workload(24, 5, 1805)
+    m = Mesh(3, 5, W.box_nodes(3, 24, 5, 0.05), W.box_neighbors(3, 24), wl["material"], cache=False)
+    U = np.zeros((m.nc, 4, m.np_))
+    U[:] = 1e-3
+    dt = CR["ader"] * 0.01
+
+    def one(cells):
+        ader.level_data(m, cells, 6)  # geometry of the sample (setup, untimed below)
+        t = time.perf_counter()
+        I = np.zeros_like(U)
+        I[cells] = ader.tck(m, U, dt, cells=cells)
+        apply_operator(m, I, cells=cells)
+        return time.perf_counter() - t
+
+    probe = np.arange(16)
+    tp = one(probe)
+    ncell = int(min(m.nc, max(16, target_s / tp * len(probe))))
+    cells = np.arange(ncell)
+    t = one(cells)
+    dof = ncell * 4 * m.np_
+    return {"value": dof / t, "unit": "DoF-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"one ADER step (TCK + operator, dense per-cell Cholesky mass solve) on {ncell} of "
+                      f"{m.nc} cells of the 24^3 k=5 workload, {t:.1f} s; geometry of the sample cells "
+                      f"recomputed inside the timed region (the oracle caches nothing at this size)"}
+
+
+def batched_sources(B=64, steps=500, precision="fp32", ncell=32, k=5, seed=64, use_graph=True):
+    """Many Ricker point sources (peak frequency 8, t0 = 1.2/8, seeded uniform
+    positions) on one 32^3 curved mesh as a batch of B right-hand sides, zero
+    initial state, ADER order k+1, autotuned launch shape, hipGraph-captured
+    steps.  Returns aggregate DoF-steps/s."""
+    import torch
+    import workloads as W
+    from paper_1805_03981_amd import binding as dg
+    wl = W.c2_workload(ncell, k, 1805)
+    mesh = dg.Mesh(3, k, W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell),
+                   dg.fourier_material_struct(wl["material"]),
+                   precision=dg.FP32_SPLIT if precision == "fp32" else dg.FP64, max_batch=B)
+    src = dg.Sources(mesh, W.random_points(seed, B, 3), frequency=8.0)
+    u = torch.zeros((B,) + mesh.shape, dtype=torch.float64, device="cuda")
+    work = mesh.work(B)
+    dt = CR["ader"] * mesh.info.dt_unit
+    rep = mesh.solve(u, dg.ADER, t_end=steps * dt, dt=dt, sources=src, use_graph=use_graph, autotune=True,
+                     work=work, B=B)
+    e = mesh.energy(u, B=B)
+    out = {"workload": f"{ncell}^3 curved hexes, k={k}, {B} Ricker sources (f=8) as batch members, ADER, "
+                       f"{precision}, hipGraph={bool(use_graph)}, autotuned",
+           "B": B, "steps": int(rep.steps), "wall_s": rep.wall_s, "dof_steps_per_s": rep.dof_steps_per_s,
+           "dofs_total": mesh.info.dofs * B, "energy_member0_end": float(e[0]),
+           "launch_shape": {"operator": mesh.launch_shape(0), "tck": mesh.launch_shape(1)}}
+    del u, work, src, mesh
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving(nreq=24, seed=5, load=0.8, nmin=6, nmax=20, tmin=0.05, tmax=0.2):
+    """A Poisson stream of solve requests: seeded periodic curved boxes with
+    n^3 cells (n log-uniform in [nmin, nmax]), k uniform in 2..8, LSRK or
+    ADER, FP32-split, final time U[tmin, tmax], Cr = 0.8 Cr_crit; arrival
+    rate = `load` x the measured capacity.  Reports p50/p99 latency."""
+    import ctypes as C
+    import numpy as np
+    import workloads as W
+    from paper_1805_03981_amd import binding as dg
+    rng = np.random.default_rng(seed)
+    reqs = []
+    work = []
+    for i in range(nreq):
+        n = int(round(np.exp(rng.uniform(np.log(nmin), np.log(nmax)))))
+        k = int(rng.integers(2, 9))
+        scheme = int(rng.integers(0, 2))
+        t_end = float(rng.uniform(tmin, tmax))
+        r = dg.Request(arrival_s=0.0, dim=3, ncell=n, degree=k, scheme=scheme, precision=1, t_end=t_end,
+                       courant=0.8 * (0.44 if scheme == 0 else 0.18), deform_amp=0.05)
+        r.material = dg.fourier_material_struct(W.FourierMaterial(seed * 1000 + i, dim=3))
+        c = W.random_points(seed * 1000 + i, 1, 3)[0]
+        for a in range(3):
+            r.ic_center[a] = c[a]
+        r.ic_width = 0.1
+        reqs.append(r)
+    # capacity: all requests at once, no arrival process
+    cap, _, _ = dg.serve(reqs, realtime=False, max_live=8)
+    mean_s = cap.wall_s / nreq
+    gaps = rng.exponential(mean_s / load, size=nreq)
+    t = np.cumsum(gaps) - gaps[0]
+    for r, a in zip(reqs, t):
+        r.arrival_s = float(a)
+    rep, res, _ = dg.serve(reqs, realtime=True, max_live=8)
+    return {"workload": f"{nreq} requests, 3D curved periodic boxes n^3, n log-uniform [{nmin},{nmax}], k in 2..8, "
+                        f"LSRK/ADER, FP32-split, T in [{tmin},{tmax}], Poisson arrivals at {load} x capacity",
+            "p50_s": rep.p50_s, "p99_s": rep.p99_s, "dof_steps_per_s": rep.dof_steps_per_s,
+            "max_wait_s": rep.max_wait_s, "n_done": rep.n_done, "n_failed": rep.n_failed,
+            "capacity_dof_steps_per_s": cap.dof_steps_per_s, "wall_s": rep.wall_s}
+
+
 def fixed_error(target=1e-6, T=0.5, iters=3, max_run_s=12.0):
     """Time to solution at a fixed error, against two FP64 references on the
     same mesh at 1/8 of their steps (0.9 of the critical Courant number):

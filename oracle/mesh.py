@@ -31,13 +31,17 @@ class Mesh:
     """A mesh of curved quads (d=2) or hexes (d=3) with degree-k DG fields.
 
     geo_nodes: float64[Nc][(q+1)^d][d]; neighbors: int64[Nc][2d] in face order
-    -x,+x,-y,+y,-z,+z (standard orientation); a negative entry marks a face on
-    the domain boundary with its condition (BC_WALL, BC_ABSORBING; the paper
-    leaves the boundary conditions open, Sec. 2); material: callable
-    x[...,d] -> (rho, c).
+    -x,+x,-y,+y,-z,+z; a negative entry marks a face on the domain boundary
+    with its condition (BC_WALL, BC_ABSORBING; the paper leaves the boundary
+    conditions open, Sec. 2); material: callable x[...,d] -> (rho, c).
+    face_orient: None (every neighbour meets face f with its face f^1, the
+    tangential coordinates aligned) or int[Nc][2d] with 8 f' + o: the
+    neighbour's face f' and the orientation o that maps the own tangential
+    coordinates (s, t) to the neighbour's: bit 2 swaps them first, bit 0
+    reverses the first, bit 1 the second (2D: bit 0 reverses s).
     """
 
-    def __init__(self, dim, k, geo_nodes, neighbors, material, cache=True):
+    def __init__(self, dim, k, geo_nodes, neighbors, material, cache=True, face_orient=None):
         self.dim = int(dim)
         self.k = int(k)
         self.n = self.k + 1
@@ -45,6 +49,14 @@ class Mesh:
         self.neighbors = np.ascontiguousarray(neighbors, dtype=np.int64)
         if np.any((self.neighbors < 0) & (self.neighbors != BC_WALL) & (self.neighbors != BC_ABSORBING)):
             raise ValueError("negative neighbour entries must be BC_WALL or BC_ABSORBING")
+        if face_orient is None:
+            fo = np.array([8 * (f ^ 1) for f in range(2 * self.dim)], dtype=np.int64)
+            self.face_orient = np.broadcast_to(fo, self.neighbors.shape).copy()
+        else:
+            self.face_orient = np.ascontiguousarray(face_orient, dtype=np.int64)
+            no = 8 if self.dim == 3 else 2
+            if np.any(self.face_orient // 8 >= 2 * self.dim) or np.any(self.face_orient % 8 >= no):
+                raise ValueError("face_orient codes out of range")
         self.material = material
         self.nc = self.geo_nodes.shape[0]
         ng = self.geo_nodes.shape[1]
@@ -78,6 +90,30 @@ class Mesh:
                 pts[:, b] = float(s)
             else:
                 pts[:, b] = tang[:, t]
+                t += 1
+        return pts
+
+    def neighbor_face_points(self, f, code):
+        """Reference points, on the neighbour's face code // 8, of the Gauss
+        points of own face f (same order as face_ref[f]), for orientation code
+        % 8 (class docstring)."""
+        fn, o = divmod(int(code), 8)
+        own = self.face_ref[f]
+        tang = [a for a in range(self.dim) if a != f // 2]
+        st = own[:, tang].copy()                       # own tangential coordinates
+        if self.dim == 3 and o & 4:
+            st = st[:, ::-1].copy()
+        if o & 1:
+            st[:, 0] = 1.0 - st[:, 0]
+        if self.dim == 3 and o & 2:
+            st[:, 1] = 1.0 - st[:, 1]
+        pts = np.empty_like(own)
+        t = 0
+        for a in range(self.dim):
+            if a == fn // 2:
+                pts[:, a] = float(fn % 2)
+            else:
+                pts[:, a] = st[:, t]
                 t += 1
         return pts
 
@@ -143,14 +179,15 @@ class Mesh:
         a = self.face_w[None, :, None] * detJ[..., None] * (JinvT @ self.face_normal_ref(f))
         rho, c = self.material(x)
         nbc = self.neighbors[cells, f]
+        code = self.face_orient[cells, f]
         Zm = np.asarray(rho * c, dtype=np.float64)
         Zp = Zm.copy()
-        inner = nbc >= 0
-        if np.any(inner):
-            xn, _ = self.map_points(nbc[inner], self.face_ref[f ^ 1])
+        for cd in np.unique(code[nbc >= 0]):
+            sel = (nbc >= 0) & (code == cd)
+            xn, _ = self.map_points(nbc[sel], self.neighbor_face_points(f, cd))
             rhon, cn = self.material(xn)
-            Zp[inner] = rhon * cn
-        return dict(a=a, x=x, Zm=Zm, Zp=Zp, nb=nbc)
+            Zp[sel] = rhon * cn
+        return dict(a=a, x=x, Zm=Zm, Zp=Zp, nb=nbc, code=code)
 
     def node_points(self, cells=None):
         """Physical positions of the GL nodes, float64[C][n^d][d] (for interpolating

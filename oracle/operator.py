@@ -116,8 +116,10 @@ def residual(mesh, U, cells, flux="upwind"):
         nb = fd["nb"]
         inner = nb >= 0
         up = exterior_state(um, nrm, nb, d)
-        if np.any(inner):
-            up[inner] = np.einsum("qi,cvi->cvq", T.phif[f ^ 1], U[nb[inner]])
+        for cd in np.unique(fd["code"][inner]):
+            sel = inner & (fd["code"] == cd)
+            phin = basis.tensor_basis(mesh.xgl, mesh.neighbor_face_points(f, cd))
+            up[sel] = np.einsum("qi,cvi->cvq", phin, U[nb[sel]])
         vnm = np.einsum("cqa,caq->cq", nrm, um[:, :d, :])
         vnp = np.einsum("cqa,caq->cq", nrm, up[:, :d, :])
         ps, vs = numerical_flux(um[:, d], up[:, d], vnm, vnp, fd["Zm"], fd["Zp"], flux)

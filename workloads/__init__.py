@@ -10,6 +10,10 @@ the oracle compute everything else from these inputs on their own.
 from .generators import (  # noqa: F401
     box_nodes,
     box_neighbors,
+    cube_rotations,
+    lattice_permutation,
+    face_orientation,
+    rotated_box,
     BC_WALL,
     BC_ABSORBING,
     FourierMaterial,

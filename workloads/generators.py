@@ -56,6 +56,126 @@ def box_neighbors(dim: int, ncell: int, bc=None) -> np.ndarray:
     return nb
 
 
+def cube_rotations(dim: int):
+    """Orientation-preserving symmetries of the reference cell [0,1]^dim as
+    (perm, flip): new coordinate b is old coordinate perm[b], reversed when
+    flip[b]; 4 in 2D, 24 in 3D, identity first."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(dim)):
+        inv = sum(1 for i in range(dim) for j in range(i + 1, dim) if perm[i] > perm[j])
+        for flip in itertools.product((0, 1), repeat=dim):
+            if (inv + sum(flip)) % 2 == 0:
+                out.append((tuple(perm), tuple(flip)))
+    out.sort(key=lambda r: (r[0] != tuple(range(dim)), r[1] != (0,) * dim))
+    return out
+
+
+def _old_index(j, rot, m):
+    """Old lattice multi-index of new multi-index j (m+1 points per direction)."""
+    perm, flip = rot
+    i = [0] * len(j)
+    for b in range(len(j)):
+        i[perm[b]] = m - j[b] if flip[b] else j[b]
+    return i
+
+
+def lattice_permutation(dim: int, m: int, rot) -> np.ndarray:
+    """Index array P with new_values[j] = old_values[P[j]] for the (m+1)^dim
+    lattice (x fastest) of a cell renumbered by the rotation rot."""
+    n = m + 1
+    P = np.empty(n ** dim, dtype=np.int64)
+    for lin in range(n ** dim):
+        j = [(lin // n ** a) % n for a in range(dim)]
+        i = _old_index(j, rot, m)
+        P[lin] = sum(i[a] * n ** a for a in range(dim))
+    return P
+
+
+def face_orientation(own, other):
+    """Orientation code o with other = orient(own) for tangential coordinate
+    tuples in [0, 1]: 3D (s, t): bit 2 swaps (s, t) first, bit 0 reverses the
+    first and bit 1 the second coordinate; 2D (s,): bit 0 reverses s."""
+    for o in range(8 if len(own) == 2 else 2):
+        a = list(own)
+        if len(a) == 2 and o & 4:
+            a = [a[1], a[0]]
+        if o & 1:
+            a[0] = 1 - a[0]
+        if len(a) == 2 and o & 2:
+            a[1] = 1 - a[1]
+        if all(abs(x - y) < 1e-12 for x, y in zip(a, other)):
+            return o
+    return None
+
+
+def rotated_box(dim: int, ncell: int, q: int, amp: float, seed: int, frac: float = 0.6):
+    """The periodic box with a random subset of its cells renumbered by random
+    reference-cell rotations: the same mesh (same physical cells), but faces
+    meet with other face indices and orientations.  Returns (geo_nodes,
+    neighbors, face_orient, rotations) where face_orient[c][f] = 8 f' + o
+    (the neighbour's face f' and the orientation o of face_orientation) and
+    rotations[c] the (perm, flip) applied to cell c."""
+    nodes = box_nodes(dim, ncell, q, amp)
+    nb_old = box_neighbors(dim, ncell)
+    rots_all = cube_rotations(dim)
+    rng = np.random.default_rng(seed)
+    nc = nodes.shape[0]
+    rot = [rots_all[0] if rng.random() > frac else rots_all[rng.integers(1, len(rots_all))] for _ in range(nc)]
+    new_nodes = np.stack([nodes[c][lattice_permutation(dim, q, rot[c])] for c in range(nc)])
+
+    def old_face(c, f):  # old face index of new face f of cell c
+        perm, flip = rot[c]
+        b, side = divmod(f, 2)
+        return 2 * perm[b] + (side ^ flip[b])
+
+    def new_face(c, F):
+        perm, flip = rot[c]
+        b = perm.index(F // 2)
+        return 2 * b + ((F % 2) ^ flip[b])
+
+    def tangential(f, pt):  # tangential coordinates of a reference point on face f
+        return tuple(pt[a] for a in range(dim) if a != f // 2)
+
+    def to_old(c, xi):  # reference point of the new numbering -> old numbering
+        perm, flip = rot[c]
+        x = [0.0] * dim
+        for b in range(dim):
+            x[perm[b]] = 1 - xi[b] if flip[b] else xi[b]
+        return x
+
+    def to_new(c, x):
+        perm, flip = rot[c]
+        return [1 - x[perm[b]] if flip[b] else x[perm[b]] for b in range(dim)]
+
+    nb = np.empty((nc, 2 * dim), dtype=np.int64)
+    fo = np.empty((nc, 2 * dim), dtype=np.int32)
+    probe = [(0.25, 0.6), (0.7, 0.15)] if dim == 3 else [(0.3,)]
+    for c in range(nc):
+        for f in range(2 * dim):
+            F = old_face(c, f)
+            c2 = nb_old[c, F]
+            f2 = new_face(c2, F ^ 1)
+            codes = set()
+            for tp in probe:
+                xi = []
+                t = 0
+                for a in range(dim):
+                    if a == f // 2:
+                        xi.append(float(f % 2))
+                    else:
+                        xi.append(tp[t])
+                        t += 1
+                x_old = to_old(c, xi)
+                x_old[F // 2] = 1.0 - x_old[F // 2]          # the same point seen from the neighbour
+                y = to_new(c2, x_old)
+                codes.add(face_orientation(tangential(f, xi), tangential(f2, y)))
+            assert len(codes) == 1 and None not in codes
+            nb[c, f] = c2
+            fo[c, f] = 8 * f2 + codes.pop()
+    return new_nodes, nb, fo, rot
+
+
 def box_nodes(dim: int, ncell: int, q: int, amp: float) -> np.ndarray:
     """Geometry nodes float64[n^dim][(q+1)^dim][dim] of the periodic unit box.
 

@@ -112,7 +112,15 @@ typedef struct dgw_mesh_desc {
   const double* geo_nodes;   /* host [n_cells][(q+1)^dim][dim]; copied          */
   const int64_t* neighbors;  /* host [n_cells][2*dim]; a negative entry marks a */
                              /* boundary face: DGW_BC_WALL or DGW_BC_ABSORBING  */
-  const int* face_orient;    /* must be NULL (standard orientation)             */
+  const int* face_orient;    /* NULL: every neighbour meets face f with its     */
+                             /* face f^1, tangential coordinates aligned.  Else */
+                             /* host int32 [n_cells][2*dim], 8 f' + o: the      */
+                             /* neighbour's face f' and the orientation o that  */
+                             /* maps the own tangential coordinates (s, t) (the */
+                             /* other directions in increasing order) to the    */
+                             /* neighbour's: bit 2 swaps them first, bit 0      */
+                             /* reverses the first, bit 1 the second (2D: bit 0 */
+                             /* reverses s).  Must be mutually consistent.      */
   dgw_material_fn material;  /* required                                        */
   void* material_ctx;
   int flux;                  /* DGW_FLUX_*                                      */

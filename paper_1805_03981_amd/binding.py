@@ -188,9 +188,12 @@ class Mesh:
     """Owns a dgw_mesh.  Create with Mesh(...) from explicit nodes or Mesh.box(...)."""
 
     def __init__(self, dim, degree, geo_nodes, neighbors, material, flux=FLUX_UPWIND, precision=FP64,
-                 device=0, max_batch=1, geo_degree=0):
+                 device=0, max_batch=1, geo_degree=0, face_orient=None):
         nodes = np.ascontiguousarray(geo_nodes, dtype=np.float64)
         nb = np.ascontiguousarray(neighbors, dtype=np.int64)
+        fo = None if face_orient is None else np.ascontiguousarray(face_orient, dtype=np.int32)
+        if fo is not None and fo.shape != nb.shape:
+            raise ValueError("face_orient must have the shape of neighbors")
         ctx = None
         if isinstance(material, FourierMaterial):
             self._ctx = material
@@ -200,7 +203,7 @@ class Mesh:
             self._cb = material if isinstance(material, MATERIAL_FN) else material_callback(material)
         d = MeshDesc(dim=dim, degree=degree, n_cells=nodes.shape[0], geo_degree=geo_degree,
                      geo_nodes=_dptr(nodes), neighbors=nb.ctypes.data_as(C.POINTER(C.c_int64)),
-                     face_orient=None, material=self._cb, material_ctx=ctx, flux=flux, precision=precision,
+                     face_orient=None if fo is None else fo.ctypes.data_as(C.POINTER(C.c_int)), material=self._cb, material_ctx=ctx, flux=flux, precision=precision,
                      device=device, max_batch=max_batch)
         h = C.c_void_p()
         check(lib.dgw_mesh_create(C.byref(d), C.byref(h)), "dgw_mesh_create")

@@ -132,6 +132,7 @@ static OpParams op_params(const dgw_mesh* m, int B, const dgw_sources* src) {
   p.geo_cell = m->d_cell;
   p.geo_face = m->d_face;
   p.nb = m->d_nb;
+  p.fo = m->d_fo;
   p.nc = m->hs.nc;
   p.cpw = m->L->cpw[m->op_shape.sel];
   p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
@@ -441,6 +442,7 @@ static dgw_status upload(dgw_mesh* m) {
   if ((st = alloc_copy(m->d_cell, hs.cell.data(), hs.cell.size()))) return st;
   if ((st = alloc_copy(m->d_face, hs.face.data(), hs.face.size()))) return st;
   if ((st = alloc_copy(m->d_nb, hs.nb.data(), hs.nb.size()))) return st;
+  if (!hs.fo.empty() && (st = alloc_copy(m->d_fo, hs.fo.data(), hs.fo.size()))) return st;
   for (int l = 1; l < m->nlev; ++l)
     if ((st = alloc_copy(m->d_level[l], hs.level[l].data(), hs.level[l].size()))) return st;
   if ((st = ensure_tables(m->device))) return st;
@@ -458,6 +460,7 @@ static void release(dgw_mesh* m) {
     (void)hipFree(m->d_cell);
     (void)hipFree(m->d_face);
     (void)hipFree(m->d_nb);
+    (void)hipFree(m->d_fo);
     for (auto* p : m->d_level) (void)hipFree(p);
     for (auto* p : m->d_level_pts) (void)hipFree(p);
     (void)hipFree(m->d_partial);
@@ -511,7 +514,6 @@ dgw_status dgw_mesh_create(const dgw_mesh_desc* desc, dgw_mesh** out) {
   if (desc->n_cells < 1) return fail(DGW_EINVAL, "n_cells must be >= 1");
   if (!desc->geo_nodes || !desc->neighbors || !desc->material)
     return fail(DGW_EINVAL, "geo_nodes, neighbors and material are required");
-  if (desc->face_orient) return fail(DGW_EUNSUPPORTED, "only the standard face orientation is supported");
   if (desc->flux != DGW_FLUX_UPWIND && desc->flux != DGW_FLUX_CENTRAL) return fail(DGW_EINVAL, "bad flux");
   if (desc->precision != DGW_FP64 && desc->precision != DGW_FP32_SPLIT) return fail(DGW_EINVAL, "bad precision");
   if (desc->max_batch < 1) return fail(DGW_EINVAL, "max_batch must be >= 1");

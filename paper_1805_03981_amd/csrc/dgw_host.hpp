@@ -39,6 +39,7 @@ struct HostSetup {
   int64_t nc = 0;
   std::vector<double> geo_nodes;           // [nc][(q+1)^d][d]
   std::vector<int32_t> nb;                 // [nc][2d]
+  std::vector<int32_t> fo;                 // [nc][2d] 8 f' + o, or empty (standard faces)
   std::vector<double> cell;                // [nc][d*d+2][np]
   std::vector<double> face;                // [nc][2d][d+2][nf]
   std::vector<std::vector<double>> level;  // [l] (l >= 1): [nc][d*d+2][m_l^d]
@@ -48,6 +49,11 @@ struct HostSetup {
   void* material_ctx = nullptr;
 };
 dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs);
+// Face pairing: the neighbour's face of face f of cell c, the orientation
+// code of the pair, and the index on the neighbour's face of own face point p.
+int face_of_neighbor(const HostSetup& hs, int64_t c, int f);
+int orient_of(const HostSetup& hs, int64_t c, int f);
+int orient_face_index(int d, int n, int o, int p);
 // Metric and mass factors at the m^d Gauss points of every cell (layout of
 // HostSetup::level), for the reduced TCK levels of another period.
 dgw_status build_level_metric(const HostSetup& hs, int m, std::vector<double>& out);
@@ -75,6 +81,7 @@ struct dgw_mesh {
   double* d_level[dgw::kMaxLevels] = {};     // reduced levels of period 2 (n - 2l points)
   double* d_level_pts[dgw::kMaxLevels + 1] = {};  // other periods' levels, by points per direction
   int32_t* d_nb = nullptr;
+  int32_t* d_fo = nullptr;  // face orientation codes, nullptr for the standard faces
   double* d_partial = nullptr;  // energy partial sums [max_batch][groups]
   int64_t device_bytes = 0;
   dgw::LaunchShape op_shape, tck_shape;

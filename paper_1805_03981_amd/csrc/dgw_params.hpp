@@ -47,6 +47,7 @@ struct OpParams {
   const double* geo_cell; // [nc][d*d+2][np]: w detJ J^-1 (b*d+a), mu_v, mu_p
   const double* geo_face; // [nc][2d][d+2][n^(d-1)]: a (d), Z-, Z+
   const int* nb;          // [nc][2d]
+  const int* fo;          // [nc][2d] 8 f' + o (neighbour face, orientation) or nullptr (f' = f^1, o = 0)
   int64_t nc;
   int cpw;                // cells per workgroup
   int groups;             // ceil(nc / cpw)

@@ -232,6 +232,24 @@ __device__ __forceinline__ int face_line_base(int dir, int t) {
   return dir == 0 ? t * N : (dir == 1 ? (t % N) + (t / N) * N * N : t);
 }
 
+// Tangential index on the neighbour's face of own face index t under
+// orientation o: bit 2 swaps the two tangential indices, then bit 0 reverses
+// the first and bit 1 the second (2D: bit 0 reverses the only one).  The GL
+// nodes are symmetric about the cell centre, so a reversal is i -> N-1-i.
+template <int D, int N>
+__device__ __forceinline__ int orient_face(int o, int t) {
+  if constexpr (D == 2) return (o & 1) ? N - 1 - t : t;
+  int i = t % N, j = t / N;
+  if (o & 4) {
+    const int x = i;
+    i = j;
+    j = x;
+  }
+  if (o & 1) i = N - 1 - i;
+  if (o & 2) j = N - 1 - j;
+  return i + N * j;
+}
+
 // C2 of the operator: R (+)= D_b^T F along the b-lines, plus the lifts of the
 // two face fluxes of direction b (rank one in the normal direction).
 template <int D, int N, typename T, int DIR>
@@ -349,10 +367,17 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
       const int t = i % NF;
       const int r = i / NF;
       const int v = r % NC;
-      const int f = (r / NC) % NFACE;
-      // GL node of the neighbour's face opposite to f, tangential index t
-      const int fo = f ^ 1, dir = fo >> 1, side = fo & 1;
-      const int q = face_line_base<D, N>(dir, t) + (side ? (N - 1) * dir_stride(N, dir) : 0);
+      const int cf = r / NC;  // c * NFACE + f
+      // GL node of the neighbour's face f' that meets own tangential index t:
+      // f' = f^1 with aligned coordinates unless the mesh gives orientations
+      int fn = (cf % NFACE) ^ 1, tn = t;
+      if (p.fo) {
+        const int code = p.fo[cell0 * NFACE + cf];
+        fn = code >> 3;
+        tn = orient_face<D, N>(code & 7, t);
+      }
+      const int dir = fn >> 1, side = fn & 1;
+      const int q = face_line_base<D, N>(dir, tn) + (side ? (N - 1) * dir_stride(N, dir) : 0);
       nv[s] = p.u[moff + (int64_t)nbi[s] * NC * NP + v * NP + q];
     }
   }

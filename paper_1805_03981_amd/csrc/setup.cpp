@@ -329,6 +329,26 @@ void node_coords(const HostSetup& hs, std::vector<double>& out) {
   });
 }
 
+// Neighbour face of face f of cell c, and the orientation of the pair.
+int face_of_neighbor(const HostSetup& hs, int64_t c, int f) {
+  return hs.fo.empty() ? (f ^ 1) : hs.fo[c * 2 * hs.dim + f] / 8;
+}
+int orient_of(const HostSetup& hs, int64_t c, int f) { return hs.fo.empty() ? 0 : hs.fo[c * 2 * hs.dim + f] % 8; }
+
+// Index on the neighbour's face (n points per direction, the first
+// tangential direction fastest) of own face point p under orientation o:
+// bit 2 swaps the two tangential indices first, bit 0 reverses the first,
+// bit 1 the second (2D: bit 0 reverses the only one).  The Gauss and GL
+// point sets are symmetric, so a reversal is i -> n-1-i.
+int orient_face_index(int d, int n, int o, int p) {
+  if (d == 2) return (o & 1) ? n - 1 - p : p;
+  int i = p % n, j = p / n;
+  if (o & 4) std::swap(i, j);
+  if (o & 1) i = n - 1 - i;
+  if (o & 2) j = n - 1 - j;
+  return i + n * j;
+}
+
 dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs) {
   const int d = desc.dim, k = desc.degree, n = k + 1;
   const int q = desc.geo_degree > 0 ? desc.geo_degree : k;
@@ -353,11 +373,27 @@ dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs) {
       if (o >= nc) return fail(DGW_EINVAL, "neighbor index out of range");
       hs.nb[c * nface + f] = (int32_t)o;
     }
+  if (desc.face_orient) {
+    hs.fo.assign(desc.face_orient, desc.face_orient + nc * nface);
+    const int norient = d == 3 ? 8 : 2;
+    for (int64_t c = 0; c < nc; ++c)
+      for (int f = 0; f < nface; ++f) {
+        const int code = hs.fo[c * nface + f];
+        if (code < 0 || code / 8 >= nface || code % 8 >= norient)
+          return fail(DGW_EINVAL, "face_orient code out of range");
+      }
+  }
   for (int64_t c = 0; c < nc; ++c)
     for (int f = 0; f < nface; ++f) {
       const int64_t o = desc.neighbors[c * nface + f];
-      if (o >= 0 && desc.neighbors[o * nface + (f ^ 1)] != c)
-        return fail(DGW_EINVAL, "neighbor table is not conforming (nb[nb[c][f]][f^1] != c)");
+      if (o < 0) continue;
+      const int fn = face_of_neighbor(hs, c, f);
+      if (desc.neighbors[o * nface + fn] != c || face_of_neighbor(hs, o, fn) != f)
+        return fail(DGW_EINVAL, "neighbor table is not conforming (the neighbour's face does not point back)");
+      // the orientation back must undo the orientation there
+      for (int p = 0; p < ipw(n, d - 1); ++p)
+        if (orient_face_index(d, n, orient_of(hs, o, fn), orient_face_index(d, n, orient_of(hs, c, f), p)) != p)
+          return fail(DGW_EINVAL, "face orientations of a face pair do not invert each other");
     }
   hs.geo_nodes.assign(desc.geo_nodes, desc.geo_nodes + nc * ng * d);
 
@@ -490,15 +526,20 @@ dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs) {
     });
     if (!err.empty()) return fail(DGW_EINVAL, err);
   }
-  // impedance of the neighbour at the shared face point (its own sample);
-  // on a boundary face the exterior impedance is the own one
+  // impedance of the neighbour at the shared face point (its own sample, at
+  // the point its face orientation maps to); on a boundary face the own one
   for (int64_t c = 0; c < nc; ++c)
     for (int f = 0; f < nface; ++f) {
       const int64_t o = hs.nb[c * nface + f];
       double* F = hs.face.data() + ((size_t)c * nface + f) * (d + 2) * nf;
-      const double* Zo = o >= 0 ? Zown.data() + ((size_t)o * nface + (f ^ 1)) * nf
-                                : Zown.data() + ((size_t)c * nface + f) * nf;
-      for (int p = 0; p < nf; ++p) F[(d + 1) * nf + p] = Zo[p];
+      if (o < 0) {
+        const double* Zo = Zown.data() + ((size_t)c * nface + f) * nf;
+        for (int p = 0; p < nf; ++p) F[(d + 1) * nf + p] = Zo[p];
+      } else {
+        const double* Zo = Zown.data() + ((size_t)o * nface + face_of_neighbor(hs, c, f)) * nf;
+        const int ori = orient_of(hs, c, f);
+        for (int p = 0; p < nf; ++p) F[(d + 1) * nf + p] = Zo[orient_face_index(d, n, ori, p)];
+      }
     }
   double dtu = 1e300, hmin = 1e300, cmax = 0;
   for (int64_t c = 0; c < nc; ++c) {

@@ -87,6 +87,47 @@ def test_host_setup_matches_oracle_geometry(B, dim, nc, k, amp, bc):
     assert np.abs(x - om.node_points()).max() < 1e-14
 
 
+@pytest.mark.parametrize("dim,nc,k", [(2, 3, 3), (3, 3, 2), (3, 2, 4)])
+def test_host_setup_with_face_orientations(B, dim, nc, k):
+    """Renumbered cells (faces meeting with other indices and orientations):
+    the host face data, the neighbour impedance at the oriented point
+    included, agrees with the oracle's."""
+    mat = W.FourierMaterial(5, dim=dim)
+    nodes, nb, fo, _ = W.rotated_box(dim, nc, k, 0.05, seed=17 + k)
+    gm = B.Mesh(dim, k, nodes, nb, mat, device=B.DEVICE_NONE, face_orient=fo)
+    om = OMesh(dim, k, nodes, nb, mat, face_orient=fo)
+    F = gm.get(B.GET_FACE)
+    for f in range(2 * dim):
+        fd = om.face_data(np.arange(om.nc), f)
+        assert np.abs(F[:, f, :dim] - np.moveaxis(fd["a"], 2, 1)).max() < 1e-14
+        assert np.abs(F[:, f, dim] - fd["Zm"]).max() < 1e-14
+        assert np.abs(F[:, f, dim + 1] - fd["Zp"]).max() < 1e-14
+    # the impedance really varies along the faces, so a wrong point map shows
+    assert np.abs(F[:, :, dim + 1] - F[:, :, dim + 1].mean(axis=-1, keepdims=True)).max() > 1e-3
+
+
+def test_face_orientation_validation(B):
+    mat = W.ConstantMaterial()
+    nodes, nb, fo, _ = W.rotated_box(3, 2, 2, 0.0, seed=5)
+    B.Mesh(3, 2, nodes, nb, mat, device=B.DEVICE_NONE, face_orient=fo)
+    c, f = np.argwhere(fo % 8 != 0)[0]
+    for bad_code in (fo[c, f] ^ 1, 6 * 8, -1, fo[c, f] // 8 * 8 + 8 if fo[c, f] // 8 < 5 else 0):
+        bad = fo.copy()
+        bad[c, f] = bad_code
+        with pytest.raises(B.DgwError) as e:
+            B.Mesh(3, 2, nodes, nb, mat, device=B.DEVICE_NONE, face_orient=bad)
+        assert e.value.status == B.EINVAL, bad_code
+    # 2D: only orientation 0 or 1
+    nodes2, nb2, fo2, _ = W.rotated_box(2, 3, 2, 0.0, seed=6)
+    bad = fo2.copy()
+    bad[0, 0] = 8 * (bad[0, 0] // 8) + 2
+    with pytest.raises(B.DgwError) as e:
+        B.Mesh(2, 2, nodes2, nb2, mat, device=B.DEVICE_NONE, face_orient=bad)
+    assert e.value.status == B.EINVAL
+    with pytest.raises(ValueError):
+        B.Mesh(2, 2, nodes2, nb2, mat, device=B.DEVICE_NONE, face_orient=fo2[:, :2])
+
+
 def test_level_metric_matches_oracle(B):
     from oracle import ader
     dim, nc, k = 3, 2, 5

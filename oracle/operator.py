@@ -37,6 +37,15 @@ The operator is evaluated with the full d-dimensional GL basis tables at the
 quadrature points (no sum factorization) and the dense per-cell mass matrices
 M_v = sum_q w detJ rho phi_i phi_j, M_p = sum_q w detJ/(rho c^2) phi_i phi_j
 are inverted through a Cholesky factorization.
+
+Storage basis (Sec. 3.1 compares two for the Runge-Kutta operator): "gl",
+the Lagrange polynomials in the k+1 Gauss-Lobatto points per direction
+(nodes on the faces), or "gauss", the Lagrange polynomials in the k+1 Gauss
+points (the collocated setup: phi is the identity at the quadrature points,
+so the mass matrices are diagonal).  Both span the same space and use the
+same quadrature, so the two operators are one linear map in two bases; the
+"gauss" one is evaluated here directly from the weak form with its own
+tables, not through that identity.
 """
 from __future__ import annotations
 
@@ -46,20 +55,32 @@ from . import basis
 from .mesh import BC_WALL
 
 
+def storage_nodes(mesh, storage):
+    """1D nodes of the storage basis: GL points ("gl") or Gauss points ("gauss")."""
+    if storage == "gl":
+        return mesh.xgl
+    if storage == "gauss":
+        return mesh.xg
+    raise ValueError(f"unknown storage basis {storage!r}")
+
+
 class Tables:
-    """Direct d-dimensional GL basis tables at the cell and face Gauss points."""
+    """Direct d-dimensional tables of the storage basis at the cell and face Gauss points."""
 
-    def __init__(self, mesh):
-        self.phi = basis.tensor_basis(mesh.xgl, mesh.cell_ref)            # [Q][np]
-        self.dphi = basis.tensor_basis_grad(mesh.xgl, mesh.cell_ref)      # [d][Q][np]
-        self.phif = [basis.tensor_basis(mesh.xgl, mesh.face_ref[f]) for f in range(mesh.nface)]
+    def __init__(self, mesh, storage="gl"):
+        x1 = storage_nodes(mesh, storage)
+        self.nodes = x1
+        self.phi = basis.tensor_basis(x1, mesh.cell_ref)            # [Q][np]
+        self.dphi = basis.tensor_basis_grad(x1, mesh.cell_ref)      # [d][Q][np]
+        self.phif = [basis.tensor_basis(x1, mesh.face_ref[f]) for f in range(mesh.nface)]
 
 
-def tables(mesh):
-    t = mesh._cache.get("tables")
+def tables(mesh, storage="gl"):
+    key = "tables" if storage == "gl" else "tables_" + storage
+    t = mesh._cache.get(key)
     if t is None:
-        t = Tables(mesh)
-        mesh._cache["tables"] = t
+        t = Tables(mesh, storage)
+        mesh._cache[key] = t
     return t
 
 
@@ -91,10 +112,11 @@ def exterior_state(um, nrm, nb, d):
     return up
 
 
-def residual(mesh, U, cells, flux="upwind"):
-    """Right-hand side r = -K U restricted to `cells`, float64[C][d+1][np] (GL test functions)."""
+def residual(mesh, U, cells, flux="upwind", storage="gl"):
+    """Right-hand side r = -K U restricted to `cells`, float64[C][d+1][np]
+    (test functions and U in the storage basis)."""
     d = mesh.dim
-    T = tables(mesh)
+    T = tables(mesh, storage)
     cells = np.atleast_1d(np.asarray(cells, dtype=np.int64))
     cd = mesh.cell_data(cells)
     Uc = U[cells]
@@ -118,7 +140,7 @@ def residual(mesh, U, cells, flux="upwind"):
         up = exterior_state(um, nrm, nb, d)
         for cd in np.unique(fd["code"][inner]):
             sel = inner & (fd["code"] == cd)
-            phin = basis.tensor_basis(mesh.xgl, mesh.neighbor_face_points(f, cd))
+            phin = basis.tensor_basis(T.nodes, mesh.neighbor_face_points(f, cd))
             up[sel] = np.einsum("qi,cvi->cvq", phin, U[nb[sel]])
         vnm = np.einsum("cqa,caq->cq", nrm, um[:, :d, :])
         vnp = np.einsum("cqa,caq->cq", nrm, up[:, :d, :])
@@ -128,9 +150,9 @@ def residual(mesh, U, cells, flux="upwind"):
     return r
 
 
-def mass_matrices(mesh, cells):
+def mass_matrices(mesh, cells, storage="gl"):
     """Dense per-cell mass matrices (M_v, M_p), each float64[C][np][np]."""
-    T = tables(mesh)
+    T = tables(mesh, storage)
     cd = mesh.cell_data(cells)
     wv = cd["wdet"] * cd["rho"]
     wp = cd["wdet"] / (cd["rho"] * cd["c"] ** 2)
@@ -139,17 +161,18 @@ def mass_matrices(mesh, cells):
     return Mv, Mp
 
 
-def cholesky_factors(mesh, cells):
+def cholesky_factors(mesh, cells, storage="gl"):
     """Lower Cholesky factors of (M_v, M_p); cached for meshes small enough."""
     cells = np.atleast_1d(np.asarray(cells, dtype=np.int64))
     if not mesh._allow_cache or mesh.nc * 2 * mesh.np_ ** 2 * 8 > 1.0e9:
-        Mv, Mp = mass_matrices(mesh, cells)
+        Mv, Mp = mass_matrices(mesh, cells, storage)
         return np.linalg.cholesky(Mv), np.linalg.cholesky(Mp)
-    full = mesh._cache.get("chol")
+    key = "chol" if storage == "gl" else "chol_" + storage
+    full = mesh._cache.get(key)
     if full is None:
-        Mv, Mp = mass_matrices(mesh, np.arange(mesh.nc))
+        Mv, Mp = mass_matrices(mesh, np.arange(mesh.nc), storage)
         full = (np.linalg.cholesky(Mv), np.linalg.cholesky(Mp))
-        mesh._cache["chol"] = full
+        mesh._cache[key] = full
     return full[0][cells], full[1][cells]
 
 
@@ -159,10 +182,10 @@ def _chol_apply(L, r):
     return np.swapaxes(x, -1, -2)
 
 
-def apply_mass_inverse(mesh, r, cells):
+def apply_mass_inverse(mesh, r, cells, storage="gl"):
     """M^-1 r with the dense per-cell mass matrices (Cholesky)."""
     d = mesh.dim
-    Lv, Lp = cholesky_factors(mesh, cells)
+    Lv, Lp = cholesky_factors(mesh, cells, storage)
     out = np.empty_like(r)
     out[:, :d, :] = _chol_apply(Lv, r[:, :d, :])
     out[:, d:, :] = _chol_apply(Lp, r[:, d:, :])
@@ -176,18 +199,25 @@ def _chunks(mesh, cells):
         yield cells[s:s + step]
 
 
-def apply_operator(mesh, U, cells=None, flux="upwind"):
+def apply_operator(mesh, U, cells=None, flux="upwind", storage="gl"):
     """L U = M^-1 (-K U) (Sec. 2.1, eq. matrix-tc-sd) on `cells` (default all).
 
-    U: float64[Nc][d+1][np] GL coefficients of the full state (neighbours are
-    read).  Returns float64[C][d+1][np].
+    U: float64[Nc][d+1][np] coefficients of the full state in the storage
+    basis (neighbours are read).  Returns float64[C][d+1][np].
     """
     U = np.asarray(U, dtype=np.float64)
     cells = np.arange(mesh.nc) if cells is None else np.atleast_1d(np.asarray(cells, dtype=np.int64))
     out = np.empty((len(cells), mesh.dim + 1, mesh.np_))
     pos = 0
     for ch in _chunks(mesh, cells):
-        r = residual(mesh, U, ch, flux)
-        out[pos:pos + len(ch)] = apply_mass_inverse(mesh, r, ch)
+        r = residual(mesh, U, ch, flux, storage)
+        out[pos:pos + len(ch)] = apply_mass_inverse(mesh, r, ch, storage)
         pos += len(ch)
     return out
+
+
+def gl_to_gauss(mesh, U):
+    """Coefficients in the Gauss storage basis (the values at the cell Gauss
+    points) of a state given in the GL basis: U_G = S U with S[q][i] the GL
+    Lagrange polynomial i at Gauss point q (Sec. 3.2)."""
+    return np.einsum("qi,cvi->cvq", tables(mesh).phi, np.asarray(U, dtype=np.float64))

@@ -84,7 +84,7 @@ def read_traffic(kernel, workload, precision):
     return float(t.group(1))
 
 
-def make_c2(B, precision, ncell=24, k=5, seed=1805):
+def make_c2(B, precision, ncell=24, k=5, seed=1805, storage_basis=0):
     import numpy as np
     import torch
     import workloads as W
@@ -92,9 +92,19 @@ def make_c2(B, precision, ncell=24, k=5, seed=1805):
     wl = W.c2_workload(ncell, k, seed)
     mat = dg.fourier_material_struct(wl["material"])
     mesh = dg.Mesh(3, k, W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell), mat,
-                   precision=dg.FP32_SPLIT if precision == "fp32" else dg.FP64, max_batch=B)
+                   precision=dg.FP32_SPLIT if precision == "fp32" else dg.FP64, max_batch=B,
+                   storage_basis=storage_basis)
     x = mesh.get(dg.GET_NODE_COORDS)
     u0 = np.ascontiguousarray(np.moveaxis(wl["ic"](x), -1, 1))
+    if storage_basis == dg.BASIS_GAUSS:
+        # the GL interpolant of the initial state, evaluated at the Gauss
+        # points with the library's own 1D GL -> Gauss matrix
+        n = k + 1
+        S = dg.basis_1d(n, 4)
+        a = u0.reshape(u0.shape[:2] + (n, n, n))
+        for ax in (2, 3, 4):
+            a = np.moveaxis(np.tensordot(a, S, axes=([ax], [1])), -1, ax)
+        u0 = np.ascontiguousarray(a.reshape(u0.shape))
     return mesh, torch.from_numpy(u0).to("cuda")[None].contiguous(), wl
 
 
@@ -392,7 +402,11 @@ def ablations(steps=10, warmup=2):
     (the paper's optimized updater) or as three BLAS-1 passes (its standard
     one); ADER with the degree reduction every second derivative (Alg. 3),
     every derivative, every third and without, and the HDG-ADER variant (one
-    more operator sweep per step).  Per variant: ms per step
+    more operator sweep per step); the storage basis of the Runge-Kutta
+    operator (Sec. 3.1): GL nodes with the basis change inside the kernel
+    against Lagrange polynomials in the Gauss points (no basis change,
+    diagonal mass, whole neighbour lines read for the face traces), for the
+    operator alone and for the LSRK step.  Per variant: ms per step
     and the mean duration of each component."""
     import torch
     from paper_1805_03981_amd import binding as dg
@@ -423,6 +437,40 @@ def ablations(steps=10, warmup=2):
                      "components_ms": {k: v[0] for k, v in prof.items()},
                      "launches_per_step": {k: v[1] / 3 for k, v in prof.items()}}
         log(f"[bench] ablation {name}: {out[name]}")
+    # storage basis: the operator alone (dgw_operator_apply) and the fused LSRK step
+    del work
+    for basis_name, sb in (("gl", dg.BASIS_GL), ("gauss", dg.BASIS_GAUSS)):
+        m2, v0, _ = (mesh, u0, None) if sb == dg.BASIS_GL else make_c2(1, "fp64", storage_basis=sb)
+        m2.autotune(1)
+        r = torch.empty_like(v0)
+        for _ in range(warmup):
+            m2.apply(v0, out=r)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5 * steps):
+            m2.apply(v0, out=r)
+        torch.cuda.synchronize()
+        ms_op = 1e3 * (time.perf_counter() - t0) / (5 * steps)
+        out[f"operator_{basis_name}_basis"] = {"ms_per_apply": ms_op,
+                                               "dof_per_s": m2.info.dofs / (ms_op * 1e-3)}
+        log(f"[bench] ablation operator_{basis_name}_basis: {out[f'operator_{basis_name}_basis']}")
+        if sb == dg.BASIS_GAUSS:
+            w2 = m2.work(1)
+            dt = CR["lsrk"] * m2.info.dt_unit
+            u = v0.clone()
+            m2.step_lsrk(u, 0.0, dt, warmup, work=w2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m2.step_lsrk(u, 0.0, dt, steps, work=w2)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / steps
+            prof = m2.profile(v0.clone(), dg.LSRK54, 0.0, dt, 3, work=w2)
+            out["lsrk_fused_gauss_basis"] = {"ms_per_step": ms, "dof_steps_per_s": m2.info.dofs / (ms * 1e-3),
+                                             "components_ms": {k: v[0] for k, v in prof.items()},
+                                             "launches_per_step": {k: v[1] / 3 for k, v in prof.items()}}
+            log(f"[bench] ablation lsrk_fused_gauss_basis: {out['lsrk_fused_gauss_basis']}")
+            del m2, v0, u, w2, r
+            torch.cuda.empty_cache()
     return out
 
 

@@ -95,6 +95,21 @@ enum { DGW_ADER_REDUCE_EVERY_STEP = 4, DGW_ADER_REDUCE_EVERY_THIRD = 8 };
  * memory): the mesh can be inspected with dgw_mesh_get but not stepped. */
 #define DGW_DEVICE_NONE (-1)
 
+/* Storage basis of the state (Sec. 3.1 compares the two for the Runge-Kutta
+ * operator).  DGW_BASIS_GL: Lagrange polynomials in the k+1 Gauss-Lobatto
+ * points per direction, nodes on the faces; the kernels change to the Gauss
+ * basis and back (Sec. 3.2).  DGW_BASIS_GAUSS: Lagrange polynomials in the
+ * k+1 Gauss points (the collocated setup): u holds the values at the cell's
+ * Gauss points in the same lexicographic order, the mass matrix is diagonal,
+ * but a face trace needs the neighbour's whole line of values along the face
+ * normal.  Same discrete operator: L_Gauss = S L_GL S^-1 with S the
+ * tensor-product interpolation from the GL nodes to the Gauss points.  A
+ * Gauss-basis mesh supports dgw_operator_apply and dgw_step_lsrk (no sources)
+ * and dgw_step_profile for LSRK, with DGW_FP64 only; every other call on it
+ * returns DGW_EUNSUPPORTED. */
+#define DGW_BASIS_GL 0
+#define DGW_BASIS_GAUSS 1
+
 /* Material callback, evaluated on the host at mapped points during setup.
  * x: [npts][dim] physical points; writes rho[npts], c[npts]. */
 typedef void (*dgw_material_fn)(const double* x, int64_t npts, int dim, double* rho, double* c,
@@ -127,6 +142,7 @@ typedef struct dgw_mesh_desc {
   int precision;             /* DGW_FP64 or DGW_FP32_SPLIT                      */
   int device;                /* HIP device ordinal or DGW_DEVICE_NONE           */
   int max_batch;             /* >= 1: largest B accepted by the stepping calls  */
+  int storage_basis;         /* DGW_BASIS_GL (0, default) or DGW_BASIS_GAUSS    */
 } dgw_mesh_desc;
 
 /* Builds the setup of Sec. 3 on the host in FP64: 1D Gauss / GL rules and

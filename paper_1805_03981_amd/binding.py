@@ -22,6 +22,7 @@ lib = C.CDLL(LIB_PATH)
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EUNSTABLE, EBUSY = 0, -1, -2, -3, -4, -5, -6
 FLUX_UPWIND, FLUX_CENTRAL = 0, 1
 FP64, FP32_SPLIT = 0, 1
+BASIS_GL, BASIS_GAUSS = 0, 1
 LSRK54, ADER = 0, 1
 LSRK54_MERGED_VU, LSRK54_STANDARD_VU = 2, 3   # unfused LSRK variants (ablation)
 ADER_REDUCE, ADER_NOREDUCE, ADER_HDG = 0, 1, 2
@@ -37,7 +38,8 @@ class MeshDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("degree", C.c_int), ("n_cells", C.c_int64), ("geo_degree", C.c_int),
                 ("geo_nodes", C.POINTER(C.c_double)), ("neighbors", C.POINTER(C.c_int64)),
                 ("face_orient", C.POINTER(C.c_int)), ("material", MATERIAL_FN), ("material_ctx", C.c_void_p),
-                ("flux", C.c_int), ("precision", C.c_int), ("device", C.c_int), ("max_batch", C.c_int)]
+                ("flux", C.c_int), ("precision", C.c_int), ("device", C.c_int), ("max_batch", C.c_int),
+                ("storage_basis", C.c_int)]
 
 
 class MeshInfo(C.Structure):
@@ -188,7 +190,7 @@ class Mesh:
     """Owns a dgw_mesh.  Create with Mesh(...) from explicit nodes or Mesh.box(...)."""
 
     def __init__(self, dim, degree, geo_nodes, neighbors, material, flux=FLUX_UPWIND, precision=FP64,
-                 device=0, max_batch=1, geo_degree=0, face_orient=None):
+                 device=0, max_batch=1, geo_degree=0, face_orient=None, storage_basis=BASIS_GL):
         nodes = np.ascontiguousarray(geo_nodes, dtype=np.float64)
         nb = np.ascontiguousarray(neighbors, dtype=np.int64)
         fo = None if face_orient is None else np.ascontiguousarray(face_orient, dtype=np.int32)
@@ -204,7 +206,7 @@ class Mesh:
         d = MeshDesc(dim=dim, degree=degree, n_cells=nodes.shape[0], geo_degree=geo_degree,
                      geo_nodes=_dptr(nodes), neighbors=nb.ctypes.data_as(C.POINTER(C.c_int64)),
                      face_orient=None if fo is None else fo.ctypes.data_as(C.POINTER(C.c_int)), material=self._cb, material_ctx=ctx, flux=flux, precision=precision,
-                     device=device, max_batch=max_batch)
+                     device=device, max_batch=max_batch, storage_basis=storage_basis)
         h = C.c_void_p()
         check(lib.dgw_mesh_create(C.byref(d), C.byref(h)), "dgw_mesh_create")
         self.h = h

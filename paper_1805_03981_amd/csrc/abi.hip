@@ -112,6 +112,20 @@ static dgw_status check_mesh(const dgw_mesh* m) {
   return DGW_OK;
 }
 
+// Calls that assume the GL storage basis (the ADER sweeps, sources, energy,
+// the solver loop) reject a Gauss-basis mesh.
+static dgw_status check_gl_basis(const dgw_mesh* m, const char* what) {
+  if (m->basis != DGW_BASIS_GL)
+    return fail(DGW_EUNSUPPORTED, std::string(what) + " needs the GL storage basis (DGW_BASIS_GL)");
+  return DGW_OK;
+}
+
+// The operator launcher for epilogue epi and launch shape sel in the mesh's
+// storage basis (only EPI_STORE and EPI_LSRK exist for the Gauss basis).
+static OpLaunch op_launch(const dgw_mesh* m, int epi, int sel) {
+  return m->basis == DGW_BASIS_GAUSS ? m->L->op_gauss[epi][sel] : m->L->op[epi][sel];
+}
+
 static dgw_status set_device(const dgw_mesh* m) {
   DGW_HIP(hipSetDevice(m->device));
   return DGW_OK;
@@ -189,7 +203,7 @@ static dgw_status lsrk_step(dgw_mesh* m, int B, const dgw_sources* src, double t
     p.acoef = kLsrk.A[i];
     p.bcoef = kLsrk.B[i];
     p.time.t_off = kLsrk.C[i] * dt;
-    DGW_HIP(m->L->op[EPI_LSRK][m->op_shape.sel](p, s));
+    DGW_HIP(op_launch(m, EPI_LSRK, m->op_shape.sel)(p, s));
     std::swap(cur, oth);
   }
   return DGW_OK;
@@ -302,7 +316,7 @@ static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* sr
     OpParams w = op_params(m, B, nullptr);
     w.u = cur;
     w.out = I;
-    DGW_HIP(m->L->op[EPI_STORE][m->op_shape.sel](w, s));
+    DGW_HIP(op_launch(m, EPI_STORE, m->op_shape.sel)(w, s));
     tp.u = I;
     tp.u_base = cur;
     DGW_HIP(m->L->tck_hdg[sel](tp, s));
@@ -391,7 +405,7 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
       p.groups = (int)((m->hs.nc + cpw - 1) / cpw);
       p.u = a;
       p.out = b;
-      const float t = time_it([&]() { return m->L->op[EPI_STORE][sel](p, s); });
+      const float t = time_it([&]() { return op_launch(m, EPI_STORE, sel)(p, s); });
       if (t < t_op) {
         t_op = t;
         best_op.sel = sel;
@@ -518,12 +532,17 @@ dgw_status dgw_mesh_create(const dgw_mesh_desc* desc, dgw_mesh** out) {
   if (desc->precision != DGW_FP64 && desc->precision != DGW_FP32_SPLIT) return fail(DGW_EINVAL, "bad precision");
   if (desc->max_batch < 1) return fail(DGW_EINVAL, "max_batch must be >= 1");
   if (desc->n_cells > (int64_t)1 << 30) return fail(DGW_EUNSUPPORTED, "too many cells");
+  if (desc->storage_basis != DGW_BASIS_GL && desc->storage_basis != DGW_BASIS_GAUSS)
+    return fail(DGW_EINVAL, "storage_basis must be DGW_BASIS_GL or DGW_BASIS_GAUSS");
+  if (desc->storage_basis == DGW_BASIS_GAUSS && desc->precision != DGW_FP64)
+    return fail(DGW_EUNSUPPORTED, "the Gauss storage basis is built for DGW_FP64 only");
   std::unique_ptr<dgw_mesh> m(new (std::nothrow) dgw_mesh);
   if (!m) return fail(DGW_ENOMEM, "host allocation");
   m->precision = desc->precision;
   m->flux = desc->flux;
   m->device = desc->device;
   m->max_batch = desc->max_batch;
+  m->basis = desc->storage_basis;
   const int n = desc->degree + 1;
   m->np = ipw(n, desc->dim);
   m->nf = ipw(n, desc->dim - 1);
@@ -630,7 +649,7 @@ dgw_status dgw_operator_apply(dgw_mesh* m, const double* u, double* out, int B, 
   OpParams p = op_params(m, B, nullptr);
   p.u = u;
   p.out = out;
-  DGW_HIP(m->L->op[EPI_STORE][m->op_shape.sel](p, (hipStream_t)stream));
+  DGW_HIP(op_launch(m, EPI_STORE, m->op_shape.sel)(p, (hipStream_t)stream));
   return DGW_OK;
 }
 
@@ -669,7 +688,7 @@ dgw_status dgw_step_lsrk(dgw_mesh* m, int scheme, double t0, double dt, int nste
     p.out = r;
     for (int k = 0; k < nsteps; ++k)
       for (int i = 0; i < 5; ++i) {
-        DGW_HIP(m->L->op[EPI_STORE][m->op_shape.sel](p, s));
+        DGW_HIP(op_launch(m, EPI_STORE, m->op_shape.sel)(p, s));
         if ((st = lsrk_vector_update(scheme, i, dt, u, du, r, state_elems(m) * B, s))) return st;
       }
     return DGW_OK;
@@ -688,6 +707,7 @@ dgw_status dgw_step_ader(dgw_mesh* m, int flags, double t0, double dt, int nstep
   dgw_status st = check_ader_flags(flags, src);
   if (st) return st;
   if ((st = check_step(m, dt, nsteps, u, work, B, src))) return st;
+  if ((st = check_gl_basis(m, "ADER"))) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
   if ((st = ensure_period_levels(m, ader_period(flags)))) return st;
@@ -714,6 +734,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
   }
   dgw_status st = check_step(m, dt, nsteps, u, work, B, src);
   if (st) return st;
+  if (scheme == DGW_SCHEME_ADER && (st = check_gl_basis(m, "ADER"))) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
   if (scheme == DGW_SCHEME_ADER && (st = ensure_period_levels(m, ader_period(flags)))) return st;
@@ -748,7 +769,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
       p.out = oth;
       for (int i = 0; i < 5 && !st; ++i) {
         st = timed(0, [&]() -> dgw_status {
-          DGW_HIP(m->L->op[EPI_STORE][m->op_shape.sel](p, s));
+          DGW_HIP(op_launch(m, EPI_STORE, m->op_shape.sel)(p, s));
           return DGW_OK;
         });
         if (!st) st = timed(1, [&] { return lsrk_vector_update(scheme, i, dt, u, aux, oth, state_elems(m) * B, s); });
@@ -765,7 +786,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
         p.bcoef = kLsrk.B[i];
         p.time.t_off = kLsrk.C[i] * dt;
         st = timed(0, [&]() -> dgw_status {
-          DGW_HIP(m->L->op[EPI_LSRK][m->op_shape.sel](p, s));
+          DGW_HIP(op_launch(m, EPI_LSRK, m->op_shape.sel)(p, s));
           return DGW_OK;
         });
         std::swap(cur, oth);
@@ -785,7 +806,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
         w.u = cur;
         w.out = aux;
         st = timed(2, [&]() -> dgw_status {
-          DGW_HIP(m->L->op[EPI_STORE][m->op_shape.sel](w, s));
+          DGW_HIP(op_launch(m, EPI_STORE, m->op_shape.sel)(w, s));
           return DGW_OK;
         });
         tp.u = aux;
@@ -864,6 +885,7 @@ dgw_status dgw_energy(dgw_mesh* m, const double* u, int B, double* host_out, voi
   if (st) return st;
   if (!u || !host_out) return fail(DGW_EINVAL, "NULL argument");
   if ((st = check_batch(m, B, nullptr))) return st;
+  if ((st = check_gl_basis(m, "the energy"))) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
   return energy_impl(m, u, B, host_out, (hipStream_t)stream);
@@ -875,6 +897,7 @@ dgw_status dgw_sources_create(dgw_mesh* m, const dgw_source_desc* desc, dgw_sour
   *out = nullptr;
   dgw_status st = check_mesh(m);
   if (st) return st;
+  if ((st = check_gl_basis(m, "point sources"))) return st;
   if (!desc || desc->n < 1 || !desc->position || !desc->frequency) return fail(DGW_EINVAL, "bad source desc");
   const auto& hs = m->hs;
   const int d = hs.dim, n = hs.n, np = m->np, ng = ipw(hs.q + 1, d);
@@ -1045,6 +1068,7 @@ dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, d
   if (!desc) return fail(DGW_EINVAL, "desc is NULL");
   dgw_status st = check_mesh(m);
   if (st) return st;
+  if ((st = check_gl_basis(m, "dgw_solve_batch (energy watchdog)"))) return st;
   if (desc->scheme != DGW_SCHEME_LSRK54 && desc->scheme != DGW_SCHEME_ADER) return fail(DGW_EINVAL, "bad scheme");
   if (desc->scheme == DGW_SCHEME_ADER && (st = check_ader_flags(desc->ader_flags, desc->sources))) return st;
   const double span = desc->t_end - desc->t0;

@@ -72,6 +72,7 @@ struct LaunchShape {
 struct dgw_mesh {
   dgw::HostSetup hs;
   int precision = 0, flux = 0, device = -1, max_batch = 1;
+  int basis = 0;  // DGW_BASIS_GL or DGW_BASIS_GAUSS
   int np = 0, nf = 0, ncomp = 0, nlev = 0;
   std::vector<int> level_pts;
   const dgw::Launchers* L = nullptr;

@@ -86,6 +86,7 @@ using EnergyLaunch = hipError_t (*)(const EnergyParams&, hipStream_t);
 // cpw[sel]); p.cpw must equal cpw[sel] of the launcher that is called.
 struct Launchers {
   OpLaunch op[3][2];      // [Epilogue][sel]
+  OpLaunch op_gauss[2][2];  // Gauss storage basis, [EPI_STORE / EPI_LSRK][sel]; FP64 only (else nullptr)
   TckLaunch tck[4][2];    // [reduction period 0 (none), 1, 2 (Alg. 3), 3][sel]
   TckLaunch tck_hdg[2];   // HDG-ADER variant (with reduction) [sel]
   EnergyLaunch energy;

@@ -1,6 +1,8 @@
 // Launch wrappers and the launcher table for one (dim, precision) pair; the
 // including translation unit defines DGW_DIM, DGW_T and DGW_INST_NAME.
 #pragma once
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace dgw {
@@ -12,15 +14,24 @@ static hipError_t ensure_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int D, int N, typename T, int EPI, int SEL>
+template <int D, int N, typename T, int EPI, int SEL, bool GB = false>
 hipError_t launch_op(const OpParams& p, hipStream_t s) {
   constexpr int CPW = cells_per_group(D, N, SEL);
   if (p.cpw != CPW) return hipErrorInvalidValue;
   const size_t lds = (size_t)CPW * OpLayout<D, N, T>::per_cell * sizeof(T);
-  hipError_t e = ensure_lds(op_kernel<D, N, T, EPI, CPW>, lds);
+  hipError_t e = ensure_lds(op_kernel<D, N, T, EPI, CPW, GB>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((op_kernel<D, N, T, EPI, CPW>), dim3(p.groups * p.B), dim3(op_threads(D, N)), lds, s, p);
+  hipLaunchKernelGGL((op_kernel<D, N, T, EPI, CPW, GB>), dim3(p.groups * p.B), dim3(op_threads(D, N)), lds, s, p);
   return hipGetLastError();
+}
+
+// Gauss storage basis launchers: FP64 arithmetic only.
+template <int D, int N, typename T, int EPI, int SEL>
+constexpr OpLaunch gauss_op() {
+  if constexpr (std::is_same_v<T, double>)
+    return launch_op<D, N, T, EPI, SEL, true>;
+  else
+    return nullptr;
 }
 
 template <int D, int N, typename T, int R, int SEL, bool HDG = false>
@@ -49,6 +60,8 @@ const Launchers* make_launchers() {
       {{launch_op<D, N, T, EPI_STORE, 0>, launch_op<D, N, T, EPI_STORE, 1>},
        {launch_op<D, N, T, EPI_LSRK, 0>, launch_op<D, N, T, EPI_LSRK, 1>},
        {launch_op<D, N, T, EPI_ADD, 0>, launch_op<D, N, T, EPI_ADD, 1>}},
+      {{gauss_op<D, N, T, EPI_STORE, 0>(), gauss_op<D, N, T, EPI_STORE, 1>()},
+       {gauss_op<D, N, T, EPI_LSRK, 0>(), gauss_op<D, N, T, EPI_LSRK, 1>()}},
       {{launch_tck<D, N, T, 0, 0>, launch_tck<D, N, T, 0, 1>},
        {launch_tck<D, N, T, 1, 0>, launch_tck<D, N, T, 1, 1>},
        {launch_tck<D, N, T, 2, 0>, launch_tck<D, N, T, 2, 1>},

@@ -314,7 +314,12 @@ __device__ __forceinline__ void op_points(const double (&g)[PS][D * D + 2], cons
   }
 }
 
-template <int D, int N, typename T, int EPI, int CPW>
+// GB selects the storage basis of u and of the result: false = Lagrange
+// polynomials in the GL points (nodes on the faces; the operator changes to
+// the Gauss basis and back), true = Lagrange polynomials in the Gauss points
+// (the collocated basis of Sec. 3.1: no basis change, diagonal mass, but a
+// neighbour's trace needs its whole line of values along the face normal).
+template <int D, int N, typename T, int EPI, int CPW, bool GB = false>
 __global__ void __launch_bounds__(op_threads(D, N))
 __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_kernel(OpParams p) {
   using Lay = OpLayout<D, N, T>;
@@ -359,6 +364,14 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
     ev[s] = i < nel ? p.u[gofs + i] : 0.0;
   }
   double nv[NS];
+  double glf0[GB ? N : 1], glf1[GB ? N : 1];  // Gauss basis: face values of the 1D Lagrange polynomials
+  if constexpr (GB) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      glf0[j] = (double)tab[tab_LF0(N) + j];
+      glf1[j] = (double)tab[tab_LF1(N) + j];
+    }
+  }
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int i = tid + s * NT;
@@ -377,8 +390,16 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
         tn = orient_face<D, N>(code & 7, t);
       }
       const int dir = fn >> 1, side = fn & 1;
-      const int q = face_line_base<D, N>(dir, tn) + (side ? (N - 1) * dir_stride(N, dir) : 0);
-      nv[s] = p.u[moff + (int64_t)nbi[s] * NC * NP + v * NP + q];
+      const double* un = p.u + moff + (int64_t)nbi[s] * NC * NP + v * NP;
+      if constexpr (GB) {  // interpolate the neighbour's normal line to its face
+        const int q0 = face_line_base<D, N>(dir, tn), st = dir_stride(N, dir);
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) acc = fma(side ? glf1[j] : glf0[j], un[q0 + j * st], acc);
+        nv[s] = acc;
+      } else {
+        nv[s] = un[face_line_base<D, N>(dir, tn) + (side ? (N - 1) * dir_stride(N, dir) : 0)];
+      }
     }
   }
   double g[PS][G2];
@@ -429,7 +450,7 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
   __syncthreads();
 
   // ---- B: GL -> G of the cell tiles; tangential GL -> G of the neighbour traces
-  {
+  if constexpr (!GB) {
     const T* S = tab + tab_S(N);
     tpass<NT, D, 0, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
     if constexpr (D == 2) tpass<NT, 1, 0, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
@@ -528,7 +549,7 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
     }
   }
   __syncthreads();
-  tensor_apply_inplace<NT, D, N, T>(sR, ncl * NC, tab + tab_Sinv(N));
+  if constexpr (!GB) tensor_apply_inplace<NT, D, N, T>(sR, ncl * NC, tab + tab_Sinv(N));
   // ---- E: epilogue (coalesced, operands prefetched in A)
   {
     int scell = -1;

@@ -15,6 +15,7 @@ import torch
 import workloads as W
 from oracle import Mesh as OMesh
 from oracle import apply_operator, ader, norms, sources as osrc, timestep as ts
+from oracle.operator import gl_to_gauss
 from tolerances import STEP_TOL as TOL, op_tol
 
 pytestmark = pytest.mark.gpu
@@ -178,6 +179,72 @@ def test_steps_with_face_orientations(gpu_lib, scheme):
         for s in range(2):
             want = ader.ader_step(om, want, dt)
     assert rel(u[0].cpu().numpy(), want) < TOL
+
+
+GAUSS_CASES = [(2, 4, 3, None, False, 0), (2, 3, 8, ("wall", "absorbing"), False, 1), (2, 3, 1, None, False, 0),
+               (3, 3, 2, None, False, 0), (3, 2, 5, None, False, 0), (3, 2, 7, ("absorbing", "periodic", "wall"), False, 0),
+               (3, 1, 4, None, False, 1), (3, 3, 3, None, True, 0), (3, 2, 6, None, True, 1)]
+
+
+def build_gauss(B, dim, nc, k, bc, orient, flux):
+    mat = W.FourierMaterial(17, dim=dim)
+    fo = None
+    if orient:
+        nodes, nb, fo, _ = W.rotated_box(dim, nc, k, 0.05, seed=37 + k)
+    else:
+        nodes, nb = W.box_nodes(dim, nc, k, 0.05), W.box_neighbors(dim, nc, bc)
+    gm = B.Mesh(dim, k, nodes, nb, mat, flux=flux, face_orient=fo, storage_basis=B.BASIS_GAUSS)
+    om = OMesh(dim, k, nodes, nb, mat, face_orient=fo)
+    return gm, om
+
+
+@pytest.mark.parametrize("dim,nc,k,bc,orient,flux", GAUSS_CASES)
+def test_operator_gauss_basis_fp64(gpu_lib, dim, nc, k, bc, orient, flux):
+    """Collocated Gauss storage basis (Sec. 3.1): against the oracle's direct
+    Gauss-basis weak form, and against the GL kernel mapped by S."""
+    say("operator gauss", dim, nc, k, bc, orient, flux)
+    gm, om = build_gauss(gpu_lib, dim, nc, k, bc, orient, flux)
+    fl = "central" if flux else "upwind"
+    U = W.random_state(dim * 11 + k, (om.nc, dim + 1, om.np_))
+    got = gm.apply(to_dev(U)).cpu().numpy()
+    assert rel(got, apply_operator(om, U, flux=fl, storage="gauss")) < op_tol(k, dim)
+    if not orient:
+        gl, _ = build(gpu_lib, dim, nc, k, 0.05, mat=W.FourierMaterial(17, dim=dim), flux=flux, bc=bc)
+        V = W.random_state(dim * 13 + k, (om.nc, dim + 1, om.np_))
+        r_gl = gl.apply(to_dev(V)).cpu().numpy()
+        r_g = gm.apply(to_dev(gl_to_gauss(om, V))).cpu().numpy()
+        assert rel(r_g, gl_to_gauss(om, r_gl)) < op_tol(k, dim)
+
+
+@pytest.mark.parametrize("scheme", [0, 3])
+def test_lsrk_gauss_basis_fp64(gpu_lib, scheme):
+    say("lsrk gauss", scheme)
+    dim, nc, k = 3, 3, 4
+    gm, om = build_gauss(gpu_lib, dim, nc, k, ("wall", "periodic", "absorbing"), False, 0)
+    U = gl_to_gauss(om, om.interpolate(lambda x: W.gaussian_pulse(x, [0.3, 0.6, 0.5], 0.15)))
+    U = U + 0.01 * W.random_state(19, U.shape)
+    dt = 0.3 * gm.info.dt_unit
+    u = to_dev(U)[None]
+    gm.step_lsrk(u, 0.0, dt, 2, scheme=scheme)
+    want = U
+    for s in range(2):
+        want = ts.lsrk_step(lambda x, t: apply_operator(om, x, storage="gauss"), want, s * dt, dt)
+    assert rel(u[0].cpu().numpy(), want) < TOL
+
+
+def test_gauss_basis_rejects_gl_only_calls(gpu_lib):
+    say("gauss rejects")
+    B = gpu_lib
+    gm, om = build_gauss(B, 3, 2, 3, None, False, 0)
+    u = to_dev(np.zeros((1,) + gm.shape))
+    for call in (lambda: gm.step_ader(u, 0.0, 0.01, 1), lambda: gm.energy(u),
+                 lambda: gm.solve(u, B.LSRK54, 0.01, dt=0.005), lambda: B.Sources(gm, [[0.5, 0.5, 0.5]], 8.0),
+                 lambda: gm.profile(u, B.ADER, 0.0, 0.01, 1)):
+        with pytest.raises(B.DgwError) as e:
+            call()
+        assert e.value.status == B.EUNSUPPORTED
+    prof = gm.profile(u, B.LSRK54, 0.0, 0.01, 1)  # LSRK profiling works
+    assert prof is not None
 
 
 @pytest.mark.parametrize("dim,nc,k,reduce", [(2, 4, 3, True), (2, 3, 4, True), (3, 3, 3, True), (3, 2, 5, True),

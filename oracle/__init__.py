@@ -17,5 +17,5 @@ right-hand side (no closed form exists for a point source on a curved mesh
 with variable coefficients) -- "parity unpinned" there, see oracle/sources.py.
 """
 from . import basis, mesh, operator, timestep, ader, norms, sources  # noqa: F401
-from .mesh import Mesh, BC_WALL, BC_ABSORBING  # noqa: F401
+from .mesh import Mesh, BC_WALL, BC_ABSORBING, BC_PRESCRIBED  # noqa: F401
 from .operator import apply_operator  # noqa: F401

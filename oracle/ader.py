@@ -170,11 +170,13 @@ def tck(mesh, U, dt, cells=None, reduce=True, source_terms=None, period=2):
     return np.ascontiguousarray(np.swapaxes(Ig, -1, -2))
 
 
-def ader_step(mesh, U, dt, flux="upwind", reduce=True, source=None, t=0.0, period=2):
-    """One ADER step u + L_h(I) (+ the exact time integral of the source)."""
+def ader_step(mesh, U, dt, flux="upwind", reduce=True, source=None, t=0.0, period=2, exterior_integral=None):
+    """One ADER step u + L_h(I) (+ the exact time integral of the source).
+    Prescribed boundary faces take exterior_integral(x), the time integral of
+    the exterior state over [t, t + dt], as the exterior state of I."""
     st = None if source is None else source.tck_terms(mesh, t)
     I = tck(mesh, U, dt, reduce=reduce, source_terms=st, period=period)
-    out = np.asarray(U, dtype=np.float64) + apply_operator(mesh, I, flux=flux)
+    out = np.asarray(U, dtype=np.float64) + apply_operator(mesh, I, flux=flux, exterior=exterior_integral)
     if source is not None:
         out = out + source.integral(t, t + dt) * source.vector_full(mesh)
     return out

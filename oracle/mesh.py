@@ -23,8 +23,8 @@ from . import basis
 
 
 # Boundary codes of the neighbour table: rigid (sound-hard) wall, first-order
-# absorbing boundary.
-BC_WALL, BC_ABSORBING = -1, -2
+# absorbing boundary, prescribed exterior state.
+BC_WALL, BC_ABSORBING, BC_PRESCRIBED = -1, -2, -3
 
 
 class Mesh:
@@ -32,8 +32,9 @@ class Mesh:
 
     geo_nodes: float64[Nc][(q+1)^d][d]; neighbors: int64[Nc][2d] in face order
     -x,+x,-y,+y,-z,+z; a negative entry marks a face on the domain boundary
-    with its condition (BC_WALL, BC_ABSORBING; the paper leaves the boundary
-    conditions open, Sec. 2); material: callable x[...,d] -> (rho, c).
+    with its condition (BC_WALL, BC_ABSORBING, BC_PRESCRIBED; the paper
+    leaves the boundary conditions open, Sec. 2); material: callable
+    x[...,d] -> (rho, c).
     face_orient: None (every neighbour meets face f with its face f^1, the
     tangential coordinates aligned) or int[Nc][2d] with 8 f' + o: the
     neighbour's face f' and the orientation o that maps the own tangential
@@ -47,8 +48,9 @@ class Mesh:
         self.n = self.k + 1
         self.geo_nodes = np.ascontiguousarray(geo_nodes, dtype=np.float64)
         self.neighbors = np.ascontiguousarray(neighbors, dtype=np.int64)
-        if np.any((self.neighbors < 0) & (self.neighbors != BC_WALL) & (self.neighbors != BC_ABSORBING)):
-            raise ValueError("negative neighbour entries must be BC_WALL or BC_ABSORBING")
+        if np.any((self.neighbors < 0) & (self.neighbors != BC_WALL) & (self.neighbors != BC_ABSORBING)
+                  & (self.neighbors != BC_PRESCRIBED)):
+            raise ValueError("negative neighbour entries must be BC_WALL, BC_ABSORBING or BC_PRESCRIBED")
         if face_orient is None:
             fo = np.array([8 * (f ^ 1) for f in range(2 * self.dim)], dtype=np.int64)
             self.face_orient = np.broadcast_to(fo, self.neighbors.shape).copy()

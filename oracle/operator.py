@@ -31,7 +31,10 @@ Sec. 2; reading): the exterior state is built from the own trace and goes
 through the same flux with Z+ = Z-.  Rigid wall (v.n = 0): the mirror state
 p+ = p-, v+ = v- - 2 (v-.n) n, so that v*_n = 0 for both fluxes.  First-order
 absorbing boundary: p+ = 0, v+ = 0, so that the upwind flux keeps only the
-outgoing characteristic (p- + Z v-.n)/2.
+outgoing characteristic (p- + Z v-.n)/2.  Prescribed exterior state: u+ is
+given data u_ext(x) at the face points (the caller chooses its time: the
+stage time for Runge-Kutta, the time integral over the step for ADER, whose
+update L(I) is linear in the exterior state of I).
 
 The operator is evaluated with the full d-dimensional GL basis tables at the
 quadrature points (no sum factorization) and the dense per-cell mass matrices
@@ -52,7 +55,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import basis
-from .mesh import BC_WALL
+from .mesh import BC_WALL, BC_PRESCRIBED
 
 
 def storage_nodes(mesh, storage):
@@ -98,21 +101,27 @@ def numerical_flux(pm, pp, vnm, vnp, Zm, Zp, flux):
     return ps, vs
 
 
-def exterior_state(um, nrm, nb, d):
+def exterior_state(um, nrm, nb, d, x=None, exterior=None):
     """Neighbour trace float64[C][d+1][Qf] of boundary faces from the own
     trace um and the unit normals nrm[C][Qf][d] (rows with nb >= 0 are left
-    zero for the caller to fill)."""
+    zero for the caller to fill); prescribed faces take exterior(x) at their
+    points x[C][Qf][d] (a state float64[...][Qf][d+1])."""
     up = np.zeros_like(um)
     wall = nb == BC_WALL
     if np.any(wall):
         vn = np.einsum("cqa,caq->cq", nrm[wall], um[wall, :d, :])
         up[wall, :d, :] = um[wall, :d, :] - 2.0 * vn[:, None, :] * np.moveaxis(nrm[wall], -1, 1)
         up[wall, d, :] = um[wall, d, :]
+    pres = nb == BC_PRESCRIBED
+    if np.any(pres):
+        if exterior is None:
+            raise ValueError("the mesh has prescribed boundary faces: give the exterior state")
+        up[pres] = np.moveaxis(np.asarray(exterior(x[pres]), dtype=np.float64), -1, 1)
     # BC_ABSORBING: zero exterior state
     return up
 
 
-def residual(mesh, U, cells, flux="upwind", storage="gl"):
+def residual(mesh, U, cells, flux="upwind", storage="gl", exterior=None):
     """Right-hand side r = -K U restricted to `cells`, float64[C][d+1][np]
     (test functions and U in the storage basis)."""
     d = mesh.dim
@@ -137,7 +146,7 @@ def residual(mesh, U, cells, flux="upwind", storage="gl"):
         nrm = a / area[..., None]
         nb = fd["nb"]
         inner = nb >= 0
-        up = exterior_state(um, nrm, nb, d)
+        up = exterior_state(um, nrm, nb, d, fd["x"], exterior)
         for cd in np.unique(fd["code"][inner]):
             sel = inner & (fd["code"] == cd)
             phin = basis.tensor_basis(T.nodes, mesh.neighbor_face_points(f, cd))
@@ -199,18 +208,20 @@ def _chunks(mesh, cells):
         yield cells[s:s + step]
 
 
-def apply_operator(mesh, U, cells=None, flux="upwind", storage="gl"):
+def apply_operator(mesh, U, cells=None, flux="upwind", storage="gl", exterior=None):
     """L U = M^-1 (-K U) (Sec. 2.1, eq. matrix-tc-sd) on `cells` (default all).
 
     U: float64[Nc][d+1][np] coefficients of the full state in the storage
-    basis (neighbours are read).  Returns float64[C][d+1][np].
+    basis (neighbours are read); exterior: the prescribed exterior state
+    x[...][d] -> float64[...][d+1] for BC_PRESCRIBED faces.  Returns
+    float64[C][d+1][np].
     """
     U = np.asarray(U, dtype=np.float64)
     cells = np.arange(mesh.nc) if cells is None else np.atleast_1d(np.asarray(cells, dtype=np.int64))
     out = np.empty((len(cells), mesh.dim + 1, mesh.np_))
     pos = 0
     for ch in _chunks(mesh, cells):
-        r = residual(mesh, U, ch, flux, storage)
+        r = residual(mesh, U, ch, flux, storage, exterior)
         out[pos:pos + len(ch)] = apply_mass_inverse(mesh, r, ch, storage)
         pos += len(ch)
     return out

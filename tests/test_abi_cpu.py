@@ -168,7 +168,7 @@ def test_footprint_and_validation(B):
         B.Mesh(2, 2, W.box_nodes(2, 3, 2, 0.0), nb, mat, device=B.DEVICE_NONE)
     assert e.value.status == B.EINVAL
     nb = W.box_neighbors(2, 3, ("wall", "periodic"))
-    nb[nb == W.BC_WALL] = -3  # not a boundary code
+    nb[nb == W.BC_WALL] = -4  # not a boundary code
     with pytest.raises(B.DgwError) as e:
         B.Mesh(2, 2, W.box_nodes(2, 3, 2, 0.0), nb, mat, device=B.DEVICE_NONE)
     assert e.value.status == B.EINVAL

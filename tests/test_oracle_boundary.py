@@ -59,7 +59,7 @@ def test_box_neighbors_boundary_codes():
     assert nb[8, 1] == BC_WALL and nb[8, 3] == BC_ABSORBING and nb[8, 0] == 7 and nb[8, 2] == 5
     assert (nb >= 0).sum() == 2 * 2 * 3 * 2  # interior faces seen from both sides
     with pytest.raises(ValueError):
-        Mesh(2, 2, W.box_nodes(2, 3, 2, 0.0), np.where(nb < 0, -3, nb), W.ConstantMaterial())
+        Mesh(2, 2, W.box_nodes(2, 3, 2, 0.0), np.where(nb < 0, -4, nb), W.ConstantMaterial())
 
 
 def _energy_rate(m, U, flux):

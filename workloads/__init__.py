@@ -16,6 +16,9 @@ from .generators import (  # noqa: F401
     rotated_box,
     BC_WALL,
     BC_ABSORBING,
+    BC_PRESCRIBED,
+    PlaneWaves,
+    c3_literal_plane_wave,
     FourierMaterial,
     ConstantMaterial,
     standing_wave_2d,

@@ -25,21 +25,23 @@ def _cell_index(idx, n):
 
 
 # Boundary codes in a neighbour table (a face on the domain boundary): a rigid
-# (sound-hard) wall and a first-order absorbing boundary.
-BC_WALL, BC_ABSORBING = -1, -2
+# (sound-hard) wall, a first-order absorbing boundary and a prescribed
+# exterior state.
+BC_WALL, BC_ABSORBING, BC_PRESCRIBED = -1, -2, -3
 
 
 def box_neighbors(dim: int, ncell: int, bc=None) -> np.ndarray:
     """Neighbour table int64[n^dim][2*dim] of the unit box (faces -x,+x,-y,+y,-z,+z).
 
     bc: None (periodic in every direction) or one entry per direction, each
-    "periodic", "wall" or "absorbing": the faces of that direction on the box
-    boundary get BC_WALL / BC_ABSORBING instead of the periodic neighbour.
+    "periodic", "wall", "absorbing" or "prescribed": the faces of that
+    direction on the box boundary get BC_WALL / BC_ABSORBING / BC_PRESCRIBED
+    instead of the periodic neighbour.
     """
     bc = ["periodic"] * dim if bc is None else list(bc)
-    if len(bc) != dim or any(b not in ("periodic", "wall", "absorbing") for b in bc):
-        raise ValueError("bc: one of periodic / wall / absorbing per direction")
-    code = {"wall": BC_WALL, "absorbing": BC_ABSORBING}
+    if len(bc) != dim or any(b not in ("periodic", "wall", "absorbing", "prescribed") for b in bc):
+        raise ValueError("bc: one of periodic / wall / absorbing / prescribed per direction")
+    code = {"wall": BC_WALL, "absorbing": BC_ABSORBING, "prescribed": BC_PRESCRIBED}
     nc = ncell ** dim
     nb = np.empty((nc, 2 * dim), dtype=np.int64)
     grid = np.indices((ncell,) * dim).reshape(dim, -1)[::-1]  # grid[0] = x index (fastest)
@@ -290,6 +292,55 @@ def membrane_mode(x: np.ndarray, t: float = 0.0, m=None) -> np.ndarray:
         others = np.prod(np.delete(cs, a, axis=-1), axis=-1) if dim > 1 else 1.0
         out[..., a] = np.sin(om * t) * (np.pi * m[a] / om) * sn[..., a] * others
     return out
+
+
+class PlaneWaves:
+    """A superposition of acoustic plane waves in a homogeneous medium, the
+    prescribed exterior state of boundary faces and a closed-form solution:
+    wave j has p_j = A_j cos(k_j.x - omega_j t + phi_j) and
+    v_j = p_j k_j / (|k_j| Z_j) (Z = rho c, omega = c |k| for a solution).
+    waves: rows (A, k_1, k_2, k_3, omega, phi, Z), k_3 ignored in 2D."""
+
+    def __init__(self, waves):
+        self.w = np.atleast_2d(np.asarray(waves, dtype=np.float64))
+        assert self.w.shape[1] == 7
+
+    def _parts(self, x):
+        x = np.asarray(x, dtype=np.float64)
+        dim = x.shape[-1]
+        for A, k1, k2, k3, om, ph, Z in self.w:
+            k = np.array([k1, k2, k3])[:dim]
+            yield dim, A, k, om, ph, Z, x @ k + ph
+
+    def __call__(self, x, t=0.0):
+        """State float64[..., d+1] at time t."""
+        x = np.asarray(x, dtype=np.float64)
+        out = np.zeros(x.shape[:-1] + (x.shape[-1] + 1,))
+        for dim, A, k, om, ph, Z, th in self._parts(x):
+            p = A * np.cos(th - om * t)
+            out[..., dim] += p
+            out[..., :dim] += p[..., None] * (k / (np.linalg.norm(k) * Z))
+        return out
+
+    def integral(self, x, t0, dt):
+        """Time integral of the state over [t0, t0 + dt], float64[..., d+1]:
+        int cos(th - om s) ds = 2 cos(th - om (t0 + dt/2)) sin(om dt/2) / om."""
+        x = np.asarray(x, dtype=np.float64)
+        out = np.zeros(x.shape[:-1] + (x.shape[-1] + 1,))
+        for dim, A, k, om, ph, Z, th in self._parts(x):
+            fac = dt if om == 0.0 else 2.0 * np.sin(0.5 * om * dt) / om
+            p = A * fac * np.cos(th - om * (t0 + 0.5 * dt))
+            out[..., dim] += p
+            out[..., :dim] += p[..., None] * (k / (np.linalg.norm(k) * Z))
+        return out
+
+
+def c3_literal_plane_wave():
+    """The plane wave of the 48^3 workload text, p = cos(2 pi (x+y+z)/sqrt 3 -
+    2 pi t), rho = c = 1 (not periodic on the unit cube: needs its own exterior
+    state on every boundary face)."""
+    s = 2.0 * np.pi / np.sqrt(3.0)
+    return PlaneWaves([[1.0, s, s, s, 2.0 * np.pi, 0.0, 1.0]])
 
 
 def travelling_pulse_x(x: np.ndarray, t: float = 0.0, x0: float = 0.6, width: float = 0.05) -> np.ndarray:

@@ -91,6 +91,22 @@ enum { DGW_ADER_REDUCE_EVERY_STEP = 4, DGW_ADER_REDUCE_EVERY_THIRD = 8 };
  * applies them to the time-integrated Taylor sum unchanged. */
 #define DGW_BC_WALL (-1)
 #define DGW_BC_ABSORBING (-2)
+/* DGW_BC_PRESCRIBED: the exterior state is given data, a superposition of
+ * the plane waves of dgw_mesh_desc.plane_waves at the face point x:
+ * p+ = sum A cos(k.x - omega t + phi), v+ = sum A cos(...) k / (|k| Z).  The
+ * time t is the stage time in dgw_step_lsrk; dgw_step_ader uses the exact
+ * time integral of that state over each step (the ADER update applies the
+ * operator to the time-integrated Taylor sum, so its exterior state is the
+ * integrated data); dgw_operator_apply takes t = 0.  Not with DGW_ADER_HDG. */
+#define DGW_BC_PRESCRIBED (-3)
+#define DGW_MAX_PLANE_WAVES 8
+typedef struct dgw_plane_wave {
+  double amplitude;          /* A                                               */
+  double k[3];               /* wave vector, |k| > 0 (k[2] unused in 2D)        */
+  double omega;              /* angular frequency (c |k| for a solution)        */
+  double phase;              /* phi                                             */
+  double impedance;          /* Z = rho c of the wave's medium, > 0             */
+} dgw_plane_wave;
 /* device = DGW_DEVICE_NONE builds the host-side setup only (no device
  * memory): the mesh can be inspected with dgw_mesh_get but not stepped. */
 #define DGW_DEVICE_NONE (-1)
@@ -126,7 +142,8 @@ typedef struct dgw_mesh_desc {
   int geo_degree;            /* q, 1..8; 0 = k                                  */
   const double* geo_nodes;   /* host [n_cells][(q+1)^dim][dim]; copied          */
   const int64_t* neighbors;  /* host [n_cells][2*dim]; a negative entry marks a */
-                             /* boundary face: DGW_BC_WALL or DGW_BC_ABSORBING  */
+                             /* boundary face: DGW_BC_WALL, DGW_BC_ABSORBING or */
+                             /* DGW_BC_PRESCRIBED                               */
   const int* face_orient;    /* NULL: every neighbour meets face f with its     */
                              /* face f^1, tangential coordinates aligned.  Else */
                              /* host int32 [n_cells][2*dim], 8 f' + o: the      */
@@ -143,6 +160,10 @@ typedef struct dgw_mesh_desc {
   int device;                /* HIP device ordinal or DGW_DEVICE_NONE           */
   int max_batch;             /* >= 1: largest B accepted by the stepping calls  */
   int storage_basis;         /* DGW_BASIS_GL (0, default) or DGW_BASIS_GAUSS    */
+  const dgw_plane_wave* plane_waves;  /* host [n_plane_waves]; copied; the    */
+                             /* exterior state of DGW_BC_PRESCRIBED faces       */
+  int n_plane_waves;         /* 0..DGW_MAX_PLANE_WAVES, >= 1 if any face is     */
+                             /* DGW_BC_PRESCRIBED                               */
 } dgw_mesh_desc;
 
 /* Builds the setup of Sec. 3 on the host in FP64: 1D Gauss / GL rules and

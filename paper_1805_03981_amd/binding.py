@@ -34,12 +34,21 @@ MATERIAL_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.c_int, C.POI
                           C.POINTER(C.c_double), C.c_void_p)
 
 
+BC_WALL, BC_ABSORBING, BC_PRESCRIBED = -1, -2, -3
+
+
+class PlaneWave(C.Structure):
+    """p = A cos(k.x - omega t + phi), v = p k / (|k| Z): exterior state of BC_PRESCRIBED faces."""
+    _fields_ = [("amplitude", C.c_double), ("k", C.c_double * 3), ("omega", C.c_double), ("phase", C.c_double),
+                ("impedance", C.c_double)]
+
+
 class MeshDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("degree", C.c_int), ("n_cells", C.c_int64), ("geo_degree", C.c_int),
                 ("geo_nodes", C.POINTER(C.c_double)), ("neighbors", C.POINTER(C.c_int64)),
                 ("face_orient", C.POINTER(C.c_int)), ("material", MATERIAL_FN), ("material_ctx", C.c_void_p),
                 ("flux", C.c_int), ("precision", C.c_int), ("device", C.c_int), ("max_batch", C.c_int),
-                ("storage_basis", C.c_int)]
+                ("storage_basis", C.c_int), ("plane_waves", C.POINTER(PlaneWave)), ("n_plane_waves", C.c_int)]
 
 
 class MeshInfo(C.Structure):
@@ -190,7 +199,8 @@ class Mesh:
     """Owns a dgw_mesh.  Create with Mesh(...) from explicit nodes or Mesh.box(...)."""
 
     def __init__(self, dim, degree, geo_nodes, neighbors, material, flux=FLUX_UPWIND, precision=FP64,
-                 device=0, max_batch=1, geo_degree=0, face_orient=None, storage_basis=BASIS_GL):
+                 device=0, max_batch=1, geo_degree=0, face_orient=None, storage_basis=BASIS_GL, plane_waves=None):
+        """plane_waves: rows (A, k1, k2, k3, omega, phi, Z), the exterior state of BC_PRESCRIBED faces."""
         nodes = np.ascontiguousarray(geo_nodes, dtype=np.float64)
         nb = np.ascontiguousarray(neighbors, dtype=np.int64)
         fo = None if face_orient is None else np.ascontiguousarray(face_orient, dtype=np.int32)
@@ -207,6 +217,13 @@ class Mesh:
                      geo_nodes=_dptr(nodes), neighbors=nb.ctypes.data_as(C.POINTER(C.c_int64)),
                      face_orient=None if fo is None else fo.ctypes.data_as(C.POINTER(C.c_int)), material=self._cb, material_ctx=ctx, flux=flux, precision=precision,
                      device=device, max_batch=max_batch, storage_basis=storage_basis)
+        if plane_waves is not None:
+            rows = np.atleast_2d(np.asarray(plane_waves, dtype=np.float64))
+            self._pw = (PlaneWave * len(rows))()
+            for j, r in enumerate(rows):
+                self._pw[j] = PlaneWave(r[0], (C.c_double * 3)(r[1], r[2], r[3]), r[4], r[5], r[6])
+            d.plane_waves = C.cast(self._pw, C.POINTER(PlaneWave))
+            d.n_plane_waves = len(rows)
         h = C.c_void_p()
         check(lib.dgw_mesh_create(C.byref(d), C.byref(h)), "dgw_mesh_create")
         self.h = h

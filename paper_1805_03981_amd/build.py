@@ -21,7 +21,7 @@ OUT = os.path.join(HERE, "libdgw.so")
 OUT_CEIL = os.path.join(HERE, "libdgw_ceilings.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["abi.hip", "serve.hip", "setup.cpp", "inst_d2_f64.hip", "inst_d2_f32.hip",
+SOURCES = ["abi.hip", "serve.hip", "setup.cpp", "exterior.hip", "inst_d2_f64.hip", "inst_d2_f32.hip",
            "inst_d3_f64.hip", "inst_d3_f32.hip"]
 CEIL_SOURCES = ["ceilings.hip"]
 

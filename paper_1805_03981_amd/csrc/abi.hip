@@ -10,6 +10,7 @@
 #include <new>
 #include <tuple>
 
+#include "dgw_exterior.hpp"
 #include "dgw_host.hpp"
 
 namespace dgw {
@@ -112,6 +113,14 @@ static dgw_status check_mesh(const dgw_mesh* m) {
   return DGW_OK;
 }
 
+// HDG-ADER takes its first derivative from the operator at the step start;
+// the time derivatives of prescribed exterior data are not part of it.
+static dgw_status check_hdg_faces(const dgw_mesh* m, int flags) {
+  if ((flags & DGW_ADER_HDG) && m->hs.prescribed)
+    return fail(DGW_EUNSUPPORTED, "DGW_ADER_HDG is not available with DGW_BC_PRESCRIBED faces");
+  return DGW_OK;
+}
+
 // Calls that assume the GL storage basis (the ADER sweeps, sources, energy,
 // the solver loop) reject a Gauss-basis mesh.
 static dgw_status check_gl_basis(const dgw_mesh* m, const char* what) {
@@ -124,6 +133,30 @@ static dgw_status check_gl_basis(const dgw_mesh* m, const char* what) {
 // storage basis (only EPI_STORE and EPI_LSRK exist for the Gauss basis).
 static OpLaunch op_launch(const dgw_mesh* m, int epi, int sel) {
   return m->basis == DGW_BASIS_GAUSS ? m->L->op_gauss[epi][sel] : m->L->op[epi][sel];
+}
+
+// One operator launch; on a mesh with prescribed faces the exterior state
+// of this launch (at p.time, or integrated over the step for the ADER
+// update) is evaluated first on the same stream.
+static hipError_t run_op(const dgw_mesh* m, int epi, int sel, const OpParams& p, hipStream_t s) {
+  if (m->d_ext) {
+    ExteriorParams q;
+    std::memset(&q, 0, sizeof(q));
+    q.faces = m->d_pfaces;
+    q.bx = m->d_bx;
+    q.geo_face = m->d_face;
+    q.waves = m->d_waves;
+    q.ext = m->d_ext;
+    q.nslots = m->n_pslots;
+    q.dim = m->hs.dim;
+    q.nf = m->nf;
+    q.n_waves = (int)(m->hs.waves.size() / 7);
+    q.integral = epi == EPI_ADD;
+    q.time = p.time;
+    const hipError_t e = launch_exterior(q, s);
+    if (e != hipSuccess) return e;
+  }
+  return op_launch(m, epi, sel)(p, s);
 }
 
 static dgw_status set_device(const dgw_mesh* m) {
@@ -147,6 +180,7 @@ static OpParams op_params(const dgw_mesh* m, int B, const dgw_sources* src) {
   p.geo_face = m->d_face;
   p.nb = m->d_nb;
   p.fo = m->d_fo;
+  p.ext = m->d_ext;
   p.nc = m->hs.nc;
   p.cpw = m->L->cpw[m->op_shape.sel];
   p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
@@ -203,7 +237,7 @@ static dgw_status lsrk_step(dgw_mesh* m, int B, const dgw_sources* src, double t
     p.acoef = kLsrk.A[i];
     p.bcoef = kLsrk.B[i];
     p.time.t_off = kLsrk.C[i] * dt;
-    DGW_HIP(op_launch(m, EPI_LSRK, m->op_shape.sel)(p, s));
+    DGW_HIP(run_op(m, EPI_LSRK, m->op_shape.sel, p, s));
     std::swap(cur, oth);
   }
   return DGW_OK;
@@ -316,7 +350,7 @@ static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* sr
     OpParams w = op_params(m, B, nullptr);
     w.u = cur;
     w.out = I;
-    DGW_HIP(op_launch(m, EPI_STORE, m->op_shape.sel)(w, s));
+    DGW_HIP(run_op(m, EPI_STORE, m->op_shape.sel, w, s));
     tp.u = I;
     tp.u_base = cur;
     DGW_HIP(m->L->tck_hdg[sel](tp, s));
@@ -328,7 +362,7 @@ static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* sr
   p.u_base = cur;
   p.u_next = oth;
   p.time = StepTime{ctr, t0, dt, step_add, 0.0};
-  DGW_HIP(m->L->op[EPI_ADD][m->op_shape.sel](p, s));
+  DGW_HIP(run_op(m, EPI_ADD, m->op_shape.sel, p, s));
   std::swap(cur, oth);
   return DGW_OK;
 }
@@ -405,7 +439,7 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
       p.groups = (int)((m->hs.nc + cpw - 1) / cpw);
       p.u = a;
       p.out = b;
-      const float t = time_it([&]() { return op_launch(m, EPI_STORE, sel)(p, s); });
+      const float t = time_it([&]() { return run_op(m, EPI_STORE, sel, p, s); });
       if (t < t_op) {
         t_op = t;
         best_op.sel = sel;
@@ -455,7 +489,30 @@ static dgw_status upload(dgw_mesh* m) {
   dgw_status st;
   if ((st = alloc_copy(m->d_cell, hs.cell.data(), hs.cell.size()))) return st;
   if ((st = alloc_copy(m->d_face, hs.face.data(), hs.face.size()))) return st;
-  if ((st = alloc_copy(m->d_nb, hs.nb.data(), hs.nb.size()))) return st;
+  {
+    // device neighbour table: a prescribed face carries kBcPrescribed - slot
+    std::vector<int32_t> nbd(hs.nb);
+    std::vector<int64_t> pfaces;
+    for (size_t i = 0; i < nbd.size(); ++i)
+      if (nbd[i] == kBcPrescribed) {
+        nbd[i] = kBcPrescribed - (int32_t)pfaces.size();
+        pfaces.push_back((int64_t)i);
+      }
+    if ((st = alloc_copy(m->d_nb, nbd.data(), nbd.size()))) return st;
+    m->n_pslots = (int64_t)pfaces.size();
+    if (!pfaces.empty()) {
+      const int d = hs.dim, nf = m->nf;
+      std::vector<double> bxp((size_t)pfaces.size() * d * nf);
+      for (size_t j = 0; j < pfaces.size(); ++j)
+        std::copy(hs.face_x.begin() + (size_t)pfaces[j] * d * nf, hs.face_x.begin() + (size_t)(pfaces[j] + 1) * d * nf,
+                  bxp.begin() + j * d * nf);
+      if ((st = alloc_copy(m->d_pfaces, pfaces.data(), pfaces.size()))) return st;
+      if ((st = alloc_copy(m->d_bx, bxp.data(), bxp.size()))) return st;
+      if ((st = alloc_copy(m->d_waves, hs.waves.data(), hs.waves.size()))) return st;
+      std::vector<double> zeros((size_t)pfaces.size() * 2 * nf, 0.0);
+      if ((st = alloc_copy(m->d_ext, zeros.data(), zeros.size()))) return st;
+    }
+  }
   if (!hs.fo.empty() && (st = alloc_copy(m->d_fo, hs.fo.data(), hs.fo.size()))) return st;
   for (int l = 1; l < m->nlev; ++l)
     if ((st = alloc_copy(m->d_level[l], hs.level[l].data(), hs.level[l].size()))) return st;
@@ -475,6 +532,10 @@ static void release(dgw_mesh* m) {
     (void)hipFree(m->d_face);
     (void)hipFree(m->d_nb);
     (void)hipFree(m->d_fo);
+    (void)hipFree(m->d_pfaces);
+    (void)hipFree(m->d_bx);
+    (void)hipFree(m->d_waves);
+    (void)hipFree(m->d_ext);
     for (auto* p : m->d_level) (void)hipFree(p);
     for (auto* p : m->d_level_pts) (void)hipFree(p);
     (void)hipFree(m->d_partial);
@@ -569,6 +630,7 @@ dgw_status dgw_mesh_create(const dgw_mesh_desc* desc, dgw_mesh** out) {
     // the host copy of the bulk geometry is not needed once uploaded
     std::vector<double>().swap(m->hs.cell);
     std::vector<double>().swap(m->hs.face);
+    std::vector<double>().swap(m->hs.face_x);
     for (auto& v : m->hs.level) std::vector<double>().swap(v);
   }
   *out = m.release();
@@ -649,7 +711,7 @@ dgw_status dgw_operator_apply(dgw_mesh* m, const double* u, double* out, int B, 
   OpParams p = op_params(m, B, nullptr);
   p.u = u;
   p.out = out;
-  DGW_HIP(op_launch(m, EPI_STORE, m->op_shape.sel)(p, (hipStream_t)stream));
+  DGW_HIP(run_op(m, EPI_STORE, m->op_shape.sel, p, (hipStream_t)stream));
   return DGW_OK;
 }
 
@@ -688,7 +750,8 @@ dgw_status dgw_step_lsrk(dgw_mesh* m, int scheme, double t0, double dt, int nste
     p.out = r;
     for (int k = 0; k < nsteps; ++k)
       for (int i = 0; i < 5; ++i) {
-        DGW_HIP(op_launch(m, EPI_STORE, m->op_shape.sel)(p, s));
+        p.time = StepTime{nullptr, t0, dt, k, kLsrk.C[i] * dt};  // prescribed data at the stage time
+        DGW_HIP(run_op(m, EPI_STORE, m->op_shape.sel, p, s));
         if ((st = lsrk_vector_update(scheme, i, dt, u, du, r, state_elems(m) * B, s))) return st;
       }
     return DGW_OK;
@@ -708,6 +771,7 @@ dgw_status dgw_step_ader(dgw_mesh* m, int flags, double t0, double dt, int nstep
   if (st) return st;
   if ((st = check_step(m, dt, nsteps, u, work, B, src))) return st;
   if ((st = check_gl_basis(m, "ADER"))) return st;
+  if ((st = check_hdg_faces(m, flags))) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
   if ((st = ensure_period_levels(m, ader_period(flags)))) return st;
@@ -735,6 +799,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
   dgw_status st = check_step(m, dt, nsteps, u, work, B, src);
   if (st) return st;
   if (scheme == DGW_SCHEME_ADER && (st = check_gl_basis(m, "ADER"))) return st;
+  if (scheme == DGW_SCHEME_ADER && (st = check_hdg_faces(m, flags))) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
   if (scheme == DGW_SCHEME_ADER && (st = ensure_period_levels(m, ader_period(flags)))) return st;
@@ -768,8 +833,9 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
       p.u = u;
       p.out = oth;
       for (int i = 0; i < 5 && !st; ++i) {
+        p.time = StepTime{nullptr, t0, dt, k, kLsrk.C[i] * dt};
         st = timed(0, [&]() -> dgw_status {
-          DGW_HIP(op_launch(m, EPI_STORE, m->op_shape.sel)(p, s));
+          DGW_HIP(run_op(m, EPI_STORE, m->op_shape.sel, p, s));
           return DGW_OK;
         });
         if (!st) st = timed(1, [&] { return lsrk_vector_update(scheme, i, dt, u, aux, oth, state_elems(m) * B, s); });
@@ -786,7 +852,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
         p.bcoef = kLsrk.B[i];
         p.time.t_off = kLsrk.C[i] * dt;
         st = timed(0, [&]() -> dgw_status {
-          DGW_HIP(op_launch(m, EPI_LSRK, m->op_shape.sel)(p, s));
+          DGW_HIP(run_op(m, EPI_LSRK, m->op_shape.sel, p, s));
           return DGW_OK;
         });
         std::swap(cur, oth);
@@ -806,7 +872,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
         w.u = cur;
         w.out = aux;
         st = timed(2, [&]() -> dgw_status {
-          DGW_HIP(op_launch(m, EPI_STORE, m->op_shape.sel)(w, s));
+          DGW_HIP(run_op(m, EPI_STORE, m->op_shape.sel, w, s));
           return DGW_OK;
         });
         tp.u = aux;
@@ -827,7 +893,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
       p.time = StepTime{nullptr, t0, dt, k, 0.0};
       if (!st)
         st = timed(1, [&]() -> dgw_status {
-          DGW_HIP(m->L->op[EPI_ADD][m->op_shape.sel](p, s));
+          DGW_HIP(run_op(m, EPI_ADD, m->op_shape.sel, p, s));
           return DGW_OK;
         });
       std::swap(cur, oth);
@@ -1071,6 +1137,7 @@ dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, d
   if ((st = check_gl_basis(m, "dgw_solve_batch (energy watchdog)"))) return st;
   if (desc->scheme != DGW_SCHEME_LSRK54 && desc->scheme != DGW_SCHEME_ADER) return fail(DGW_EINVAL, "bad scheme");
   if (desc->scheme == DGW_SCHEME_ADER && (st = check_ader_flags(desc->ader_flags, desc->sources))) return st;
+  if (desc->scheme == DGW_SCHEME_ADER && (st = check_hdg_faces(m, desc->ader_flags))) return st;
   const double span = desc->t_end - desc->t0;
   if (!(span > 0) || !std::isfinite(span)) return fail(DGW_EINVAL, "t_end must exceed t0");
   double dt = desc->dt > 0 ? desc->dt : desc->courant * m->hs.dt_unit;

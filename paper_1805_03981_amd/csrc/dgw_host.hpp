@@ -44,6 +44,9 @@ struct HostSetup {
   std::vector<double> face;                // [nc][2d][d+2][nf]
   std::vector<std::vector<double>> level;  // [l] (l >= 1): [nc][d*d+2][m_l^d]
   std::vector<double> hK, cK;
+  bool prescribed = false;                 // some face is DGW_BC_PRESCRIBED
+  std::vector<double> face_x;              // [nc][2d][d][nf] face point coordinates (only if prescribed)
+  std::vector<double> waves;               // [n][7]: A, k (3), omega, phi, Z
   double dt_unit = 0, h_min = 0, c_max = 0;
   dgw_material_fn material = nullptr;
   void* material_ctx = nullptr;
@@ -83,6 +86,13 @@ struct dgw_mesh {
   double* d_level_pts[dgw::kMaxLevels + 1] = {};  // other periods' levels, by points per direction
   int32_t* d_nb = nullptr;
   int32_t* d_fo = nullptr;  // face orientation codes, nullptr for the standard faces
+  // prescribed faces (slots in face order): face ids, face point
+  // coordinates, plane waves, and the exterior state of the current launch
+  int64_t n_pslots = 0;
+  int64_t* d_pfaces = nullptr;
+  double* d_bx = nullptr;
+  double* d_waves = nullptr;
+  double* d_ext = nullptr;
   double* d_partial = nullptr;  // energy partial sums [max_batch][groups]
   int64_t device_bytes = 0;
   dgw::LaunchShape op_shape, tck_shape;

@@ -11,7 +11,8 @@ namespace dgw {
 constexpr int kMaxLevels = 9;  // TCK levels: up to k+1 with the reduction every derivative
 
 // Boundary codes of the neighbour table (DGW_BC_WALL, DGW_BC_ABSORBING).
-constexpr int kBcWall = -1, kBcAbsorbing = -2;
+constexpr int kBcWall = -1, kBcAbsorbing = -2, kBcPrescribed = -3;
+constexpr int kMaxPlaneWaves = 8;
 
 // Threads per workgroup for dimension d and n points per direction.  The
 // kernels run one cell per workgroup once a cell has more than 256 points;
@@ -48,6 +49,8 @@ struct OpParams {
   const double* geo_face; // [nc][2d][d+2][n^(d-1)]: a (d), Z-, Z+
   const int* nb;          // [nc][2d]
   const int* fo;          // [nc][2d] 8 f' + o (neighbour face, orientation) or nullptr (f' = f^1, o = 0)
+  const double* ext;      // [slot][2][n^(d-1)]: p+, v+.n of the prescribed faces for this launch, or
+                          // nullptr; nb holds kBcPrescribed - slot for such a face
   int64_t nc;
   int cpw;                // cells per workgroup
   int groups;             // ceil(nc / cpw)

@@ -501,7 +501,8 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
         vnm *= inv_area;
         vnp *= inv_area;
         double pp = up[D];
-        if (fnb[s] < 0) {  // boundary: mirror state (wall) or zero state (absorbing)
+        if (fnb[s] < 0) {  // boundary: mirror state (wall), else zero state (absorbing;
+                           // prescribed data are added below)
           pp = fnb[s] == kBcWall ? um[D] : 0.0;
           vnp = fnb[s] == kBcWall ? -vnm : 0.0;
         }
@@ -518,6 +519,39 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
 #pragma unroll
         for (int e = 0; e < D; ++e) sN[(cf * NC + e) * NF + t] = (T)(-fg[s][e] * ps);
         sN[(cf * NC + D) * NF + t] = (T)(-area * vs);
+      }
+    }
+    // Prescribed faces (device neighbour entry kBcPrescribed - slot): both
+    // fluxes are linear in the exterior state, so the flux of the given data
+    // (p+, v+.n, evaluated for this launch into ext[slot][2][NF]) is added to
+    // the zero-state flux written above.  Same thread as above for each face
+    // point; operands re-read from memory so that this rare path takes no
+    // registers from the loop above.
+    if (p.ext) {
+#pragma unroll 1
+      for (int i = tid; i < ncl * NFACE * NF; i += NT) {
+        const int cf = i / NF, t = i - (i / NF) * NF;
+        const int code = p.nb[cell0 * NFACE + cf];
+        if (code > kBcPrescribed) continue;
+        const double* ex = p.ext + (int64_t)(kBcPrescribed - code) * 2 * NF + t;
+        const double pe = ex[0], vne = ex[NF];
+        const double* fp = p.geo_face + (cell0 * NFACE + cf) * (int64_t)((D + 2) * NF) + t;
+        double area2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < D; ++e) area2 = fma(fp[e * NF], fp[e * NF], area2);
+        double dps, dvs;
+        if (p.central) {
+          dps = 0.5 * pe;
+          dvs = 0.5 * vne;
+        } else {
+          const double Zm = fp[D * NF], Zp = fp[(D + 1) * NF];
+          const double inv = 1.0 / (Zm + Zp);
+          dps = (Zm * pe - Zm * Zp * vne) * inv;
+          dvs = (Zp * vne - pe) * inv;
+        }
+#pragma unroll
+        for (int e = 0; e < D; ++e) sN[(cf * NC + e) * NF + t] += (T)(-fp[e * NF] * dps);
+        sN[(cf * NC + D) * NF + t] += (T)(-sqrt(area2) * dvs);
       }
     }
   }

@@ -13,7 +13,9 @@
 
 #include "dgw_host.hpp"
 
-static_assert(DGW_BC_WALL == dgw::kBcWall && DGW_BC_ABSORBING == dgw::kBcAbsorbing, "boundary codes");
+static_assert(DGW_BC_WALL == dgw::kBcWall && DGW_BC_ABSORBING == dgw::kBcAbsorbing &&
+                  DGW_BC_PRESCRIBED == dgw::kBcPrescribed && DGW_MAX_PLANE_WAVES == dgw::kMaxPlaneWaves,
+              "boundary codes");
 
 namespace dgw {
 
@@ -368,11 +370,27 @@ dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs) {
   for (int64_t c = 0; c < nc; ++c)
     for (int f = 0; f < nface; ++f) {
       const int64_t o = desc.neighbors[c * nface + f];
-      if (o < 0 && o != DGW_BC_WALL && o != DGW_BC_ABSORBING)
-        return fail(DGW_EINVAL, "negative neighbor entries must be DGW_BC_WALL or DGW_BC_ABSORBING");
+      if (o < 0 && o != DGW_BC_WALL && o != DGW_BC_ABSORBING && o != DGW_BC_PRESCRIBED)
+        return fail(DGW_EINVAL, "negative neighbor entries must be DGW_BC_WALL, DGW_BC_ABSORBING or DGW_BC_PRESCRIBED");
+      if (o == DGW_BC_PRESCRIBED) hs.prescribed = true;
       if (o >= nc) return fail(DGW_EINVAL, "neighbor index out of range");
       hs.nb[c * nface + f] = (int32_t)o;
     }
+  if (desc.n_plane_waves < 0 || desc.n_plane_waves > DGW_MAX_PLANE_WAVES ||
+      (desc.n_plane_waves > 0 && !desc.plane_waves))
+    return fail(DGW_EINVAL, "n_plane_waves must be in 0..DGW_MAX_PLANE_WAVES with plane_waves given");
+  if (hs.prescribed && desc.n_plane_waves < 1)
+    return fail(DGW_EINVAL, "DGW_BC_PRESCRIBED faces need plane_waves (the exterior state)");
+  hs.waves.clear();
+  for (int j = 0; j < desc.n_plane_waves; ++j) {
+    const dgw_plane_wave& w = desc.plane_waves[j];
+    const double kk = w.k[0] * w.k[0] + w.k[1] * w.k[1] + (d == 3 ? w.k[2] * w.k[2] : 0.0);
+    const double v[7] = {w.amplitude, w.k[0], w.k[1], d == 3 ? w.k[2] : 0.0, w.omega, w.phase, w.impedance};
+    for (double x : v)
+      if (!std::isfinite(x)) return fail(DGW_EINVAL, "plane wave parameters must be finite");
+    if (!(kk > 0) || !(w.impedance > 0)) return fail(DGW_EINVAL, "plane waves need |k| > 0 and impedance > 0");
+    hs.waves.insert(hs.waves.end(), v, v + 7);
+  }
   if (desc.face_orient) {
     hs.fo.assign(desc.face_orient, desc.face_orient + nc * nface);
     const int norient = d == 3 ? 8 : 2;
@@ -410,6 +428,7 @@ dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs) {
   }
   hs.cell.assign((size_t)nc * ncomp_geo * np, 0.0);
   hs.face.assign((size_t)nc * nface * (d + 2) * nf, 0.0);
+  if (hs.prescribed) hs.face_x.assign((size_t)nc * nface * d * nf, 0.0);
   hs.level.assign(nlev, {});
   for (int l = 1; l < nlev; ++l) hs.level[l].assign((size_t)nc * ncomp_geo * ipw(n - 2 * l, d), 0.0);
   hs.hK.assign(nc, 0.0);
@@ -509,6 +528,10 @@ dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs) {
             for (int a = 0; a < d; ++a) F[a * nf + p] = wd * Ji[dir * d + a];
             F[d * nf + p] = r * c;
             Zown[((size_t)cell * nface + f) * nf + p] = r * c;
+            if (hs.prescribed) {
+              const double* xp = X.data() + pp * d;
+              for (int a = 0; a < d; ++a) hs.face_x[(((size_t)cell * nface + f) * d + a) * nf + p] = xp[a];
+            }
           } else {
             const int l = s - nface;
             const int m = set_pts[s];

@@ -180,6 +180,27 @@ def test_footprint_and_validation(B):
     assert e.value.status == B.EINVAL
 
 
+def test_prescribed_faces_setup_and_validation(B):
+    """Prescribed boundary faces: face data as the oracle's (exterior
+    impedance = own), plane waves required and checked."""
+    dim, nc, k = 3, 2, 3
+    mat = W.FourierMaterial(8, dim=dim)
+    nodes, nb = W.box_nodes(dim, nc, k, 0.05), W.box_neighbors(dim, nc, ("prescribed", "periodic", "wall"))
+    pw = W.c3_literal_plane_wave().w
+    gm = B.Mesh(dim, k, nodes, nb, mat, device=B.DEVICE_NONE, plane_waves=pw)
+    om = OMesh(dim, k, nodes, nb, mat)
+    F = gm.get(B.GET_FACE)
+    for f in range(2 * dim):
+        fd = om.face_data(np.arange(om.nc), f)
+        assert np.abs(F[:, f, dim + 1] - fd["Zp"]).max() < 1e-14
+        assert np.abs(F[:, f, :dim] - np.moveaxis(fd["a"], 2, 1)).max() < 1e-14
+    for waves in (None, np.zeros((0, 7)), [[1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 1.0]], [[1.0, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0]],
+                  [[np.nan, 1.0, 0.0, 0.0, 1.0, 0.0, 1.0]], np.tile(pw, (9, 1))):
+        with pytest.raises(B.DgwError) as e:
+            B.Mesh(dim, k, nodes, nb, mat, device=B.DEVICE_NONE, plane_waves=waves)
+        assert e.value.status == B.EINVAL, waves
+
+
 def test_storage_basis_validation(B):
     mat = W.ConstantMaterial()
     args = (2, 2, W.box_nodes(2, 3, 2, 0.0), W.box_neighbors(2, 3), mat)

@@ -247,6 +247,91 @@ def test_gauss_basis_rejects_gl_only_calls(gpu_lib):
     assert prof is not None
 
 
+def _pw(dim):
+    k = 2 * np.pi * np.array([1.0, 0.6, 0.3])[:dim]
+    return W.PlaneWaves([[1.0, *np.pad(k, (0, 3 - dim)), 1.1 * np.linalg.norm(k), 0.4, 1.1],
+                         [0.3, *np.pad(-0.5 * k[::-1], (0, 3 - dim)), 0.5 * np.linalg.norm(k), -1.0, 0.9]])
+
+
+def build_prescribed(B, dim, nc, k, bc, flux=0, storage_basis=0):
+    mat = W.FourierMaterial(23, dim=dim)
+    nodes, nb = W.box_nodes(dim, nc, k, 0.05), W.box_neighbors(dim, nc, bc)
+    pw = _pw(dim)
+    gm = B.Mesh(dim, k, nodes, nb, mat, flux=flux, plane_waves=pw.w, storage_basis=storage_basis)
+    return gm, OMesh(dim, k, nodes, nb, mat), pw
+
+
+PRESCRIBED_CASES = [(2, 3, 3, ("prescribed", "prescribed"), 0), (2, 4, 5, ("prescribed", "wall"), 1),
+                    (3, 2, 3, ("prescribed", "periodic", "absorbing"), 0), (3, 3, 2, ("prescribed",) * 3, 1),
+                    (3, 2, 5, ("prescribed",) * 3, 0)]
+
+
+@pytest.mark.parametrize("dim,nc,k,bc,flux", PRESCRIBED_CASES)
+def test_operator_prescribed_faces_fp64(gpu_lib, dim, nc, k, bc, flux):
+    """Prescribed exterior state (plane waves, evaluated at t = 0 by the operator)."""
+    say("operator prescribed", dim, nc, k, bc, flux)
+    gm, om, pw = build_prescribed(gpu_lib, dim, nc, k, bc, flux)
+    U = W.random_state(dim * 17 + k, (om.nc, dim + 1, om.np_))
+    got = gm.apply(to_dev(U)).cpu().numpy()
+    want = apply_operator(om, U, flux="central" if flux else "upwind", exterior=lambda x: pw(x, 0.0))
+    assert rel(got, want) < op_tol(k, dim)
+    if dim == 3 and k == 3:  # and in the Gauss storage basis
+        gg, _, _ = build_prescribed(gpu_lib, dim, nc, k, bc, flux, storage_basis=gpu_lib.BASIS_GAUSS)
+        got = gg.apply(to_dev(U)).cpu().numpy()
+        want = apply_operator(om, U, flux="central" if flux else "upwind", exterior=lambda x: pw(x, 0.0),
+                              storage="gauss")
+        assert rel(got, want) < op_tol(k, dim)
+
+
+@pytest.mark.parametrize("scheme", ["lsrk", "lsrk_standard_vu", "ader"])
+def test_steps_with_prescribed_faces(gpu_lib, scheme):
+    """Exterior data at the LSRK stage times, integrated over the step for
+    ADER; steps start at t0 != 0."""
+    say("steps prescribed", scheme)
+    B = gpu_lib
+    dim, nc, k = 3, 3, 3
+    gm, om, pw = build_prescribed(B, dim, nc, k, ("prescribed", "periodic", "prescribed"))
+    U = om.interpolate(lambda x: pw(x, 0.0)) + 0.01 * W.random_state(29, (om.nc, dim + 1, om.np_))
+    dt, t0 = 0.3 * gm.info.dt_unit, 0.37
+    u = to_dev(U)[None]
+    want = U
+    if scheme == "ader":
+        gm.step_ader(u, t0, dt, 3)
+        for s in range(3):
+            want = ader.ader_step(om, want, dt, exterior_integral=lambda x: pw.integral(x, t0 + s * dt, dt))
+    else:
+        gm.step_lsrk(u, t0, dt, 3, scheme=B.LSRK54 if scheme == "lsrk" else B.LSRK54_STANDARD_VU)
+        for s in range(3):
+            want = ts.lsrk_step(lambda x, t: apply_operator(om, x, exterior=lambda y: pw(y, t)), want,
+                                t0 + s * dt, dt)
+    assert rel(u[0].cpu().numpy(), want) < TOL
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_prescribed_graph_replay_equals_eager(gpu_lib, scheme):
+    """Captured steps take the step time from the device counter: the same
+    bits as eager steps."""
+    say("prescribed graph", scheme)
+    B = gpu_lib
+    gm, om, pw = build_prescribed(B, 3, 2, 4, ("prescribed", "prescribed", "periodic"))
+    U = om.interpolate(lambda x: pw(x, 0.0))
+    dt, t0, n = 0.25 * gm.info.dt_unit, 0.11, 6
+    a = to_dev(U)[None]
+    b = to_dev(U)[None]
+    t_end = t0 + n * dt
+    gm.solve(a, B.ADER if scheme else B.LSRK54, t_end=t_end, dt=dt, t0=t0, use_graph=True)
+    dts = (t_end - t0) / n  # the step the solver takes
+    if scheme:
+        gm.step_ader(b, t0, dts, n)
+    else:
+        gm.step_lsrk(b, t0, dts, n)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    with pytest.raises(B.DgwError) as e:
+        gm.step_ader(b, 0.0, dt, 1, flags=B.ADER_HDG)
+    assert e.value.status == B.EUNSUPPORTED
+
+
 @pytest.mark.parametrize("dim,nc,k,reduce", [(2, 4, 3, True), (2, 3, 4, True), (3, 3, 3, True), (3, 2, 5, True),
                                              (3, 2, 4, False), (3, 2, 8, True), (2, 3, 1, True)])
 def test_ader_step_fp64(gpu_lib, dim, nc, k, reduce):

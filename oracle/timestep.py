@@ -8,6 +8,16 @@ scheme of Carpenter and Kennedy (NASA TM-109112, 1994) in Williamson form
 
     du <- A_i du + dt F(u, t + c_i dt);   u <- u + B_i du,   i = 1..5.
 
+LSRK5(9) (the paper's second scheme: nine stages, order five, two
+registers; its coefficients are not reproduced either).  Reading: the
+two-register (2R) form, whose Butcher tableau has a_ij = b_j for j < i-1 and
+a free subdiagonal a_{i,i-1} = alpha_i, so nine stages leave 8 + 9 = 17 free
+coefficients for the 17 conditions of order five.  These have a finite set
+of real solutions; the one taken is named by the 10-digit key
+LSRK59_KEY_ALPHA / LSRK59_KEY_B and refined to full precision by Newton's
+method on the conditions (it has all c_i in [0, 1] and |coefficients| <=
+0.62).  The step is the plain explicit Runge-Kutta step of that tableau.
+
 Sec. 2.3 gives the Courant number Cr = c dt k^1.5 / h; "a characteristic
 element size h" is read as the smallest singular value of the Jacobian over
 the cell's Gauss points (1/n on the uniform n^d box), c as its largest value
@@ -64,6 +74,86 @@ def lsrk_step(rhs, U, t, dt, A=LSRK54_A, B=LSRK54_B, C=LSRK54_C):
         du = float(Ai) * du + dt * rhs(u, t + float(Ci) * dt)
         u = u + float(Bi) * du
     return u
+
+
+LSRK59_KEY_ALPHA = [0.1702644982, -0.09676474868, 0.0244514839, 0.1382907685, 0.2294641842, 0.5748250612,
+                    -0.1211285367, 0.09183392377]
+LSRK59_KEY_B = [0.1804864076, 0.622352667, -0.4110536782, -0.01125784998, 0.009612188747, 0.1576014651,
+                0.1129031225, 0.08522852155, 0.2541271558]
+
+
+def tableau_2r(alpha, b):
+    """Butcher (a, b, c) of a two-register scheme: a_ij = b_j (j < i-1), a_{i,i-1} = alpha_i."""
+    s = len(b)
+    a = np.zeros((s, s), dtype=np.result_type(np.asarray(alpha), np.asarray(b)))
+    for i in range(1, s):
+        a[i, :i - 1] = b[:i - 1]
+        a[i, i - 1] = alpha[i - 1]
+    b = np.asarray(b)
+    return a, b, a.sum(axis=1)
+
+
+def order5_conditions(a, b):
+    """The 17 order conditions of order five, sum_j b_j Phi_j(tree) - 1/gamma(tree),
+    for the rooted trees with up to five vertices (order 1: 1, 2: 1, 3: 2, 4: 4, 5: 9)."""
+    c = a.sum(axis=1)
+    ac, ac2, ac3 = a @ c, a @ c ** 2, a @ c ** 3
+    aac = a @ ac
+    return np.array([
+        b.sum() - 1, b @ c - 1 / 2,
+        b @ c ** 2 - 1 / 3, b @ ac - 1 / 6,
+        b @ c ** 3 - 1 / 4, b @ (c * ac) - 1 / 8, b @ ac2 - 1 / 12, b @ aac - 1 / 24,
+        b @ c ** 4 - 1 / 5, b @ (c ** 2 * ac) - 1 / 10, b @ (c * ac2) - 1 / 15, b @ (c * aac) - 1 / 30,
+        b @ (ac * ac) - 1 / 20, b @ ac3 - 1 / 20, b @ (a @ (c * ac)) - 1 / 40, b @ (a @ ac2) - 1 / 60,
+        b @ (a @ aac) - 1 / 120])
+
+
+_LSRK59 = []
+
+
+def lsrk59_tableau(iters=20):
+    """(a, b, c) of LSRK5(9): Newton on the 17 conditions from the key
+    (derivatives by complex steps, exact for these polynomials)."""
+    if _LSRK59:
+        return _LSRK59[0]
+    x = np.array(LSRK59_KEY_ALPHA + LSRK59_KEY_B, dtype=np.float64)
+
+    def res(v):
+        return order5_conditions(*tableau_2r(v[:8], v[8:])[:2])
+    for _ in range(iters):
+        r = res(x)
+        if np.max(np.abs(r)) < 1e-16:
+            break
+        J = np.empty((17, 17))
+        for j in range(17):
+            e = x.astype(np.complex128)
+            e[j] += 1e-30j
+            J[:, j] = res(e).imag / 1e-30
+        x = x - np.linalg.solve(J, r)
+    _LSRK59.append(tableau_2r(x[:8], x[8:]))
+    return _LSRK59[0]
+
+
+def rk_step(rhs, U, t, dt, a, b, c):
+    """One explicit Runge-Kutta step of Butcher tableau (a, b, c) (Sec. 2.2):
+    k_i = rhs(U + dt sum_{j<i} a_ij k_j, t + c_i dt), U + dt sum_i b_i k_i."""
+    u = np.asarray(U, dtype=np.float64)
+    k = []
+    for i in range(len(b)):
+        y = u.copy()
+        for j in range(i):
+            if a[i][j] != 0.0:
+                y = y + dt * float(a[i][j]) * k[j]
+        k.append(rhs(y, t + float(c[i]) * dt))
+    out = u.copy()
+    for i in range(len(b)):
+        out = out + dt * float(b[i]) * k[i]
+    return out
+
+
+def lsrk59_step(rhs, U, t, dt):
+    """One LSRK5(9) step (see the module docstring)."""
+    return rk_step(rhs, U, t, dt, *lsrk59_tableau())
 
 
 def cell_h_and_c(mesh, cells=None):

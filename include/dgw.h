@@ -63,6 +63,20 @@ enum { DGW_SCHEME_LSRK54 = 0, DGW_SCHEME_ADER = 1 };
  * updater) or as three BLAS-1 passes (its standard one).  dgw_step_lsrk and
  * dgw_step_profile only; no sources. */
 enum { DGW_SCHEME_LSRK54_MERGED_VU = 2, DGW_SCHEME_LSRK54_STANDARD_VU = 3 };
+/* LSRK5(9): nine stages, order five, two registers (Sec. 2.2; the reference's
+ * coefficients are not printed).  Two-register (2R) form: the Butcher tableau
+ * has a_ij = b_j for j < i-1 and a free subdiagonal alpha; with U the
+ * accumulated solution and Y the stage state, stage i computes
+ * k = dt (L Y + s(t + c_i dt) g), U <- U + b_i k, Y <- U + (alpha_{i+1} - b_i) k.
+ * The 17 coefficients are the real root of the 17 order-5 conditions named
+ * by the 10-digit key alpha = (0.1702644982, -0.09676474868, 0.0244514839,
+ * 0.1382907685, 0.2294641842, 0.5748250612, -0.1211285367, 0.09183392377),
+ * b = (0.1804864076, 0.622352667, -0.4110536782, -0.01125784998,
+ * 0.009612188747, 0.1576014651, 0.1129031225, 0.08522852155, 0.2541271558),
+ * refined by Newton's method when the library loads.  Fused into the
+ * operator sweep like DGW_SCHEME_LSRK54 (dgw_step_lsrk, dgw_step_profile,
+ * dgw_solve_batch; sources allowed). */
+enum { DGW_SCHEME_LSRK59 = 4 };
 /* ADER flags: DGW_ADER_NOREDUCE evaluates every time derivative at k+1
  * points per direction (Alg. 2 without the degree reduction of Sec. 3.3).
  * DGW_ADER_HDG selects the HDG-ADER variant (Sec. 2.4, eq. hdg-ader): the
@@ -314,7 +328,7 @@ dgw_status dgw_autotune(dgw_mesh* mesh, int B, void* stream);
 
 /* ---------------------------------------------------------------- b6 ---- */
 typedef struct dgw_solve_desc {
-  int scheme;                /* DGW_SCHEME_LSRK54 or DGW_SCHEME_ADER              */
+  int scheme;                /* DGW_SCHEME_LSRK54, DGW_SCHEME_LSRK59 or ADER      */
   int ader_flags;
   double courant;            /* used when dt <= 0: dt = courant * dt_unit         */
   double dt;                 /* rounded down so that dt = (t_end-t0)/nsteps       */
@@ -380,6 +394,11 @@ const char* dgw_version(void);
  * n x n, S[q][j] = l^GL_j(xi^G_q)), 5 S^-1, 6 D (collocation derivative on
  * the Gauss points, D[q][j] = l^G_j'(xi^G_q)). */
 dgw_status dgw_basis_1d(int n, int what, double* host_out);
+
+/* Runge-Kutta coefficients in use, for inspection.  DGW_SCHEME_LSRK54: 15
+ * values A (5), B (5), c (5) of the 2N form; DGW_SCHEME_LSRK59: 26 values
+ * alpha (8), b (9), c (9) of the 2R form.  Other schemes: DGW_EINVAL. */
+dgw_status dgw_lsrk_coefficients(int scheme, double* host_out);
 
 #ifdef __cplusplus
 }

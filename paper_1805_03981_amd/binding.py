@@ -25,6 +25,7 @@ FP64, FP32_SPLIT = 0, 1
 BASIS_GL, BASIS_GAUSS = 0, 1
 LSRK54, ADER = 0, 1
 LSRK54_MERGED_VU, LSRK54_STANDARD_VU = 2, 3   # unfused LSRK variants (ablation)
+LSRK59 = 4                                     # nine-stage fifth-order two-register scheme
 ADER_REDUCE, ADER_NOREDUCE, ADER_HDG = 0, 1, 2
 ADER_REDUCE_EVERY_STEP, ADER_REDUCE_EVERY_THIRD = 4, 8
 DEVICE_NONE = -1
@@ -132,6 +133,7 @@ _SIGS = {
     "dgw_last_error": ([], C.c_char_p),
     "dgw_version": ([], C.c_char_p),
     "dgw_basis_1d": ([_i, _i, _dp], _i),
+    "dgw_lsrk_coefficients": ([_i, _dp], _i),
     "dgw_material_fourier": ([_dp, _i64, _i, _dp, _dp, _vp], None),
 }
 for _name, (_args, _res) in _SIGS.items():

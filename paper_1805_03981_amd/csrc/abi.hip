@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -69,6 +70,123 @@ struct Lsrk54 {
   }
 };
 static const Lsrk54 kLsrk;
+
+// LSRK5(9) in two-register form: subdiagonal alpha (8) and weights b (9) of
+// the Butcher tableau (a_ij = b_j for j < i-1), the root of the 17 order-5
+// conditions named by a 10-digit key, refined by Newton's method in long
+// double with derivatives by complex steps (exact for polynomials).
+struct Lsrk59 {
+  double alpha[8], b[9], c[9];
+  bool ok = false;
+  template <typename X>
+  static void conditions(const X* x, X* r) {
+    X a[9][9] = {}, c[9], ac[9], ac2[9], ac3[9], aac[9], acac[9], aac2[9], aaac[9], bb[9];
+    for (int j = 0; j < 9; ++j) bb[j] = x[8 + j];
+    for (int i = 1; i < 9; ++i) {
+      for (int j = 0; j + 1 < i; ++j) a[i][j] = bb[j];
+      a[i][i - 1] = x[i - 1];
+    }
+    for (int i = 0; i < 9; ++i) {
+      c[i] = X(0);
+      for (int j = 0; j < 9; ++j) c[i] += a[i][j];
+    }
+    auto mv = [&](const X* v, X* out) {
+      for (int i = 0; i < 9; ++i) {
+        out[i] = X(0);
+        for (int j = 0; j < 9; ++j) out[i] += a[i][j] * v[j];
+      }
+    };
+    X c2[9], c3[9], cac[9];
+    for (int i = 0; i < 9; ++i) {
+      c2[i] = c[i] * c[i];
+      c3[i] = c2[i] * c[i];
+    }
+    mv(c, ac);
+    mv(c2, ac2);
+    mv(c3, ac3);
+    mv(ac, aac);
+    for (int i = 0; i < 9; ++i) cac[i] = c[i] * ac[i];
+    mv(cac, acac);
+    mv(ac2, aac2);
+    mv(aac, aaac);
+    auto dot = [&](auto f) {
+      X acc(0);
+      for (int j = 0; j < 9; ++j) acc += bb[j] * f(j);
+      return acc;
+    };
+    r[0] = dot([&](int) { return X(1); }) - X(1.0L);
+    r[1] = dot([&](int j) { return c[j]; }) - X(1.0L / 2);
+    r[2] = dot([&](int j) { return c2[j]; }) - X(1.0L / 3);
+    r[3] = dot([&](int j) { return ac[j]; }) - X(1.0L / 6);
+    r[4] = dot([&](int j) { return c3[j]; }) - X(1.0L / 4);
+    r[5] = dot([&](int j) { return cac[j]; }) - X(1.0L / 8);
+    r[6] = dot([&](int j) { return ac2[j]; }) - X(1.0L / 12);
+    r[7] = dot([&](int j) { return aac[j]; }) - X(1.0L / 24);
+    r[8] = dot([&](int j) { return c2[j] * c2[j]; }) - X(1.0L / 5);
+    r[9] = dot([&](int j) { return c2[j] * ac[j]; }) - X(1.0L / 10);
+    r[10] = dot([&](int j) { return c[j] * ac2[j]; }) - X(1.0L / 15);
+    r[11] = dot([&](int j) { return c[j] * aac[j]; }) - X(1.0L / 30);
+    r[12] = dot([&](int j) { return ac[j] * ac[j]; }) - X(1.0L / 20);
+    r[13] = dot([&](int j) { return ac3[j]; }) - X(1.0L / 20);
+    r[14] = dot([&](int j) { return acac[j]; }) - X(1.0L / 40);
+    r[15] = dot([&](int j) { return aac2[j]; }) - X(1.0L / 60);
+    r[16] = dot([&](int j) { return aaac[j]; }) - X(1.0L / 120);
+  }
+  Lsrk59() {
+    using L = long double;
+    using Cx = std::complex<long double>;
+    L x[17] = {0.1702644982L, -0.09676474868L, 0.0244514839L, 0.1382907685L, 0.2294641842L, 0.5748250612L,
+               -0.1211285367L, 0.09183392377L, 0.1804864076L, 0.622352667L, -0.4110536782L, -0.01125784998L,
+               0.009612188747L, 0.1576014651L, 0.1129031225L, 0.08522852155L, 0.2541271558L};
+    const L h = 1e-40L;
+    for (int it = 0; it < 30; ++it) {
+      L r[17], J[17][18];
+      conditions<L>(x, r);
+      L rmax = 0;
+      for (L v : r) rmax = std::max(rmax, std::fabs(v));
+      if (rmax < 1e-18L) {
+        ok = true;
+        break;
+      }
+      for (int j = 0; j < 17; ++j) {
+        Cx xc[17], rc[17];
+        for (int i = 0; i < 17; ++i) xc[i] = Cx(x[i], i == j ? h : 0.0L);
+        conditions<Cx>(xc, rc);
+        for (int i = 0; i < 17; ++i) J[i][j] = rc[i].imag() / h;
+      }
+      for (int i = 0; i < 17; ++i) J[i][17] = -r[i];
+      // Gaussian elimination with partial pivoting
+      for (int col = 0; col < 17; ++col) {
+        int piv = col;
+        for (int i = col + 1; i < 17; ++i)
+          if (std::fabs(J[i][col]) > std::fabs(J[piv][col])) piv = i;
+        for (int k = 0; k < 18; ++k) std::swap(J[col][k], J[piv][k]);
+        for (int i = col + 1; i < 17; ++i) {
+          const L f = J[i][col] / J[col][col];
+          for (int k = col; k < 18; ++k) J[i][k] -= f * J[col][k];
+        }
+      }
+      L dx[17];
+      for (int i = 16; i >= 0; --i) {
+        L acc = J[i][17];
+        for (int k = i + 1; k < 17; ++k) acc -= J[i][k] * dx[k];
+        dx[i] = acc / J[i][i];
+      }
+      for (int i = 0; i < 17; ++i) x[i] += dx[i];
+    }
+    L cc[9] = {0};
+    for (int i = 1; i < 9; ++i) {
+      for (int j = 0; j + 1 < i; ++j) cc[i] += x[8 + j];
+      cc[i] += x[i - 1];
+    }
+    for (int i = 0; i < 8; ++i) alpha[i] = (double)x[i];
+    for (int i = 0; i < 9; ++i) {
+      b[i] = (double)x[8 + i];
+      c[i] = (double)cc[i];
+    }
+  }
+};
+static const Lsrk59 kLsrk59;
 
 static int ipw(int b, int e) {
   int r = 1;
@@ -223,20 +341,42 @@ static dgw_status check_batch(const dgw_mesh* m, int B, const dgw_sources* src) 
   return DGW_OK;
 }
 
-// One LSRK step (5 fused stages).  cur/oth: ping-pong state buffers; returns
-// with the new state in *cur.
+// One LSRK step (fused stages: 5 of the 2N LSRK4(5), or 9 of the 2R
+// LSRK5(9)).  cur/oth: ping-pong state buffers; returns with the new state
+// in *cur.
+static int lsrk_stages(int scheme) { return scheme == DGW_SCHEME_LSRK59 ? 9 : 5; }
+
+// Coefficients of fused stage i.  2N LSRK4(5): du <- A_i du + k,
+// u <- u + B_i du.  2R LSRK5(9): du holds the accumulated solution U,
+// U <- U + b_i k, and u_next the next stage state Y = U + (alpha_{i+1} - b_i) k
+// (= U after the last stage).
+static void set_lsrk_stage(OpParams& p, int scheme, int i, double dt) {
+  if (scheme == DGW_SCHEME_LSRK59) {
+    p.two_r = 1;
+    p.first = i == 0;
+    p.bcoef = kLsrk59.b[i];
+    p.acoef = i < 8 ? kLsrk59.alpha[i] - kLsrk59.b[i] : 0.0;
+    p.time.t_off = kLsrk59.c[i] * dt;
+  } else {
+    p.two_r = 0;
+    p.first = 0;
+    p.acoef = kLsrk.A[i];
+    p.bcoef = kLsrk.B[i];
+    p.time.t_off = kLsrk.C[i] * dt;
+  }
+}
+
 static dgw_status lsrk_step(dgw_mesh* m, int B, const dgw_sources* src, double t0, double dt, int step_add,
-                            const long long* ctr, double*& cur, double*& oth, double* du, hipStream_t s) {
+                            const long long* ctr, double*& cur, double*& oth, double* du, hipStream_t s,
+                            int scheme = DGW_SCHEME_LSRK54) {
   OpParams p = op_params(m, B, src);
   p.dt = dt;
   p.du = du;
   p.time = StepTime{ctr, t0, dt, step_add, 0.0};
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < lsrk_stages(scheme); ++i) {
     p.u = cur;
     p.u_next = oth;
-    p.acoef = kLsrk.A[i];
-    p.bcoef = kLsrk.B[i];
-    p.time.t_off = kLsrk.C[i] * dt;
+    set_lsrk_stage(p, scheme, i, dt);
     DGW_HIP(run_op(m, EPI_LSRK, m->op_shape.sel, p, s));
     std::swap(cur, oth);
   }
@@ -580,6 +720,28 @@ dgw_status dgw_basis_1d(int n, int what, double* out) {
   return fail(DGW_EINVAL, "unknown table");
 }
 
+dgw_status dgw_lsrk_coefficients(int scheme, double* out) {
+  if (!out) return fail(DGW_EINVAL, "out is NULL");
+  if (scheme == DGW_SCHEME_LSRK54) {
+    for (int i = 0; i < 5; ++i) {
+      out[i] = kLsrk.A[i];
+      out[5 + i] = kLsrk.B[i];
+      out[10 + i] = kLsrk.C[i];
+    }
+    return DGW_OK;
+  }
+  if (scheme == DGW_SCHEME_LSRK59) {
+    if (!kLsrk59.ok) return fail(DGW_EDEVICE, "LSRK5(9) coefficients did not converge");
+    for (int i = 0; i < 8; ++i) out[i] = kLsrk59.alpha[i];
+    for (int i = 0; i < 9; ++i) {
+      out[8 + i] = kLsrk59.b[i];
+      out[17 + i] = kLsrk59.c[i];
+    }
+    return DGW_OK;
+  }
+  return fail(DGW_EINVAL, "scheme has no Runge-Kutta coefficients");
+}
+
 dgw_status dgw_mesh_create(const dgw_mesh_desc* desc, dgw_mesh** out) {
   if (!out) return fail(DGW_EINVAL, "out is NULL");
   *out = nullptr;
@@ -732,15 +894,17 @@ static dgw_status check_step(dgw_mesh* m, double dt, int nsteps, double* u, doub
 dgw_status dgw_step_lsrk(dgw_mesh* m, int scheme, double t0, double dt, int nsteps, double* u, double* work,
                          int B, const dgw_sources* src, void* stream) {
   if (scheme != DGW_SCHEME_LSRK54 && scheme != DGW_SCHEME_LSRK54_MERGED_VU &&
-      scheme != DGW_SCHEME_LSRK54_STANDARD_VU)
-    return fail(DGW_EUNSUPPORTED, "scheme must be one of the DGW_SCHEME_LSRK54 variants");
-  if (scheme != DGW_SCHEME_LSRK54 && src) return fail(DGW_EUNSUPPORTED, "the unfused LSRK variants take no sources");
+      scheme != DGW_SCHEME_LSRK54_STANDARD_VU && scheme != DGW_SCHEME_LSRK59)
+    return fail(DGW_EUNSUPPORTED, "scheme must be one of the DGW_SCHEME_LSRK54 variants or DGW_SCHEME_LSRK59");
+  if (scheme == DGW_SCHEME_LSRK59 && !kLsrk59.ok) return fail(DGW_EDEVICE, "LSRK5(9) coefficients did not converge");
+  const bool fused = scheme == DGW_SCHEME_LSRK54 || scheme == DGW_SCHEME_LSRK59;
+  if (!fused && src) return fail(DGW_EUNSUPPORTED, "the unfused LSRK variants take no sources");
   dgw_status st = check_step(m, dt, nsteps, u, work, B, src);
   if (st) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (scheme != DGW_SCHEME_LSRK54) {
+  if (!fused) {
     // operator sweep stores r = L u into the second work register; the
     // vector update then advances u in place
     double* du = work;
@@ -760,7 +924,7 @@ dgw_status dgw_step_lsrk(dgw_mesh* m, int scheme, double t0, double dt, int nste
   double* cur = u;
   double* oth = work + state_elems(m) * B;
   for (int k = 0; k < nsteps; ++k)
-    if ((st = lsrk_step(m, B, src, t0, dt, k, nullptr, cur, oth, du, s))) return st;
+    if ((st = lsrk_step(m, B, src, t0, dt, k, nullptr, cur, oth, du, s, scheme))) return st;
   if (cur != u) DGW_HIP(hipMemcpyAsync(u, cur, state_elems(m) * 8 * B, hipMemcpyDeviceToDevice, s));
   return DGW_OK;
 }
@@ -789,7 +953,8 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
                             double* work, int B, const dgw_sources* src, void* stream, dgw_profile* out) {
   if (!out) return fail(DGW_EINVAL, "out is NULL");
   const bool unfused = scheme == DGW_SCHEME_LSRK54_MERGED_VU || scheme == DGW_SCHEME_LSRK54_STANDARD_VU;
-  if (scheme != DGW_SCHEME_LSRK54 && scheme != DGW_SCHEME_ADER && !unfused) return fail(DGW_EINVAL, "bad scheme");
+  if (scheme != DGW_SCHEME_LSRK54 && scheme != DGW_SCHEME_LSRK59 && scheme != DGW_SCHEME_ADER && !unfused)
+    return fail(DGW_EINVAL, "bad scheme");
   if (unfused && src) return fail(DGW_EUNSUPPORTED, "the unfused LSRK variants take no sources");
   const bool hdg = scheme == DGW_SCHEME_ADER && (flags & DGW_ADER_HDG);
   if (scheme == DGW_SCHEME_ADER) {
@@ -840,17 +1005,15 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
         });
         if (!st) st = timed(1, [&] { return lsrk_vector_update(scheme, i, dt, u, aux, oth, state_elems(m) * B, s); });
       }
-    } else if (scheme == DGW_SCHEME_LSRK54) {
+    } else if (scheme == DGW_SCHEME_LSRK54 || scheme == DGW_SCHEME_LSRK59) {
       OpParams p = op_params(m, B, src);
       p.dt = dt;
       p.du = aux;
       p.time = StepTime{nullptr, t0, dt, k, 0.0};
-      for (int i = 0; i < 5 && !st; ++i) {
+      for (int i = 0; i < lsrk_stages(scheme) && !st; ++i) {
         p.u = cur;
         p.u_next = oth;
-        p.acoef = kLsrk.A[i];
-        p.bcoef = kLsrk.B[i];
-        p.time.t_off = kLsrk.C[i] * dt;
+        set_lsrk_stage(p, scheme, i, dt);
         st = timed(0, [&]() -> dgw_status {
           DGW_HIP(run_op(m, EPI_LSRK, m->op_shape.sel, p, s));
           return DGW_OK;
@@ -1135,7 +1298,8 @@ dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, d
   dgw_status st = check_mesh(m);
   if (st) return st;
   if ((st = check_gl_basis(m, "dgw_solve_batch (energy watchdog)"))) return st;
-  if (desc->scheme != DGW_SCHEME_LSRK54 && desc->scheme != DGW_SCHEME_ADER) return fail(DGW_EINVAL, "bad scheme");
+  if (desc->scheme != DGW_SCHEME_LSRK54 && desc->scheme != DGW_SCHEME_LSRK59 && desc->scheme != DGW_SCHEME_ADER)
+    return fail(DGW_EINVAL, "bad scheme");
   if (desc->scheme == DGW_SCHEME_ADER && (st = check_ader_flags(desc->ader_flags, desc->sources))) return st;
   if (desc->scheme == DGW_SCHEME_ADER && (st = check_hdg_faces(m, desc->ader_flags))) return st;
   const double span = desc->t_end - desc->t0;
@@ -1164,8 +1328,8 @@ dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, d
   }
   const double growth = desc->watchdog_growth > 0 ? desc->watchdog_growth : 10.0;
   auto one = [&](int64_t k, const long long* ctr, int add) -> dgw_status {
-    return desc->scheme == DGW_SCHEME_LSRK54
-               ? lsrk_step(m, B, src, desc->t0, dt, (int)(ctr ? add : k), ctr, cur, oth, aux, s)
+    return desc->scheme != DGW_SCHEME_ADER
+               ? lsrk_step(m, B, src, desc->t0, dt, (int)(ctr ? add : k), ctr, cur, oth, aux, s, desc->scheme)
                : ader_step(m, desc->ader_flags, B, src, desc->t0, dt, (int)(ctr ? add : k), ctr, cur, oth, aux, s);
   };
   DGW_HIP(hipStreamSynchronize(s));

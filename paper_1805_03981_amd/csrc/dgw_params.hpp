@@ -57,6 +57,9 @@ struct OpParams {
   int B;
   int central;            // 1: central flux, 0: upwind
   double acoef, bcoef, dt;  // LSRK: du <- acoef du + dt (L u + s g); u_next <- u + bcoef du
+  int two_r;              // LSRK 2R form: k = dt (L u + s g); du <- du + bcoef k (du := u in the
+                          // first stage); u_next <- du + acoef k
+  int first;              // 2R: first stage of the step
   StepTime time;          // LSRK: source at tn + t_off; ADER update: int_{tn}^{tn+dt} s * g
   SourceParams src;
 };

@@ -435,7 +435,7 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
     if constexpr (EPI == EPI_ADD)
       if (i < nel) eb[s] = p.u_base[gofs + i];
     if constexpr (EPI == EPI_LSRK)
-      if (i < nel && p.acoef != 0.0) eb[s] = p.du[gofs + i];
+      if (i < nel && (p.two_r ? !p.first : p.acoef != 0.0)) eb[s] = p.du[gofs + i];
   }
 #pragma unroll
   for (int s = 0; s < ES; ++s) {
@@ -611,9 +611,16 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
           if (cell0 + c == scell && v == D) add = sval * p.src.gvec[(int64_t)member * NP + (i % NP)];
         }
         if constexpr (EPI == EPI_LSRK) {
-          const double d = p.acoef * eb[s] + p.dt * (val + add);
-          p.du[gi] = d;
-          p.u_next[gi] = ev[s] + p.bcoef * d;
+          if (p.two_r) {  // accumulated solution in du, next stage state in u_next
+            const double k = p.dt * (val + add);
+            const double un = (p.first ? ev[s] : eb[s]) + p.bcoef * k;
+            p.du[gi] = un;
+            p.u_next[gi] = un + p.acoef * k;
+          } else {
+            const double d = p.acoef * eb[s] + p.dt * (val + add);
+            p.du[gi] = d;
+            p.u_next[gi] = ev[s] + p.bcoef * d;
+          }
         } else {
           p.u_next[gi] = eb[s] + val + add;
         }

@@ -201,6 +201,23 @@ def test_prescribed_faces_setup_and_validation(B):
         assert e.value.status == B.EINVAL, waves
 
 
+def test_lsrk_coefficients_match_oracle(B):
+    """The library refines the LSRK5(9) key with its own Newton solver; the
+    result equals the oracle's tableau, and the LSRK4(5) table its rationals."""
+    import ctypes as C
+    out = np.empty(26)
+    assert B.lib.dgw_lsrk_coefficients(B.LSRK59, out.ctypes.data_as(C.POINTER(C.c_double))) == 0
+    a, b, c = ts.lsrk59_tableau()
+    # the same root to a few units in the last place (it is conditioned ~1e3)
+    assert np.abs(out[:8] - np.diag(a, -1)).max() < 5e-15
+    assert np.abs(out[8:17] - b).max() < 5e-15
+    assert np.abs(out[17:] - c).max() < 5e-15
+    assert B.lib.dgw_lsrk_coefficients(B.LSRK54, out.ctypes.data_as(C.POINTER(C.c_double))) == 0
+    want = [float(x) for x in ts.LSRK54_A + ts.LSRK54_B + ts.LSRK54_C]
+    assert np.abs(out[:15] - want).max() < 1e-16
+    assert B.lib.dgw_lsrk_coefficients(B.ADER, out.ctypes.data_as(C.POINTER(C.c_double))) == B.EINVAL
+
+
 def test_storage_basis_validation(B):
     mat = W.ConstantMaterial()
     args = (2, 2, W.box_nodes(2, 3, 2, 0.0), W.box_neighbors(2, 3), mat)

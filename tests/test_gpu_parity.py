@@ -332,6 +332,62 @@ def test_prescribed_graph_replay_equals_eager(gpu_lib, scheme):
     assert e.value.status == B.EUNSUPPORTED
 
 
+@pytest.mark.parametrize("dim,nc,k,bc", [(2, 4, 3, None), (3, 3, 3, ("wall", "periodic", "absorbing")),
+                                       (3, 2, 5, None), (2, 3, 8, None), (3, 2, 1, None)])
+def test_lsrk59_step_fp64(gpu_lib, dim, nc, k, bc):
+    """LSRK5(9) in two-register form (nine fused stages) against the oracle's
+    Butcher-form step of the same tableau."""
+    say("lsrk59", dim, nc, k, bc)
+    gm, om = build(gpu_lib, dim, nc, k, 0.05, bc=bc)
+    U = om.interpolate(lambda x: W.gaussian_pulse(x, [0.4] * dim, 0.15)) + 0.01 * W.random_state(27, (om.nc, dim + 1, om.np_))
+    dt = 0.4 * gm.info.dt_unit
+    u = to_dev(U)[None]
+    gm.step_lsrk(u, 0.0, dt, 2, scheme=gpu_lib.LSRK59)
+    want = U
+    for s in range(2):
+        want = ts.lsrk59_step(lambda x, t: apply_operator(om, x), want, s * dt, dt)
+    assert rel(u[0].cpu().numpy(), want) < TOL
+    # and it differs from the LSRK4(5) step
+    v = to_dev(U)[None]
+    gm.step_lsrk(v, 0.0, dt, 2)
+    assert rel(v[0].cpu().numpy(), want) > 1e-12
+
+
+def test_lsrk59_sources_prescribed_and_graph(gpu_lib):
+    """LSRK5(9) with point sources (stage times c_i) and prescribed faces, and
+    the solver's captured steps equal to eager steps."""
+    say("lsrk59 sources")
+    B = gpu_lib
+    dim, nc, k, Bn = 3, 3, 3, 2
+    mat = W.FourierMaterial(23, dim=dim)
+    nodes, nb = W.box_nodes(dim, nc, k, 0.05), W.box_neighbors(dim, nc, ("prescribed", "periodic", "periodic"))
+    pw = _pw(dim)
+    gm = B.Mesh(dim, k, nodes, nb, mat, plane_waves=pw.w, max_batch=Bn)
+    om = OMesh(dim, k, nodes, nb, mat)
+    pos = W.random_points(33, Bn, dim)
+    src = B.Sources(gm, pos, frequency=4.0, amplitude=[1.0, 2.5])
+    dt, t0 = 0.3 * gm.info.dt_unit, 0.2
+    U = np.zeros((Bn, om.nc, dim + 1, om.np_))
+    u = to_dev(U)
+    gm.step_lsrk(u, t0, dt, 2, sources=src, B=Bn, scheme=B.LSRK59)
+    for b in range(Bn):
+        ps = osrc.PointSource(om, pos[b], osrc.Ricker(f=4.0, amp=[1.0, 2.5][b]))
+        want = U[b]
+        for s in range(2):
+            want = ts.lsrk59_step(lambda x, tt: apply_operator(om, x, exterior=lambda y: pw(y, tt)) + ps.rhs(om, tt),
+                                  want, t0 + s * dt, dt)
+        assert rel(u[b].cpu().numpy(), want) < 1e-11
+    a = to_dev(U)
+    c = to_dev(U)
+    t_end = t0 + 4 * dt
+    rep = gm.solve(a, B.LSRK59, t_end=t_end, dt=dt, t0=t0, sources=src, use_graph=True, B=Bn)
+    gm.step_lsrk(c, t0, rep.dt, rep.steps, sources=src, B=Bn, scheme=B.LSRK59)
+    torch.cuda.synchronize()
+    assert torch.equal(a, c)
+    prof = gm.profile(to_dev(U), B.LSRK59, t0, dt, 1, sources=src, B=Bn)
+    assert prof["operator_lsrk"][1] == 9
+
+
 @pytest.mark.parametrize("dim,nc,k,reduce", [(2, 4, 3, True), (2, 3, 4, True), (3, 3, 3, True), (3, 2, 5, True),
                                              (3, 2, 4, False), (3, 2, 8, True), (2, 3, 1, True)])
 def test_ader_step_fp64(gpu_lib, dim, nc, k, reduce):

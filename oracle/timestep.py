@@ -116,21 +116,25 @@ def lsrk59_tableau(iters=20):
     (derivatives by complex steps, exact for these polynomials)."""
     if _LSRK59:
         return _LSRK59[0]
-    x = np.array(LSRK59_KEY_ALPHA + LSRK59_KEY_B, dtype=np.float64)
+    # residuals in extended precision (the root is conditioned ~1e3, so a
+    # double residual would leave ~1e-13 in the coefficients), Jacobian in
+    # double: the iteration converges to the root to double precision
+    x = np.array(LSRK59_KEY_ALPHA + LSRK59_KEY_B, dtype=np.longdouble)
 
     def res(v):
         return order5_conditions(*tableau_2r(v[:8], v[8:])[:2])
     for _ in range(iters):
         r = res(x)
-        if np.max(np.abs(r)) < 1e-16:
+        if np.max(np.abs(r)) < 1e-18:
             break
         J = np.empty((17, 17))
         for j in range(17):
-            e = x.astype(np.complex128)
+            e = x.astype(np.float64).astype(np.complex128)
             e[j] += 1e-30j
             J[:, j] = res(e).imag / 1e-30
-        x = x - np.linalg.solve(J, r)
-    _LSRK59.append(tableau_2r(x[:8], x[8:]))
+        x = x - np.linalg.solve(J, r.astype(np.float64)).astype(np.longdouble)
+    a, b, c = tableau_2r(x[:8], x[8:])
+    _LSRK59.append((a.astype(np.float64), b.astype(np.float64), c.astype(np.float64)))
     return _LSRK59[0]
 
 

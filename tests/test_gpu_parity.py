@@ -388,6 +388,38 @@ def test_lsrk59_sources_prescribed_and_graph(gpu_lib):
     assert prof["operator_lsrk"][1] == 9
 
 
+def test_feature_combinations(gpu_lib):
+    """LSRK5(9) on a Gauss-basis mesh with prescribed faces; LSRK5(9) in
+    FP32-split (error stated against FP64); the standard-VU LSRK variant on a
+    Gauss-basis mesh with prescribed faces."""
+    say("combinations")
+    B = gpu_lib
+    dim, nc, k = 3, 3, 3
+    gm, om, pw = build_prescribed(B, dim, nc, k, ("prescribed", "periodic", "wall"),
+                                  storage_basis=B.BASIS_GAUSS)
+    U = gl_to_gauss(om, om.interpolate(lambda x: pw(x, 0.0))) + 0.01 * W.random_state(37, (om.nc, dim + 1, om.np_))
+    dt, t0 = 0.3 * gm.info.dt_unit, 0.05
+    for scheme, step in ((B.LSRK59, ts.lsrk59_step), (B.LSRK54_STANDARD_VU, ts.lsrk_step)):
+        u = to_dev(U)[None]
+        gm.step_lsrk(u, t0, dt, 2, scheme=scheme)
+        want = U
+        for s in range(2):
+            want = step(lambda x, t: apply_operator(om, x, exterior=lambda y: pw(y, t), storage="gauss"), want,
+                        t0 + s * dt, dt)
+        assert rel(u[0].cpu().numpy(), want) < TOL, scheme
+    # FP32-split LSRK5(9): parity unpinned, error at the single-precision level
+    g64, _ = build(B, dim, nc, k, 0.05)
+    g32, _ = build(B, dim, nc, k, 0.05, precision=B.FP32_SPLIT)
+    V = om.interpolate(lambda x: W.gaussian_pulse(x, [0.5] * dim, 0.15))
+    a, b = to_dev(V)[None], to_dev(V)[None]
+    dt = 0.3 * g64.info.dt_unit
+    g64.step_lsrk(a, 0.0, dt, 3, scheme=B.LSRK59)
+    g32.step_lsrk(b, 0.0, dt, 3, scheme=B.LSRK59)
+    err = rel(b[0].cpu().numpy(), a[0].cpu().numpy())
+    say("lsrk59 fp32 vs fp64 after 3 steps", err)
+    assert 0 < err < 1e-5
+
+
 @pytest.mark.parametrize("dim,nc,k,reduce", [(2, 4, 3, True), (2, 3, 4, True), (3, 3, 3, True), (3, 2, 5, True),
                                              (3, 2, 4, False), (3, 2, 8, True), (2, 3, 1, True)])
 def test_ader_step_fp64(gpu_lib, dim, nc, k, reduce):

@@ -418,6 +418,26 @@ def test_feature_combinations(gpu_lib):
     err = rel(b[0].cpu().numpy(), a[0].cpu().numpy())
     say("lsrk59 fp32 vs fp64 after 3 steps", err)
     assert 0 < err < 1e-5
+    # FP32-split operator with prescribed faces: error at the single-precision level
+    mat = W.FourierMaterial(23, dim=dim)
+    nodes, nb = W.box_nodes(dim, nc, k, 0.05), W.box_neighbors(dim, nc, ("prescribed", "wall", "periodic"))
+    gf = B.Mesh(dim, k, nodes, nb, mat, precision=B.FP32_SPLIT, plane_waves=pw.w)
+    of = OMesh(dim, k, nodes, nb, mat)
+    Y = W.random_state(41, (of.nc, dim + 1, of.np_))
+    e32 = rel(gf.apply(to_dev(Y)).cpu().numpy(), apply_operator(of, Y, exterior=lambda y: pw(y, 0.0)))
+    say("prescribed fp32 operator error", e32)
+    assert e32 < 1e-5
+    # batch of two on a Gauss-basis mesh: each member as its own run
+    gb, ob, _ = build_prescribed(B, dim, nc, k, ("periodic", "periodic", "wall"), storage_basis=B.BASIS_GAUSS)
+    gb2 = B.Mesh(dim, k, W.box_nodes(dim, nc, k, 0.05), W.box_neighbors(dim, nc, ("periodic", "periodic", "wall")),
+                 W.FourierMaterial(23, dim=dim), plane_waves=pw.w, storage_basis=B.BASIS_GAUSS, max_batch=2)
+    Z = np.stack([W.random_state(43, (ob.nc, dim + 1, ob.np_)), W.random_state(44, (ob.nc, dim + 1, ob.np_))])
+    zz = to_dev(Z)
+    gb2.step_lsrk(zz, 0.0, 0.2 * gb2.info.dt_unit, 2, B=2)
+    for m in range(2):
+        z1 = to_dev(Z[m])[None]
+        gb.step_lsrk(z1, 0.0, 0.2 * gb.info.dt_unit, 2)
+        assert torch.equal(zz[m], z1[0])
 
 
 @pytest.mark.parametrize("dim,nc,k,reduce", [(2, 4, 3, True), (2, 3, 4, True), (3, 3, 3, True), (3, 2, 5, True),

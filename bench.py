@@ -610,8 +610,8 @@ def main():
                     help="skip the time-to-solution at a fixed error (relative L2(p) 1e-6 at T = 0.5)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design is "
-              "described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the cells would shard "
+              "by slabs with a face-trace exchange per operator sweep); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)

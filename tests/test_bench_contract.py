@@ -1,5 +1,5 @@
 """CPU checks of bench.py's contract: every leg main() can call exists, and
-more than one GPU is refused with a message (this build measures one GPU)."""
+more than one GPU is refused with a message (the benchmark measures one GPU)."""
 import ast
 import builtins
 import os

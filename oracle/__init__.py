@@ -12,9 +12,10 @@ function cites the part of the paper (Schoeder, Kormann, Wall, Kronbichler,
 "Efficient explicit time stepping of high order discontinuous Galerkin schemes
 for waves", arXiv:1805.03981) it follows.
 
-Parity status: every function is pinned by a CPU test except the point-source
-right-hand side (no closed form exists for a point source on a curved mesh
-with variable coefficients) -- "parity unpinned" there, see oracle/sources.py.
+Parity status: every function is pinned by a CPU test (tests/test_oracle_*.py);
+the point-source injection through its convergence to the retarded solution
+in a homogeneous periodic box (no closed form exists on curved meshes with
+variable coefficients, which take the same code path).
 """
 from . import basis, mesh, operator, timestep, ader, norms, sources  # noqa: F401
 from .mesh import Mesh, BC_WALL, BC_ABSORBING, BC_PRESCRIBED  # noqa: F401

@@ -1,4 +1,4 @@
-"""Point sources with a Ricker wavelet (oracle).  Parity unpinned.
+"""Point sources with a Ricker wavelet (oracle).
 
 Not part of the paper (its experiments have no sources); the reading used
 for batched-source workloads:
@@ -16,10 +16,12 @@ for batched-source workloads:
   at the level points) inside the Cauchy-Kowalevski recursion and the exact
   time integral of s times g to the update.
 
-Parity unpinned: no closed form exists for a point source on a curved mesh
-with variable coefficients; the tests check linearity/superposition, the
-Ricker closed forms against finite differences and quadrature, and LSRK
-versus ADER cross-convergence in dt.
+Pins: in a homogeneous periodic box the pressure converges at order k+1 to
+the retarded solution of p_tt - c^2 lap p = s'(t) delta(x - x_s) (2D, with
+the periodic images), for LSRK and ADER; the Ricker closed forms against
+finite differences and quadrature; linearity/superposition.  On curved
+meshes with variable coefficients no closed form exists; the same code
+path serves them.
 """
 from __future__ import annotations
 

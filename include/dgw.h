@@ -395,9 +395,11 @@ const char* dgw_version(void);
  * the Gauss points, D[q][j] = l^G_j'(xi^G_q)). */
 dgw_status dgw_basis_1d(int n, int what, double* host_out);
 
-/* Runge-Kutta coefficients in use, for inspection.  DGW_SCHEME_LSRK54: 15
- * values A (5), B (5), c (5) of the 2N form; DGW_SCHEME_LSRK59: 26 values
- * alpha (8), b (9), c (9) of the 2R form.  Other schemes: DGW_EINVAL. */
+/* Coefficients of the low-storage Runge-Kutta schemes in use (Sec. 2.2),
+ * for inspection; host_out: caller-owned host buffer.  DGW_SCHEME_LSRK54:
+ * 15 values A (5), B (5), c (5) of the 2N form; DGW_SCHEME_LSRK59: 26 values
+ * alpha (8), b (9), c (9) of the 2R form (DGW_EDEVICE if its refinement did
+ * not converge).  Other schemes or host_out NULL: DGW_EINVAL. */
 dgw_status dgw_lsrk_coefficients(int scheme, double* host_out);
 
 #ifdef __cplusplus

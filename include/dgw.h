@@ -352,7 +352,10 @@ dgw_status dgw_solve_batch(dgw_mesh* mesh, const dgw_solve_desc* desc, double* u
 /* ---------------------------------------------------------------- b7 ---- */
 typedef struct dgw_request {
   double arrival_s;          /* seconds after serving starts                       */
-  int dim, ncell, degree, scheme, precision;
+  int dim, ncell, degree;
+  int scheme;                /* DGW_SCHEME_LSRK54, DGW_SCHEME_LSRK59 or ADER; else */
+                             /* the result is DGW_EINVAL                            */
+  int precision;
   double t_end, courant, deform_amp;
   dgw_fourier_material material;
   double ic_center[3], ic_width; /* Gaussian pressure pulse, v = 0                 */

@@ -94,6 +94,7 @@ dgw_status dgw_mesh_create_box(int dim, int ncell, int degree, double amp, dgw_m
 
 int64_t dgw_request_footprint(const dgw_request* r) {
   if (!r || r->dim < 2 || r->dim > 3 || r->degree < 1 || r->degree > 8 || r->ncell < 1) return -1;
+  if (r->scheme != DGW_SCHEME_LSRK54 && r->scheme != DGW_SCHEME_LSRK59 && r->scheme != DGW_SCHEME_ADER) return -1;
   const int d = r->dim, n = r->degree + 1;
   int64_t nc = 1, np = 1, nf = 1;
   for (int a = 0; a < d; ++a) {
@@ -265,8 +266,7 @@ dgw_status dgw_serve(const dgw_server_desc* desc, const dgw_request* reqs, int n
       const double t0 = (double)L.done * L.dt;
       const dgw_status st = r.scheme == DGW_SCHEME_ADER
                                 ? dgw_step_ader(L.mesh, 0, t0, L.dt, 1, L.u, L.work, 1, nullptr, L.stream)
-                                : dgw_step_lsrk(L.mesh, DGW_SCHEME_LSRK54, t0, L.dt, 1, L.u, L.work, 1, nullptr,
-                                                L.stream);
+                                : dgw_step_lsrk(L.mesh, r.scheme, t0, L.dt, 1, L.u, L.work, 1, nullptr, L.stream);
       if (st) {
         L.done = -1 - L.done;  // mark failed
         continue;

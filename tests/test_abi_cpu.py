@@ -151,6 +151,11 @@ def test_footprint_and_validation(B):
     fp = B.lib.dgw_request_footprint(C.byref(r))
     state = 512 * 4 * 64 * 8
     assert fp > 3 * state
+    r.scheme = B.LSRK59
+    assert B.lib.dgw_request_footprint(C.byref(r)) == fp
+    r.scheme = 7  # not a scheme
+    assert B.lib.dgw_request_footprint(C.byref(r)) == -1
+    r.scheme = 0
     r.degree = 9
     assert B.lib.dgw_request_footprint(C.byref(r)) == -1
     mat = W.ConstantMaterial()

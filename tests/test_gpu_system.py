@@ -175,7 +175,7 @@ def test_full_size_c3_sampled(gpu_lib):
 def _request(B, seed, ncell, k, scheme, t_end, arrival):
     mat = W.FourierMaterial(seed, dim=3)
     r = B.Request(arrival_s=arrival, dim=3, ncell=ncell, degree=k, scheme=scheme, precision=1,
-                  t_end=t_end, courant=0.8 * (0.44 if scheme == 0 else 0.18), deform_amp=0.05)
+                  t_end=t_end, courant=0.8 * {0: 0.44, 1: 0.18, 4: 0.57}[scheme], deform_amp=0.05)
     r.material = B.fourier_material_struct(mat)
     c = W.random_points(seed + 1000, 1, 3)[0]
     for a in range(3):
@@ -189,7 +189,7 @@ def test_serving_alone_equals_mix(gpu_lib):
     request larger than the budget fails with DGW_ENOMEM and the rest go on."""
     say("serve")
     B = gpu_lib
-    reqs = [_request(B, 10 + i, n, k, i % 2, t, 0.002 * i)
+    reqs = [_request(B, 10 + i, n, k, (B.LSRK54, B.ADER, B.LSRK59)[i % 3], t, 0.002 * i)
             for i, (n, k, t) in enumerate([(4, 2, 0.05), (6, 3, 0.04), (5, 4, 0.03), (8, 2, 0.05), (4, 5, 0.02)])]
     big = _request(B, 99, 40, 8, 0, 0.1, 0.0)
     budget = 3 * max(B.lib.dgw_request_footprint(C.byref(r)) for r in reqs)

@@ -243,7 +243,7 @@ def batched_sources(B=64, steps=500, precision="fp32", ncell=32, k=5, seed=64, u
     return out
 
 
-def serving(nreq=24, seed=5, load=0.8, nmin=6, nmax=20, tmin=0.05, tmax=0.2):
+def serving(nreq=24, seed=5, load=0.8, nmin=6, nmax=20, tmin=0.05, tmax=0.2, progress=False):
     """A Poisson stream of solve requests: seeded periodic curved boxes with
     n^3 cells (n log-uniform in [nmin, nmax]), k uniform in 2..8, LSRK or
     ADER, FP32-split, final time U[tmin, tmax], Cr = 0.8 Cr_crit; arrival
@@ -269,13 +269,17 @@ def serving(nreq=24, seed=5, load=0.8, nmin=6, nmax=20, tmin=0.05, tmax=0.2):
         r.ic_width = 0.1
         reqs.append(r)
     # capacity: all requests at once, no arrival process
-    cap, _, _ = dg.serve(reqs, realtime=False, max_live=8)
+    if progress:
+        log(f"[bench] serving: capacity pass over {nreq} requests")
+    cap, _, _ = dg.serve(reqs, realtime=False, max_live=8, progress=progress)
     mean_s = cap.wall_s / nreq
     gaps = rng.exponential(mean_s / load, size=nreq)
     t = np.cumsum(gaps) - gaps[0]
     for r, a in zip(reqs, t):
         r.arrival_s = float(a)
-    rep, res, _ = dg.serve(reqs, realtime=True, max_live=8)
+    if progress:
+        log(f"[bench] serving: Poisson arrivals at {load} x capacity")
+    rep, res, _ = dg.serve(reqs, realtime=True, max_live=8, progress=progress)
     return {"workload": f"{nreq} requests, 3D curved periodic boxes n^3, n log-uniform [{nmin},{nmax}], k in 2..8, "
                         f"LSRK/ADER, FP32-split, T in [{tmin},{tmax}], Poisson arrivals at {load} x capacity",
             "p50_s": rep.p50_s, "p99_s": rep.p99_s, "dof_steps_per_s": rep.dof_steps_per_s,
@@ -596,6 +600,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 error measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--no-serving", action="store_true", help="skip the small serving trace")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="also serve 200 requests, n in [8, 48], k in 2..8, T in [0.05, 0.2] "
+                         "(about ten minutes; one line per finished request)")
     ap.add_argument("--batched", action="store_true",
                     help="also run the 32^3 k=5 batch of 64 point sources (500 ADER steps)")
     ap.add_argument("--ceilings", action="store_true",
@@ -656,6 +663,10 @@ def main():
         log("[bench] serving trace")
         extras["serving"] = serving()
         log(f"[bench] serving: {extras['serving']}")
+    if args.serving_full:
+        log("[bench] full serving trace")
+        extras["serving_full"] = serving(nreq=200, seed=7, nmin=8, nmax=48, tmin=0.05, tmax=0.2, progress=True)
+        log(f"[bench] serving full: {extras['serving_full']}")
     if args.batched:
         log("[bench] batched sources")
         extras["batched_sources"] = batched_sources()

@@ -372,6 +372,7 @@ typedef struct dgw_server_desc {
   double hbm_budget_bytes;   /* admission budget for all live requests             */
   int max_live;              /* most requests in flight (streams)                  */
   int realtime;              /* 1: honour arrival_s; 0: all arrive at 0            */
+  int progress;              /* 1: one line on stderr per finished request         */
 } dgw_server_desc;
 typedef struct dgw_serve_report {
   int n_done, n_failed;

@@ -103,7 +103,7 @@ class Result(C.Structure):
 
 class ServerDesc(C.Structure):
     _fields_ = [("device", C.c_int), ("hbm_budget_bytes", C.c_double), ("max_live", C.c_int),
-                ("realtime", C.c_int)]
+                ("realtime", C.c_int), ("progress", C.c_int)]
 
 
 class ServeReport(C.Structure):
@@ -377,7 +377,7 @@ def basis_1d(n, what):
     return out.reshape(n, n) if what >= 4 else out
 
 
-def serve(requests, device=0, budget_bytes=None, max_live=8, realtime=True, keep_states=False):
+def serve(requests, device=0, budget_bytes=None, max_live=8, realtime=True, keep_states=False, progress=False):
     n = len(requests)
     arr = (Request * n)(*requests)
     res = (Result * n)()
@@ -394,7 +394,8 @@ def serve(requests, device=0, budget_bytes=None, max_live=8, realtime=True, keep
     if budget_bytes is None:
         free, _ = torch.cuda.mem_get_info(device)
         budget_bytes = 0.9 * free
-    sd = ServerDesc(device=device, hbm_budget_bytes=float(budget_bytes), max_live=max_live, realtime=int(realtime))
+    sd = ServerDesc(device=device, hbm_budget_bytes=float(budget_bytes), max_live=max_live, realtime=int(realtime),
+                    progress=int(progress))
     rep = ServeReport()
     check(lib.dgw_serve(C.byref(sd), arr, n, res, C.byref(rep)), "dgw_serve")
     return rep, list(res), states

@@ -7,8 +7,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <deque>
+#include <future>
 #include <memory>
 #include <thread>
 #include <vector>
@@ -151,6 +153,32 @@ void initial_state(dgw_mesh* m, const dgw_request& r, std::vector<double>& u) {
     }
 }
 
+// A request whose mesh and initial state are being built on a worker thread
+// (the host setup of a large curved mesh takes seconds; the live requests
+// keep stepping meanwhile).
+struct Prep {
+  int idx = 0;
+  int64_t footprint = 0;
+  dgw_mesh* mesh = nullptr;
+  std::vector<double> u0;
+  std::future<dgw_status> done;
+};
+
+std::shared_ptr<Prep> prepare(const dgw_request& r, int idx, int64_t fp, int device) {
+  auto P = std::make_shared<Prep>();
+  P->idx = idx;
+  P->footprint = fp;
+  P->done = std::async(std::launch::async, [P, r, device]() -> dgw_status {
+    dgw_fourier_material mat = r.material;  // read during the setup only
+    const dgw_status st = dgw_mesh_create_box(r.dim, r.ncell, r.degree, r.deform_amp, dgw_material_fourier, &mat,
+                                              DGW_FLUX_UPWIND, r.precision, device, 1, &P->mesh);
+    if (st) return st;
+    initial_state(P->mesh, r, P->u0);
+    return DGW_OK;
+  });
+  return P;
+}
+
 }  // namespace
 
 dgw_status dgw_serve(const dgw_server_desc* desc, const dgw_request* reqs, int n, dgw_result* out,
@@ -171,6 +199,7 @@ dgw_status dgw_serve(const dgw_server_desc* desc, const dgw_request* reqs, int n
   }
   std::deque<int> pending(order.begin(), order.end());
   std::vector<Live> live;
+  std::vector<std::shared_ptr<Prep>> preparing;
   double used = 0;
   int64_t dof_steps = 0;
   std::vector<double> lat;
@@ -193,15 +222,21 @@ dgw_status dgw_serve(const dgw_server_desc* desc, const dgw_request* reqs, int n
     R.t_done = now();
     R.steps = L.done;
     lat.push_back(R.t_done - R.t_arrive);
+    if (desc->progress) {
+      std::fprintf(stderr, "[serve] request %d: status %d, %lld steps, %lld DoF, latency %.3f s (%zu finished)\n",
+                   L.idx, st, (long long)L.done, (long long)L.dofs, R.t_done - R.t_arrive, lat.size());
+      std::fflush(stderr);
+    }
     (void)hipFree(L.u);
     (void)hipFree(L.work);
     (void)hipStreamDestroy(L.stream);
     dgw_mesh_destroy(L.mesh);
     used -= (double)L.footprint;
   };
-  while (!pending.empty() || !live.empty()) {
-    // admission: arrived requests, in arrival order, while the budget allows
-    while (!pending.empty() && (int)live.size() < max_live) {
+  while (!pending.empty() || !live.empty() || !preparing.empty()) {
+    // admission: arrived requests, in arrival order, while the budget allows;
+    // the budget is reserved now and the mesh is built on a worker thread
+    while (!pending.empty() && (int)(live.size() + preparing.size()) < max_live) {
       const int i = pending.front();
       const dgw_request& r = reqs[i];
       if (desc->realtime && r.arrival_s > now()) break;
@@ -215,20 +250,34 @@ dgw_status dgw_serve(const dgw_server_desc* desc, const dgw_request* reqs, int n
       }
       if (used + (double)fp > desc->hbm_budget_bytes) break;  // wait for memory
       pending.pop_front();
-      Live L;
-      L.idx = i;
-      L.footprint = fp;
       out[i].t_admit = now();
       max_wait = std::max(max_wait, out[i].t_admit - out[i].t_arrive);
-      dgw_fourier_material mat = r.material;
-      dgw_status st = dgw_mesh_create_box(r.dim, r.ncell, r.degree, r.deform_amp, dgw_material_fourier, &mat,
-                                          DGW_FLUX_UPWIND, r.precision, desc->device, 1, &L.mesh);
+      used += (double)fp;
+      preparing.push_back(prepare(r, i, fp, desc->device));
+    }
+    // requests whose mesh is ready: device state, then live
+    for (size_t j = 0; j < preparing.size();) {
+      Prep& P = *preparing[j];
+      if (P.done.wait_for(std::chrono::seconds(0)) != std::future_status::ready) {
+        ++j;
+        continue;
+      }
+      const dgw_status st = P.done.get();
+      const int i = P.idx;
+      const dgw_request& r = reqs[i];
       if (st) {
+        if (P.mesh) dgw_mesh_destroy(P.mesh);
         out[i].status = st;
         out[i].t_done = now();
         ++failed;
+        used -= (double)P.footprint;
+        preparing.erase(preparing.begin() + j);
         continue;
       }
+      Live L;
+      L.idx = i;
+      L.footprint = P.footprint;
+      L.mesh = P.mesh;
       dgw_mesh_info info;
       dgw_mesh_info_get(L.mesh, &info);
       L.dofs = info.dofs;
@@ -236,25 +285,25 @@ dgw_status dgw_serve(const dgw_server_desc* desc, const dgw_request* reqs, int n
       const double dt0 = r.courant * info.dt_unit;
       L.steps = std::max<int64_t>(1, (int64_t)std::ceil(r.t_end / dt0 - 1e-12));
       L.dt = r.t_end / (double)L.steps;
-      std::vector<double> u0;
-      initial_state(L.mesh, r, u0);
       if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
           hipMalloc(&L.u, L.dofs * 8) != hipSuccess || hipMalloc(&L.work, 2 * L.dofs * 8) != hipSuccess) {
         (void)hipGetLastError();
-        used += (double)fp;
         retire(L, fail(DGW_ENOMEM, "device allocation for a request"));
+        preparing.erase(preparing.begin() + j);
         continue;
       }
-      (void)hipMemcpyAsync(L.u, u0.data(), L.dofs * 8, hipMemcpyHostToDevice, L.stream);
+      (void)hipMemcpyAsync(L.u, P.u0.data(), L.dofs * 8, hipMemcpyHostToDevice, L.stream);
       (void)hipStreamSynchronize(L.stream);
       double e0 = 0;
       (void)dgw_energy(L.mesh, L.u, 1, &e0, L.stream);
       out[i].energy0 = e0;
-      used += (double)fp;
       live.push_back(L);
+      preparing.erase(preparing.begin() + j);
     }
     if (live.empty()) {
-      if (!pending.empty() && desc->realtime) {
+      if (!preparing.empty()) {
+        preparing.front()->done.wait_for(std::chrono::milliseconds(2));
+      } else if (!pending.empty() && desc->realtime) {
         const double wait = reqs[pending.front()].arrival_s - now();
         if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.01)));
       }

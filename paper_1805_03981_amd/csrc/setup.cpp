@@ -493,7 +493,16 @@ dgw_status build_setup(const dgw_mesh_desc& desc, HostSetup& hs) {
     });
     rho.resize((size_t)cn * pts_per_cell);
     cc.resize((size_t)cn * pts_per_cell);
-    desc.material(X.data(), cn * pts_per_cell, d, rho.data(), cc.data(), desc.material_ctx);
+    if (desc.material == dgw_material_fourier) {
+      // the library's own material is thread-safe: one block of cells per
+      // call; a caller's callback is called from this thread only
+      parallel_for(cn, [&](int64_t i) {
+        const size_t o = (size_t)i * pts_per_cell;
+        desc.material(X.data() + o * d, pts_per_cell, d, rho.data() + o, cc.data() + o, desc.material_ctx);
+      });
+    } else {
+      desc.material(X.data(), cn * pts_per_cell, d, rho.data(), cc.data(), desc.material_ctx);
+    }
     parallel_for(cn, [&](int64_t i) {
       const int64_t cell = c0 + i;
       double Ji[9];

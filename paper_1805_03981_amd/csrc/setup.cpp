@@ -154,39 +154,6 @@ int ipw(int b, int e) {
   return r;
 }
 
-// Apply per-direction matrices M[e] (mo[e] x mi) to a tensor of extents mi^d
-// (x fastest); out has extents mo[0] x mo[1] (x mo[2]).
-void tensor_eval(int d, int mi, const double* in, const std::vector<const double*>& M, const int* mo, double* out,
-                 std::vector<double>& t1, std::vector<double>& t2) {
-  int ext[3] = {mi, mi, d == 3 ? mi : 1};
-  const double* src = in;
-  for (int e = 0; e < d; ++e) {
-    int eo[3] = {ext[0], ext[1], ext[2]};
-    eo[e] = mo[e];
-    const int nout = eo[0] * eo[1] * eo[2];
-    std::vector<double>& dst = (e % 2 == 0) ? t1 : t2;
-    double* o = (e == d - 1) ? out : (dst.resize(nout), dst.data());
-    const int si[3] = {1, ext[0], ext[0] * ext[1]};
-    const int so[3] = {1, eo[0], eo[0] * eo[1]};
-    for (int k2 = 0; k2 < eo[2]; ++k2)
-      for (int k1 = 0; k1 < eo[1]; ++k1)
-        for (int k0 = 0; k0 < eo[0]; ++k0) {
-          int kk[3] = {k0, k1, k2};
-          const int io = kk[0] * so[0] + kk[1] * so[1] + kk[2] * so[2];
-          const int row = kk[e];
-          kk[e] = 0;
-          const int ib = kk[0] * si[0] + kk[1] * si[1] + kk[2] * si[2];
-          double acc = 0;
-          for (int j = 0; j < ext[e]; ++j) acc += M[e][row * ext[e] + j] * src[ib + j * si[e]];
-          o[io] = acc;
-        }
-    src = o;
-    ext[0] = eo[0];
-    ext[1] = eo[1];
-    ext[2] = eo[2];
-  }
-}
-
 struct GeoMats {
   // value and derivative of the equispaced Lagrange polynomials at 1D points
   std::vector<double> V, W;
@@ -208,30 +175,77 @@ GeoMats geo_mats(int q, const std::vector<ld>& pts) {
   return g;
 }
 
+// One sum-factorized pass along direction dir of a tensor of d-vectors:
+// in has extents E[3] (x fastest, the d components innermost), the m x E[dir]
+// matrix M replaces extent dir by m; out[point * ostride + a * cstride].
+static void map_pass(int d, const int* E, int dir, const double* in, const double* M, int m, double* out,
+                     int ostride, int cstride) {
+  int eo[3] = {E[0], E[1], E[2]};
+  eo[dir] = m;
+  const int si[3] = {1, E[0], E[0] * E[1]};
+  const int so[3] = {1, eo[0], eo[0] * eo[1]};
+  const int n = E[dir];
+  for (int k2 = 0; k2 < eo[2]; ++k2)
+    for (int k1 = 0; k1 < eo[1]; ++k1)
+      for (int k0 = 0; k0 < eo[0]; ++k0) {
+        int kk[3] = {k0, k1, k2};
+        const int io = k0 * so[0] + k1 * so[1] + k2 * so[2];
+        const int row = kk[dir];
+        kk[dir] = 0;
+        const double* src = in + (size_t)(kk[0] * si[0] + kk[1] * si[1] + kk[2] * si[2]) * d;
+        const double* mr = M + (size_t)row * n;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < n; ++j) {
+          const double w = mr[j];
+          const double* v = src + (size_t)j * si[dir] * d;
+          for (int a = 0; a < d; ++a) acc[a] += w * v[a];
+        }
+        for (int a = 0; a < d; ++a) out[(size_t)io * ostride + a * cstride] = acc[a];
+      }
+}
+
 // x [P][d] and J [P][d][d] (J[p][a][b] = dx_a/dxi_b) of one cell at the tensor
-// point set given by per-direction matrices.
+// point set given by per-direction matrices (V values, W derivatives of the
+// 1D geometry Lagrange polynomials).  All d coordinates in one pass, and the
+// passes shared between the map and its derivatives: in 3D, V0/W0 along x,
+// then V1 on both and W1 on the V0 branch, then the last direction.
 void eval_map(int d, int q, const double* X, const std::vector<const GeoMats*>& gm, double* x, double* J,
               std::vector<double>& comp, std::vector<double>& res, std::vector<double>& t1,
               std::vector<double>& t2) {
-  const int ng = ipw(q + 1, d);
-  int mo[3] = {gm[0]->m, gm[1]->m, d == 3 ? gm[2]->m : 1};
-  const int P = mo[0] * mo[1] * mo[2];
-  comp.resize(ng);
-  res.resize(P);
-  for (int a = 0; a < d; ++a) {
-    for (int g = 0; g < ng; ++g) comp[g] = X[g * d + a];
-    for (int b = -1; b < d; ++b) {
-      std::vector<const double*> M(d);
-      for (int e = 0; e < d; ++e) M[e] = (e == b) ? gm[e]->W.data() : gm[e]->V.data();
-      tensor_eval(d, q + 1, comp.data(), M, mo, res.data(), t1, t2);
-      for (int p = 0; p < P; ++p) {
-        if (b < 0)
-          x[p * d + a] = res[p];
-        else
-          J[(p * d + a) * d + b] = res[p];
-      }
-    }
+  const int Q = q + 1;
+  const int m0 = gm[0]->m, m1 = gm[1]->m;
+  int E[3] = {Q, Q, d == 3 ? Q : 1};
+  // direction 0: A = V0 X, B = W0 X
+  const int nA = m0 * Q * (d == 3 ? Q : 1);
+  comp.resize((size_t)nA * d);
+  res.resize((size_t)nA * d);
+  map_pass(d, E, 0, X, gm[0]->V.data(), m0, comp.data(), d, 1);
+  map_pass(d, E, 0, X, gm[0]->W.data(), m0, res.data(), d, 1);
+  E[0] = m0;
+  if (d == 2) {
+    // direction 1: x = V1 A, dx/dxi1 = W1 A, dx/dxi0 = V1 B
+    map_pass(d, E, 1, comp.data(), gm[1]->V.data(), m1, x, d, 1);
+    map_pass(d, E, 1, comp.data(), gm[1]->W.data(), m1, J + 1, d * d, d);
+    map_pass(d, E, 1, res.data(), gm[1]->V.data(), m1, J + 0, d * d, d);
+    return;
   }
+  const int m2 = gm[2]->m;
+  // direction 1: AA = V1 A, AW = W1 A, BV = V1 B
+  const int nB = m0 * m1 * Q;
+  t1.resize((size_t)2 * nB * d);
+  t2.resize((size_t)nB * d);
+  double* AA = t1.data();
+  double* AW = t1.data() + (size_t)nB * d;
+  double* BV = t2.data();
+  map_pass(d, E, 1, comp.data(), gm[1]->V.data(), m1, AA, d, 1);
+  map_pass(d, E, 1, comp.data(), gm[1]->W.data(), m1, AW, d, 1);
+  map_pass(d, E, 1, res.data(), gm[1]->V.data(), m1, BV, d, 1);
+  E[1] = m1;
+  // direction 2: x = V2 AA, dx/dxi2 = W2 AA, dx/dxi1 = V2 AW, dx/dxi0 = V2 BV
+  map_pass(d, E, 2, AA, gm[2]->V.data(), m2, x, d, 1);
+  map_pass(d, E, 2, AA, gm[2]->W.data(), m2, J + 2, d * d, d);
+  map_pass(d, E, 2, AW, gm[2]->V.data(), m2, J + 1, d * d, d);
+  map_pass(d, E, 2, BV, gm[2]->V.data(), m2, J + 0, d * d, d);
 }
 
 double det_inv(int d, const double* J, double* Ji) {

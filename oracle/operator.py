@@ -191,13 +191,68 @@ def _chol_apply(L, r):
     return np.swapaxes(x, -1, -2)
 
 
-def apply_mass_inverse(mesh, r, cells, storage="gl"):
-    """M^-1 r with the dense per-cell mass matrices (Cholesky)."""
+def apply_mass_inverse(mesh, r, cells, storage="gl", extended=False):
+    """M^-1 r with the dense per-cell mass matrices (Cholesky).
+
+    extended: assemble M and solve in extended precision (numpy.longdouble,
+    64-bit significand on x86) and round the result to float64.  The dense
+    mass matrix has condition kappa_1D^d (about 3.5e3 for k = 7 in 3D), so the
+    float64 solve carries a relative error up to about kappa eps; the extended
+    solve removes that part of the oracle's own rounding."""
     d = mesh.dim
+    if extended:
+        return _mass_inverse_extended(mesh, r, cells, storage)
     Lv, Lp = cholesky_factors(mesh, cells, storage)
     out = np.empty_like(r)
     out[:, :d, :] = _chol_apply(Lv, r[:, :d, :])
     out[:, d:, :] = _chol_apply(Lp, r[:, d:, :])
+    return out
+
+
+def _cholesky_ld(M):
+    """Lower Cholesky factors of a batch M[C][n][n] in the dtype of M
+    (column by column: L_jj = sqrt(M_jj - sum_k L_jk^2), then the column below)."""
+    C, n, _ = M.shape
+    L = np.zeros_like(M)
+    for j in range(n):
+        col = M[:, j:, j] - np.einsum("cik,ck->ci", L[:, j:, :j], L[:, j, :j])
+        piv = np.sqrt(col[:, 0])
+        L[:, j, j] = piv
+        L[:, j + 1:, j] = col[:, 1:] / piv[:, None]
+    return L
+
+
+def _tri_solve_ld(L, b, lower):
+    """Solve L x = b (lower) or L^T x = b (upper) for b[C][n][m] by substitution."""
+    C, n, _ = L.shape
+    x = np.zeros_like(b)
+    rng = range(n) if lower else range(n - 1, -1, -1)
+    for i in rng:
+        if lower:
+            acc = b[:, i, :] - np.einsum("ck,ckm->cm", L[:, i, :i], x[:, :i, :])
+        else:
+            acc = b[:, i, :] - np.einsum("ck,ckm->cm", L[:, i + 1:, i], x[:, i + 1:, :])
+        x[:, i, :] = acc / L[:, i, i][:, None]
+    return x
+
+
+def _mass_inverse_extended(mesh, r, cells, storage):
+    ld = np.longdouble
+    d = mesh.dim
+    T = tables(mesh, storage)
+    cd = mesh.cell_data(cells)
+    phi = T.phi.astype(ld)
+    wdet = cd["wdet"].astype(ld)
+    rho = cd["rho"].astype(ld)
+    c = cd["c"].astype(ld)
+    out = np.empty_like(r)
+    for wq, comps in ((wdet * rho, slice(0, d)), (wdet / (rho * c * c), slice(d, d + 1))):
+        M = np.stack([(phi * wq[i][:, None]).T @ phi for i in range(len(cells))])
+        L = _cholesky_ld(M)
+        b = np.swapaxes(r[:, comps, :].astype(ld), 1, 2)          # [C][np][ncomp]
+        y = _tri_solve_ld(L, b, lower=True)
+        x = _tri_solve_ld(L, y, lower=False)
+        out[:, comps, :] = np.swapaxes(x, 1, 2).astype(np.float64)
     return out
 
 
@@ -208,12 +263,13 @@ def _chunks(mesh, cells):
         yield cells[s:s + step]
 
 
-def apply_operator(mesh, U, cells=None, flux="upwind", storage="gl", exterior=None):
+def apply_operator(mesh, U, cells=None, flux="upwind", storage="gl", exterior=None, extended=False):
     """L U = M^-1 (-K U) (Sec. 2.1, eq. matrix-tc-sd) on `cells` (default all).
 
     U: float64[Nc][d+1][np] coefficients of the full state in the storage
     basis (neighbours are read); exterior: the prescribed exterior state
-    x[...][d] -> float64[...][d+1] for BC_PRESCRIBED faces.  Returns
+    x[...][d] -> float64[...][d+1] for BC_PRESCRIBED faces; extended: the
+    mass solve in extended precision (apply_mass_inverse).  Returns
     float64[C][d+1][np].
     """
     U = np.asarray(U, dtype=np.float64)
@@ -222,7 +278,7 @@ def apply_operator(mesh, U, cells=None, flux="upwind", storage="gl", exterior=No
     pos = 0
     for ch in _chunks(mesh, cells):
         r = residual(mesh, U, ch, flux, storage, exterior)
-        out[pos:pos + len(ch)] = apply_mass_inverse(mesh, r, ch, storage)
+        out[pos:pos + len(ch)] = apply_mass_inverse(mesh, r, ch, storage, extended)
         pos += len(ch)
     return out
 

@@ -195,3 +195,34 @@ def test_curved_3d_plane_wave_convergence():
             U = ts.lsrk_step(lambda u, t: apply_operator(m, u), U, s * dt, dt)
         errs.append(norms.l2_error(m, U, W.plane_wave_3d, 0.1)[0])
     assert np.log(errs[0] / errs[1]) / np.log(1.5) > k + 1 - 0.5
+
+
+@pytest.mark.parametrize("k", [5, 7])
+def test_mass_solve_matches_extended_precision(k):
+    """The oracle's float64 Cholesky solve of the dense mass matrix (condition
+    kappa_1D^3, about 3.5e3 for k = 7) against the same solve in extended
+    precision: the oracle's own rounding is far below the 1e-12 parity bar.
+    And the extended solve equals the basis-change formula of Sec. 3.1
+    (M_GL^-1 = S^-1 diag(1/(w det J rho)) S^-T), evaluated in float64 one
+    direction at a time, to the same level."""
+    dim = 3
+    m = make(dim, 1, k, 0.05, W.FourierMaterial(11, dim=dim, rho_amp=0.3))
+    r = W.random_state(k, (m.nc, dim + 1, m.np_))
+    cells = np.arange(m.nc)
+    a = op.apply_mass_inverse(m, r, cells)
+    b = op.apply_mass_inverse(m, r, cells, extended=True)
+    assert norms.rel_l2(a, b) < 1e-14
+    assert np.abs(a - b).max() < 1e-14 * np.abs(b).max()
+    n = k + 1
+    xg, _ = basis.gauss(n)
+    Si = np.linalg.inv(basis.lagrange(m.xgl, xg))       # G values -> GL coefficients
+    cd = m.cell_data(cells)
+    mu = [1.0 / (cd["wdet"][0] * cd["rho"][0])] * dim + [cd["rho"][0] * cd["c"][0] ** 2 / cd["wdet"][0]]
+    for v in range(dim + 1):
+        t = r[0, v].reshape(n, n, n)                        # [z][y][x]
+        for ax in range(3):                                 # S^-T
+            t = np.moveaxis(np.tensordot(Si.T, t, axes=([1], [2 - ax])), 0, 2 - ax)
+        t = t * mu[v].reshape(n, n, n)
+        for ax in range(3):                                 # S^-1
+            t = np.moveaxis(np.tensordot(Si, t, axes=([1], [2 - ax])), 0, 2 - ax)
+        assert np.abs(t.ravel() - b[0, v]).max() < 1e-13 * np.abs(b[0, v]).max()

@@ -1,21 +1,16 @@
-"""Parity tolerances derived from the arithmetic.
+"""Parity tolerances.
 
-FP64 time steps from the same state: 1e-12 relative (coefficient 2-norm).
-A single FP64 operator application: max(1e-12, 4 eps kappa_1D(k)^d), where
-kappa_1D is the condition number of the 1D Gauss-Lobatto mass matrix (Gauss
-quadrature): the oracle inverts the dense d-dimensional mass matrix by
-Cholesky, whose rounding error grows with kappa_1D^d (7.7e-13 for k = 7 in
-3D), and the operator output has no damping factor dt in front of it.
+FP64 time steps from the same state and single FP64 operator applications:
+1e-12 relative, both in the coefficient 2-norm and element by element per
+state component.  The oracle's own rounding stays far below that bar: its
+dense float64 Cholesky mass solve agrees with the same solve in extended
+precision to about 2e-15 even for k = 7 in 3D, where the condition number
+kappa_1D^d of the mass matrix is about 3.5e3
+(tests/test_oracle_operator.py::test_mass_solve_matches_extended_precision).
 """
-import numpy as np
-
 STEP_TOL = 1e-12
 
 
 def op_tol(k, dim):
-    from oracle import basis
-    n = k + 1
-    xg, wg = basis.gauss(n)
-    S = basis.lagrange(basis.gauss_lobatto(n)[0], xg)
-    kappa = np.linalg.cond(S.T @ np.diag(wg) @ S) ** dim
-    return max(STEP_TOL, 4 * np.finfo(float).eps * kappa)
+    """Bar of a single operator application (the same for every degree)."""
+    return STEP_TOL

@@ -20,6 +20,7 @@ from .generators import (  # noqa: F401
     PlaneWaves,
     c3_literal_plane_wave,
     FourierMaterial,
+    GradedMedium,
     ConstantMaterial,
     standing_wave_2d,
     plane_wave_3d,

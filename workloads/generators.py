@@ -209,27 +209,41 @@ class ConstantMaterial:
         return np.full(shp, self.rho), np.full(shp, self.c)
 
 
+def _fourier_modes(rng, dim, nmodes):
+    """nmodes wave vectors uniform in {-2..2}^d without 0, amplitudes ~ U[-1,1],
+    phases ~ U[0, 2 pi), drawn in this order from rng."""
+    modes = []
+    while len(modes) < nmodes:
+        m = rng.integers(-2, 3, size=dim)
+        if np.any(m != 0):
+            modes.append(m)
+    return (np.array(modes, dtype=np.int64), rng.uniform(-1.0, 1.0, size=nmodes),
+            rng.uniform(0.0, TWO_PI, size=nmodes))
+
+
 class FourierMaterial:
-    """c(x) = clamp(c0 + amp * nmodes^-1/2 * sum_i a_i cos(2 pi m_i.x + phi_i), cmin, cmax), rho const.
+    """c(x) = clamp(c0 + amp * nmodes^-1/2 * sum_i a_i cos(2 pi m_i.x + phi_i), cmin, cmax).
 
     The mode data are drawn with numpy.random.default_rng(seed): wave vectors
     m_i uniform in {-2..2}^d without 0, a_i ~ U[-1,1], phi_i ~ U[0, 2 pi).
     The field is 1-periodic in every coordinate.
+
+    Density: rho(x) = rho for rho_amp = 0 (the default); otherwise a second
+    field of the same kind with its own modes, drawn from
+    default_rng(seed + 7919) so that c is the same for either choice:
+    rho(x) = clamp(rho (1 + rho_amp nmodes^-1/2 sum_i b_i cos(2 pi n_i.x + psi_i)),
+    0.7 rho, 1.3 rho).
     """
 
     def __init__(self, seed: int, dim: int = 3, nmodes: int = 8, amp: float = 0.3,
-                 c0: float = 1.0, cmin: float = 0.7, cmax: float = 1.3, rho: float = 1.0):
-        rng = np.random.default_rng(seed)
-        modes = []
-        while len(modes) < nmodes:
-            m = rng.integers(-2, 3, size=dim)
-            if np.any(m != 0):
-                modes.append(m)
-        self.m = np.array(modes, dtype=np.int64)
-        self.a = rng.uniform(-1.0, 1.0, size=nmodes)
-        self.phi = rng.uniform(0.0, TWO_PI, size=nmodes)
+                 c0: float = 1.0, cmin: float = 0.7, cmax: float = 1.3, rho: float = 1.0,
+                 rho_amp: float = 0.0):
+        self.m, self.a, self.phi = _fourier_modes(np.random.default_rng(seed), dim, nmodes)
         self.dim, self.nmodes, self.amp = dim, nmodes, amp
         self.c0, self.cmin, self.cmax, self.rho = c0, cmin, cmax, rho
+        self.rho_amp = float(rho_amp)
+        if self.rho_amp != 0.0:
+            self.rm, self.rb, self.rpsi = _fourier_modes(np.random.default_rng(seed + 7919), dim, nmodes)
 
     def c(self, x: np.ndarray) -> np.ndarray:
         x = np.asarray(x, dtype=np.float64)
@@ -237,9 +251,16 @@ class FourierMaterial:
         s = np.cos(arg) @ self.a
         return np.clip(self.c0 + self.amp / np.sqrt(self.nmodes) * s, self.cmin, self.cmax)
 
+    def density(self, x: np.ndarray) -> np.ndarray:
+        x = np.asarray(x, dtype=np.float64)
+        if self.rho_amp == 0.0:
+            return np.full(x.shape[:-1], self.rho)
+        arg = TWO_PI * (x @ self.rm.T.astype(np.float64)) + self.rpsi
+        s = np.cos(arg) @ self.rb
+        return np.clip(self.rho * (1.0 + self.rho_amp / np.sqrt(self.nmodes) * s), 0.7 * self.rho, 1.3 * self.rho)
+
     def __call__(self, x: np.ndarray):
-        c = self.c(x)
-        return np.full_like(c, self.rho), c
+        return self.density(x), self.c(x)
 
 
 def standing_wave_2d(x: np.ndarray, t: float = 0.0) -> np.ndarray:
@@ -386,3 +407,35 @@ def c2_workload(ncell: int = 24, k: int = 5, seed: int = 1805):
     x0 = random_points(seed + 1, 1, 3)[0]
     return dict(dim=3, ncell=ncell, k=k, q=k, amp=0.05, material=mat,
                 ic=lambda x: gaussian_pulse(x, x0, 0.05), x0=x0)
+
+
+class GradedMedium:
+    """A medium graded along x with a constant impedance, and its exact wave.
+
+    c(x) = c0 / (1 + eps sin(2 pi x)), rho(x) = (Z / c0)(1 + eps sin(2 pi x)),
+    so Z = rho c is constant and both coefficients vary inside every cell along
+    the direction of propagation.  With the travel time
+    tau(x) = (x + eps (1 - cos(2 pi x)) / (2 pi)) / c0 (tau' = 1/c) the
+    right-going wave p = cos(2 pi c0 (tau(x) - t)), v = (p / Z, 0, ..) solves
+    rho v_t + grad p = 0, p_t + rho c^2 div v = 0 exactly (p + Z v_x is carried
+    along x at the local speed c; the impedance is matched, so nothing is
+    reflected).  The field is 1-periodic in x."""
+
+    def __init__(self, eps: float = 0.3, c0: float = 1.0, Z: float = 1.2):
+        self.eps, self.c0, self.Z = float(eps), float(c0), float(Z)
+
+    def _g(self, x):
+        return 1.0 + self.eps * np.sin(TWO_PI * np.asarray(x, dtype=np.float64)[..., 0])
+
+    def __call__(self, x):
+        g = self._g(x)
+        return self.Z / self.c0 * g, self.c0 / g
+
+    def wave(self, x, t=0.0):
+        x = np.asarray(x, dtype=np.float64)
+        s = x[..., 0] + self.eps * (1.0 - np.cos(TWO_PI * x[..., 0])) / TWO_PI
+        p = np.cos(TWO_PI * (s - self.c0 * t))
+        out = np.zeros(x.shape[:-1] + (x.shape[-1] + 1,))
+        out[..., 0] = p / self.Z
+        out[..., -1] = p
+        return out

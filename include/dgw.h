@@ -336,8 +336,11 @@ typedef struct dgw_solve_desc {
   const dgw_sources* sources;/* may be NULL                                       */
   int use_graph;             /* capture one step in a hipGraph and replay it      */
   int autotune;              /* time the launch shapes once and keep the fastest  */
-  int watchdog_every;        /* energy check every N steps (0 = off)              */
-  double watchdog_growth;    /* DGW_EUNSTABLE if energy > growth * initial (10)   */
+  int watchdog_every;        /* energy check of every member every N steps (0 = off) */
+  double watchdog_growth;    /* DGW_EUNSTABLE if a member's energy is not finite, or
+                                exceeds growth (default 10) times its initial energy;
+                                members that start at rest are checked for a finite
+                                energy only                                       */
   void* stream;
 } dgw_solve_desc;
 typedef struct dgw_solve_report {

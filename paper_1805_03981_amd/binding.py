@@ -185,7 +185,10 @@ def material_callback(fn):
 
 
 def fourier_material_struct(mat) -> FourierMaterial:
-    """The C struct of a workloads.FourierMaterial (same modes, same formula)."""
+    """The C struct of a workloads.FourierMaterial (same modes, same formula;
+    the C material has a constant density)."""
+    if getattr(mat, "rho_amp", 0.0) != 0.0:
+        raise ValueError("the C Fourier material has a constant density (rho_amp must be 0)")
     f = FourierMaterial()
     f.nmodes = mat.nmodes
     for i in range(mat.nmodes):

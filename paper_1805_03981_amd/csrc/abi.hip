@@ -1321,12 +1321,21 @@ dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, d
   double* aux = work;  // du (LSRK) or I (ADER)
   const dgw_sources* src = desc->sources;
   double e0 = 0, e1 = 0;
-  std::vector<double> en(B);
+  std::vector<double> en(B), en0(B, 0.0);
   if (desc->watchdog_every > 0 || report) {
     if ((st = energy_impl(m, cur, B, en.data(), s))) return st;
     e0 = en[0];
+    en0 = en;
   }
   const double growth = desc->watchdog_growth > 0 ? desc->watchdog_growth : 10.0;
+  // every member: a non-finite energy trips; a member that started with
+  // positive energy trips when it exceeds growth times that energy (one that
+  // starts at rest, driven by a source, is checked for a finite energy only)
+  auto unstable = [&]() {
+    for (int b = 0; b < B; ++b)
+      if (!std::isfinite(en[b]) || (en0[b] > 0 && !(en[b] <= growth * en0[b]))) return true;
+    return false;
+  };
   auto one = [&](int64_t k, const long long* ctr, int add) -> dgw_status {
     return desc->scheme != DGW_SCHEME_ADER
                ? lsrk_step(m, B, src, desc->t0, dt, (int)(ctr ? add : k), ctr, cur, oth, aux, s, desc->scheme)
@@ -1388,8 +1397,7 @@ dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, d
       k += 2;
       if (desc->watchdog_every > 0 && (k % desc->watchdog_every) < 2) {
         if ((st = energy_impl(m, cur, B, en.data(), gs))) break;
-        if (!(en[0] <= growth * e0))
-          st = fail(DGW_EUNSTABLE, "energy grew beyond the watchdog limit (time step too large?)");
+        if (unstable()) st = fail(DGW_EUNSTABLE, "energy grew beyond the watchdog limit (time step too large?)");
       }
     }
     cleanup();
@@ -1403,7 +1411,7 @@ dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, d
     if ((st = one(k, nullptr, 0))) return st;
     if (desc->watchdog_every > 0 && (k + 1) % desc->watchdog_every == 0) {
       if ((st = energy_impl(m, cur, B, en.data(), s))) return st;
-      if (!(en[0] <= growth * e0)) return fail(DGW_EUNSTABLE, "energy grew beyond the watchdog limit (time step too large?)");
+      if (unstable()) return fail(DGW_EUNSTABLE, "energy grew beyond the watchdog limit (time step too large?)");
     }
   }
   if (cur != u) DGW_HIP(hipMemcpyAsync(u, cur, ne * 8, hipMemcpyDeviceToDevice, s));

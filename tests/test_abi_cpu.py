@@ -63,7 +63,7 @@ def test_basis_tables_match_oracle(B, n):
                                              (2, 3, 3, 0.05, ("wall", "absorbing")),
                                              (3, 3, 2, 0.05, ("absorbing", "periodic", "wall"))])
 def test_host_setup_matches_oracle_geometry(B, dim, nc, k, amp, bc):
-    mat = W.FourierMaterial(3, dim=dim)
+    mat = W.FourierMaterial(3, dim=dim, rho_amp=0.3)
     nodes, nb = W.box_nodes(dim, nc, k, amp), W.box_neighbors(dim, nc, bc)
     gm = B.Mesh(dim, k, nodes, nb, mat, device=B.DEVICE_NONE)
     om = OMesh(dim, k, nodes, nb, mat)
@@ -92,7 +92,7 @@ def test_host_setup_with_face_orientations(B, dim, nc, k):
     """Renumbered cells (faces meeting with other indices and orientations):
     the host face data, the neighbour impedance at the oriented point
     included, agrees with the oracle's."""
-    mat = W.FourierMaterial(5, dim=dim)
+    mat = W.FourierMaterial(5, dim=dim, rho_amp=0.3)
     nodes, nb, fo, _ = W.rotated_box(dim, nc, k, 0.05, seed=17 + k)
     gm = B.Mesh(dim, k, nodes, nb, mat, device=B.DEVICE_NONE, face_orient=fo)
     om = OMesh(dim, k, nodes, nb, mat, face_orient=fo)
@@ -131,7 +131,7 @@ def test_face_orientation_validation(B):
 def test_level_metric_matches_oracle(B):
     from oracle import ader
     dim, nc, k = 3, 2, 5
-    mat = W.FourierMaterial(4, dim=dim)
+    mat = W.FourierMaterial(4, dim=dim, rho_amp=0.3)
     nodes, nb = W.box_nodes(dim, nc, k, 0.05), W.box_neighbors(dim, nc)
     gm = B.Mesh(dim, k, nodes, nb, mat, device=B.DEVICE_NONE)
     om = OMesh(dim, k, nodes, nb, mat)
@@ -143,6 +143,11 @@ def test_level_metric_matches_oracle(B):
         jr = Gl[:, :dim * dim] * Gl[:, dim * dim:dim * dim + 1]
         want = np.moveaxis(ld["Jinv"].reshape(om.nc, m ** dim, dim * dim), 1, 2) / ld["rho"][:, None, :]
         assert np.abs(jr - want).max() < 1e-13 * np.abs(want).max()
+        jp = Gl[:, :dim * dim] * Gl[:, dim * dim + 1:dim * dim + 2]
+        want = want * (ld["rho"] ** 2 * ld["c"] ** 2)[:, None, :]
+        assert np.abs(jp - want).max() < 1e-13 * np.abs(want).max()
+    # the density really varies inside the cells
+    assert np.ptp(om.cell_data(np.arange(om.nc))["rho"], axis=1).min() > 1e-3
 
 
 def test_footprint_and_validation(B):

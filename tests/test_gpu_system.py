@@ -101,19 +101,62 @@ def test_graph_replay_equals_eager(gpu_lib, scheme):
     assert torch.equal(a, c)
 
 
-def test_autotune_keeps_results(gpu_lib):
-    say("autotune")
+@pytest.mark.parametrize("k", [3, 5])
+def test_launch_shapes_give_identical_bits(gpu_lib, k):
+    """Every compiled launch shape (cells per workgroup) of the operator and of
+    the TCK gives bitwise the same operator, LSRK and ADER results (each cell's
+    arithmetic does not depend on its neighbours in the workgroup); the
+    autotuner only picks among them."""
+    say("launch shapes", k)
     B = gpu_lib
-    gm = B.Mesh(3, 5, W.box_nodes(3, 3, 5, 0.05), W.box_neighbors(3, 3), W.FourierMaterial(1, dim=3))
-    U = to_dev(W.random_state(1, (1,) + gm.shape))
+    gm = B.Mesh(3, k, W.box_nodes(3, 3, k, 0.05), W.box_neighbors(3, 3), W.FourierMaterial(1, dim=3, rho_amp=0.3))
+    U = W.random_state(1, (1,) + gm.shape)
+    dt = 0.3 * gm.info.dt_unit
+    cpw = sorted({gm.launch_shape(0)[0]} | {2 * gm.launch_shape(0)[0]} | {max(1, gm.launch_shape(0)[0] // 2)})
     shapes = []
-    outs = []
-    for cells in (gm.launch_shape(0)[0],):
-        outs.append(gm.apply(U).clone())
+    for c in cpw:
+        try:
+            gm.launch_shape(0, cells=c)
+            gm.launch_shape(1, cells=c)
+        except B.DgwError:
+            continue
+        shapes.append(c)
+    assert len(shapes) >= 2, shapes
+    res = []
+    for c in shapes:
+        gm.launch_shape(0, cells=c)
+        gm.launch_shape(1, cells=c)
+        assert gm.launch_shape(0)[0] == c and gm.launch_shape(1)[0] == c
+        a = gm.apply(to_dev(U))
+        ul = to_dev(U)
+        gm.step_lsrk(ul, 0.0, dt, 2)
+        ua = to_dev(U)
+        gm.step_ader(ua, 0.0, dt, 2)
+        res.append((a, ul, ua))
+    for r in res[1:]:
+        for x, y in zip(res[0], r):
+            assert torch.equal(x, y)
     gm.autotune(1)
-    shapes.append(gm.launch_shape(0))
-    outs.append(gm.apply(U))
-    assert torch.allclose(outs[0], outs[1], rtol=0, atol=1e-12 * outs[0].abs().max().item())
+    assert gm.launch_shape(0)[0] in shapes
+    assert torch.equal(gm.apply(to_dev(U)), res[0][0])
+
+
+def test_watchdog_checks_every_member(gpu_lib):
+    """Member 0 at rest and member 1 unstable: the watchdog trips (it checks
+    every member); a source-driven solve from rest at a stable step runs
+    through (a zero initial energy is no reference for growth)."""
+    say("watchdog members")
+    B = gpu_lib
+    gm = B.Mesh(2, 3, W.box_nodes(2, 4, 3, 0.0), W.box_neighbors(2, 4), W.ConstantMaterial(), max_batch=2)
+    U = np.zeros((2,) + gm.shape)
+    U[1] = W.random_state(2, gm.shape)
+    with pytest.raises(B.DgwError) as e:
+        gm.solve(to_dev(U), B.ADER, t_end=200 * 3.0 * gm.info.dt_unit, courant=3.0, watchdog_every=10, B=2)
+    assert e.value.status == B.EUNSTABLE
+    src = B.Sources(gm, W.random_points(4, 2, 2), frequency=6.0)
+    u = to_dev(np.zeros((2,) + gm.shape))
+    rep = gm.solve(u, B.ADER, t_end=0.3, courant=0.1, sources=src, watchdog_every=5, B=2)
+    assert rep.steps > 20 and rep.energy_end > 0
 
 
 def test_watchdog_trips_on_unstable_step(gpu_lib):
@@ -206,3 +249,66 @@ def test_serving_alone_equals_mix(gpu_lib):
         assert np.array_equal(states[i], st1[0])
         assert res[i].t_admit >= res[i].t_arrive - 1e-9 and res[i].t_done >= res[i].t_admit
     assert rep.p99_s >= rep.p50_s > 0
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_served_request_matches_oracle(gpu_lib, scheme):
+    """An FP64 request through dgw_serve (C box generator, C-built Gaussian
+    initial state, the server's step count) against the oracle's steps on the
+    same box from the same pulse, and against dgw_step_* on a mesh made by
+    dgw_mesh_create_box."""
+    say("served vs oracle", scheme)
+    B = gpu_lib
+    n, k, T = 3, 3, 0.03
+    mat = W.FourierMaterial(61, dim=3)
+    r = B.Request(arrival_s=0.0, dim=3, ncell=n, degree=k, scheme=scheme, precision=0, t_end=T,
+                  courant=0.2, deform_amp=0.05)
+    r.material = B.fourier_material_struct(mat)
+    c = [0.3, 0.55, 0.7]
+    for a in range(3):
+        r.ic_center[a] = c[a]
+    r.ic_width = 0.15
+    rep, res, states = B.serve([r], budget_bytes=1 << 30, max_live=1, realtime=False, keep_states=True)
+    assert res[0].status == 0
+    steps = res[0].steps
+    dt = T / steps
+    got = states[0].reshape(n ** 3, 4, (k + 1) ** 3)
+    om = OMesh(3, k, W.box_nodes(3, n, k, 0.05), W.box_neighbors(3, n), mat)
+    U0 = om.interpolate(lambda x: W.gaussian_pulse(x, c, 0.15))
+    want = U0
+    for s in range(steps):
+        want = (ts.lsrk_step(lambda x, t: apply_operator(om, x), want, s * dt, dt) if scheme == 0
+                else ader.ader_step(om, want, dt))
+    e = norms.rel_l2(got, want)
+    say(f"served request scheme {scheme}: {steps} steps, rel err vs oracle {e:.2e}")
+    assert steps >= 3 and e < 1e-12 * steps
+    gm = B.Mesh.box(3, n, k, 0.05, B.fourier_material_struct(mat))
+    u = to_dev(U0)[None]
+    (gm.step_ader if scheme else gm.step_lsrk)(u, 0.0, dt, steps)
+    assert norms.rel_l2(got, u[0].cpu().numpy()) < 1e-13
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_graded_medium_against_closed_form(gpu_lib, scheme):
+    """Density and sound speed graded along x inside every cell, impedance
+    matched: the right-going wave on the curved 2D box (k = 3, 8x8 cells) to
+    T = 0.15 against its closed form, and the same steps on the oracle."""
+    say("graded medium", scheme)
+    B = gpu_lib
+    g = W.GradedMedium()
+    k, nc = 3, 8
+    nodes, nb = W.box_nodes(2, nc, k, 0.05), W.box_neighbors(2, nc)
+    gm = B.Mesh(2, k, nodes, nb, g)
+    om = OMesh(2, k, nodes, nb, g)
+    U0 = om.interpolate(lambda x: g.wave(x, 0.0))
+    u = to_dev(U0)[None]
+    rep = gm.solve(u, scheme, t_end=0.15, courant=0.15)
+    got = u[0].cpu().numpy()
+    ep, ev = norms.l2_error(om, got, g.wave, 0.15)
+    say(f"graded medium scheme {scheme}: {rep.steps} steps, L2(p) {ep:.3e} L2(v) {ev:.3e}")
+    assert ep < 2e-4 and ev < 2e-4
+    want = U0
+    for s in range(rep.steps):
+        want = (ts.lsrk_step(lambda x, t: apply_operator(om, x), want, s * rep.dt, rep.dt) if scheme == 0
+                else ader.ader_step(om, want, rep.dt))
+    assert norms.rel_l2(got, want) < 1e-11

@@ -127,13 +127,19 @@ class Mesh:
 
     # ---- the map ---------------------------------------------------------
     def map_points(self, cells, ref_pts):
-        """Physical points x[C][P][d] and Jacobians J[C][P][d][d] (J[..,a,b] = dx_a/dxi_b)."""
+        """Physical points x[C][P][d] and Jacobians J[C][P][d][d] (J[..,a,b] = dx_a/dxi_b).
+
+        J is the derivative of the map of the nodes taken relative to the
+        cell's first node (a translation leaves it unchanged; in absolute
+        coordinates of order 1 a cell of size 1/48 would lose about 1e-12 of
+        its Jacobian to cancellation in the derivative sums)."""
         cells = np.atleast_1d(np.asarray(cells, dtype=np.int64))
         psi = basis.tensor_basis(self._geo_ref, ref_pts)          # [P][Ng]
         dpsi = basis.tensor_basis_grad(self._geo_ref, ref_pts)    # [d][P][Ng]
         X = self.geo_nodes[cells]                                  # [C][Ng][d]
         x = np.einsum("pg,cga->cpa", psi, X)
-        J = np.stack([np.einsum("pg,cga->cpa", dpsi[b], X) for b in range(self.dim)], axis=-1)
+        Xr = X - X[:, :1, :]
+        J = np.stack([np.einsum("pg,cga->cpa", dpsi[b], Xr) for b in range(self.dim)], axis=-1)
         return x, J
 
     # ---- cached per-point data ---------------------------------------------

@@ -209,12 +209,29 @@ static void map_pass(int d, const int* E, int dir, const double* in, const doubl
 // 1D geometry Lagrange polynomials).  All d coordinates in one pass, and the
 // passes shared between the map and its derivatives: in 3D, V0/W0 along x,
 // then V1 on both and W1 on the V0 branch, then the last direction.
-void eval_map(int d, int q, const double* X, const std::vector<const GeoMats*>& gm, double* x, double* J,
+//
+// The passes run on the nodes relative to the cell's first node: J does not
+// depend on a translation, and a small cell far from the origin would
+// otherwise lose digits in the sums of its derivatives (absolute coordinates
+// of order 1 cancelling down to a cell size of order 1/n); x gets that node
+// back at the end.
+void eval_map(int d, int q, const double* X_abs, const std::vector<const GeoMats*>& gm, double* x, double* J,
               std::vector<double>& comp, std::vector<double>& res, std::vector<double>& t1,
               std::vector<double>& t2) {
   const int Q = q + 1;
   const int m0 = gm[0]->m, m1 = gm[1]->m;
   int E[3] = {Q, Q, d == 3 ? Q : 1};
+  const int ng = Q * Q * (d == 3 ? Q : 1);
+  thread_local std::vector<double> rel;
+  rel.resize((size_t)ng * d);
+  for (int g = 0; g < ng; ++g)
+    for (int a = 0; a < d; ++a) rel[(size_t)g * d + a] = X_abs[(size_t)g * d + a] - X_abs[a];
+  const double* X = rel.data();
+  const int npts = m0 * m1 * (d == 3 ? gm[2]->m : 1);
+  auto shift_back = [&]() {
+    for (int p = 0; p < npts; ++p)
+      for (int a = 0; a < d; ++a) x[(size_t)p * d + a] += X_abs[a];
+  };
   // direction 0: A = V0 X, B = W0 X
   const int nA = m0 * Q * (d == 3 ? Q : 1);
   comp.resize((size_t)nA * d);
@@ -227,6 +244,7 @@ void eval_map(int d, int q, const double* X, const std::vector<const GeoMats*>& 
     map_pass(d, E, 1, comp.data(), gm[1]->V.data(), m1, x, d, 1);
     map_pass(d, E, 1, comp.data(), gm[1]->W.data(), m1, J + 1, d * d, d);
     map_pass(d, E, 1, res.data(), gm[1]->V.data(), m1, J + 0, d * d, d);
+    shift_back();
     return;
   }
   const int m2 = gm[2]->m;
@@ -246,6 +264,7 @@ void eval_map(int d, int q, const double* X, const std::vector<const GeoMats*>& 
   map_pass(d, E, 2, AA, gm[2]->W.data(), m2, J + 2, d * d, d);
   map_pass(d, E, 2, AW, gm[2]->V.data(), m2, J + 1, d * d, d);
   map_pass(d, E, 2, BV, gm[2]->V.data(), m2, J + 0, d * d, d);
+  shift_back();
 }
 
 double det_inv(int d, const double* J, double* Ji) {

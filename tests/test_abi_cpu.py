@@ -87,6 +87,25 @@ def test_host_setup_matches_oracle_geometry(B, dim, nc, k, amp, bc):
     assert np.abs(x - om.node_points()).max() < 1e-14
 
 
+def test_host_metric_of_small_cells(B):
+    """Cells of the 48^3 box at degree 7 (each cell its own neighbour: only
+    the cell metric is compared): the library's metric against the oracle's
+    to 2e-13 relative, where the map's derivative sums would lose about
+    4e-12 in absolute coordinates."""
+    k, n = 7, 48
+    nodes = W.box_nodes(3, n, k, 0.05)[[0, 1234, 50000, n ** 3 - 1]]
+    nb = np.tile(np.arange(4)[:, None], (1, 6))
+    mat = W.FourierMaterial(3, dim=3, rho_amp=0.3)
+    gm = B.Mesh(3, k, nodes, nb, mat, device=B.DEVICE_NONE)
+    om = OMesh(3, k, nodes, nb, mat)
+    cd = om.cell_data(np.arange(om.nc))
+    G = gm.get(B.GET_CELL_METRIC)
+    want = np.moveaxis((cd["wdet"][:, :, None, None] * cd["Jinv"]).reshape(om.nc, om.np_, 9), 1, 2)
+    assert np.abs(G[:, :9] - want).max() < 2e-13 * np.abs(want).max()
+    muv = 1 / (cd["wdet"] * cd["rho"])
+    assert np.abs(G[:, 9] - muv).max() < 2e-13 * muv.max()
+
+
 @pytest.mark.parametrize("dim,nc,k", [(2, 3, 3), (3, 3, 2), (3, 2, 4)])
 def test_host_setup_with_face_orientations(B, dim, nc, k):
     """Renumbered cells (faces meeting with other indices and orientations):

@@ -11,15 +11,22 @@ LSRK(5,4) stages.  `value` is the FP64 ADER throughput in DoF-steps/s with
 the state resident in HBM, timed over exactly K steps launched back to back
 (the solver's hipGraph time loop over the same K steps, capture included, is
 reported beside it); the other scheme/precision variants are reported
-beside it.  Also reported: per-kernel roofline (HIP events on the launch
-stream), FP32-split error against FP64, the time to solution at a fixed
+beside it.  Also reported by default: per-kernel roofline (HIP events on the
+launch stream), FP32-split error against FP64, the batch of 64 point
+sources on 32^3 cells (k = 5, 500 ADER steps, FP32-split, hipGraph), a
+bounded leg of the 48^3 k = 7 workload (throughput of both schemes and
+precisions, one step against the oracle on sampled cells, plane-wave error
+against the closed form), a serving trace of 24 requests drawn like the
+serving workload (n^3 cells, n in [8, 48], k in 2..8, T in [0.1, 1], Poisson
+arrivals at 0.8 x capacity, p50/p99), the time to solution at a fixed
 pressure error (1e-6 relative at T = 0.5) against FP64 ADER and FP64 LSRK
 references, and the CPU FP64 oracle timed on a bounded sample of the same
-workload.  Optional: the degree sweep k = 1..8 on the paper's cube sizes,
-measured device ceilings, the batch of 64 point sources, a serving trace.
+workload.  Optional: the 200-request serving trace, the degree sweep
+k = 1..8 on the paper's cube sizes, measured device ceilings, ablations.
 
     python bench.py [--steps K] [--warmup W] [--variants ader-fp64,...]
-                    [--no-fixed-error] [--ablations] [--c3] [--sweep] [--ceilings] [--batched] [--no-serving]
+                    [--no-fixed-error] [--ablations] [--c3] [--sweep] [--ceilings] [--no-batched] [--no-c3]
+                    [--no-serving] [--serving-full]
 """
 from __future__ import annotations
 
@@ -48,18 +55,25 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+T_START = time.perf_counter()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print(f"[{time.perf_counter() - T_START:7.1f}s]", *a, file=sys.stderr, flush=True)
 
 
 def algorithmic_bytes(dim, k, kernel):
-    """Minimum HBM bytes per cell of one launch (FP64 state, FP64 metric):
-    every value of the inputs read once and of the outputs written once."""
+    """Algorithmic HBM bytes per cell of one launch (FP64 state, FP64 metric),
+    by the byte model of the measurement plan: a state register
+    (d+1) n^d 8 B per pass, the metric w det J J^-1 (d^2 n^d doubles) and the
+    two mass factors (2 n^d), the face geometry of the faces a cell owns
+    (d faces, d+1 values per face point: d(d+1) n^(d-1) doubles) and the
+    metric of the reduced Gauss sets of the TCK ((d^2+2) m^d per set)."""
     n = k + 1
     np_, nf, nc = n ** dim, n ** (dim - 1), dim + 1
     state = nc * np_ * 8
     cell_geo = (dim * dim + 2) * np_ * 8
-    face_geo = 2 * dim * (dim + 2) * nf * 8 + 2 * dim * 4
+    face_geo = 8 * dim * (dim + 1) * nf
     levels = sum((dim * dim + 2) * m ** dim * 8 for m in range(n - 2, 0, -2))
     if kernel == "operator_lsrk":     # read u, du; write du, u_next
         return 4 * state + cell_geo + face_geo
@@ -422,6 +436,93 @@ def c3_plane_wave(T=0.5, ncell=48, k=7):
     return out
 
 
+def c3_bounded(steps=8, ncell=48, k=7, nsample=6):
+    """48^3 curved hexes, k = 7 (2.27e8 DoF) within a bounded time.  (i) The
+    2.4e4-cell workload's material (c = 8-mode Fourier field) and pulse:
+    ADER and LSRK(5,4) in FP64 and FP32-split over `steps` steps at 0.9 of
+    the critical Courant number (graph-replayed solve): DoF-steps/s, and the
+    FP32-split state against the FP64 one after those steps; one ADER step
+    from the pulse against the oracle on `nsample` sampled cells (the oracle
+    evaluates the Taylor sum on them and their face neighbours), both
+    precisions.  (ii) rho = c = 1, periodic plane wave: the error against the
+    closed form after `steps` steps, both schemes and precisions."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from oracle import Mesh as OMesh
+    from oracle import ader, apply_operator
+    from paper_1805_03981_amd import binding as dg
+    wl = W.c2_workload(ncell, k, 1805)
+    out = {"ncell": ncell, "k": k, "steps": steps, "courant": {s: CR[s] for s in ("ader", "lsrk")}}
+    unit = dg.FourierMaterial()
+    unit.nmodes, unit.c0, unit.amp, unit.cmin, unit.cmax, unit.rho0 = 1, 1.0, 0.0, 1.0, 1.0, 1.0
+    rng = np.random.default_rng(48)
+    om = None
+    cells = None
+    final = {}
+    for prec in ("fp64", "fp32"):
+        pid = dg.FP32_SPLIT if prec == "fp32" else dg.FP64
+        log(f"[bench] c3: {ncell}^3 k={k} {prec} mesh (Fourier material)")
+        mesh = dg.Mesh.box(3, ncell, k, 0.05, dg.fourier_material_struct(wl["material"]), precision=pid)
+        mesh.autotune(1)
+        x = mesh.get(dg.GET_NODE_COORDS)
+        U = np.ascontiguousarray(np.moveaxis(wl["ic"](x), -1, 1))
+        u0 = torch.from_numpy(U).to("cuda")[None]
+        for scheme in ("ader", "lsrk"):
+            u = u0.clone()
+            rep = mesh.solve(u, dg.ADER if scheme == "ader" else dg.LSRK54, t_end=steps * CR[scheme] * mesh.info.dt_unit,
+                             dt=CR[scheme] * mesh.info.dt_unit, use_graph=True)
+            out[f"{scheme}-{prec}"] = {"dofs": mesh.info.dofs, "steps": rep.steps, "dt": rep.dt, "wall_s": rep.wall_s,
+                                       "dof_steps_per_s": rep.dof_steps_per_s}
+            final[(scheme, prec)] = u
+            log(f"[bench] c3 {scheme}-{prec}: {out[f'{scheme}-{prec}']}")
+        # one ADER step from the pulse, sampled cells against the oracle
+        if om is None:
+            om = OMesh(3, k, W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell), wl["material"], cache=False)
+            cells = np.unique(np.concatenate([rng.choice(om.nc, nsample, replace=False), [0, om.nc - 1]]))
+            nbrs = np.unique(np.concatenate([cells, om.neighbors[cells].ravel()]))
+            dt1 = CR["ader"] * mesh.info.dt_unit
+            t0 = time.perf_counter()
+            # the oracle's own interpolant of the pulse on the cells it needs
+            Uo = np.zeros_like(U)
+            Uo[nbrs] = om.interpolate(wl["ic"], cells=nbrs)
+            I = np.zeros_like(U)
+            I[nbrs] = ader.tck(om, Uo, dt1, cells=nbrs)
+            want = Uo[cells] + apply_operator(om, I, cells=cells)
+            out["oracle_sampled_step_s"] = time.perf_counter() - t0
+        u = u0.clone()
+        mesh.step_ader(u, 0.0, dt1, 1)
+        got = u[0].cpu().numpy()[cells]
+        out[f"ader_step_vs_oracle_{prec}"] = {
+            "cells": len(cells), "rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+            "max_abs_over_max": float(np.abs(got - want).max() / np.abs(want).max())}
+        log(f"[bench] c3 ader step vs oracle {prec}: {out[f'ader_step_vs_oracle_{prec}']}")
+        del mesh, u0, u
+        torch.cuda.empty_cache()
+    for scheme in ("ader", "lsrk"):
+        out[f"fp32_vs_fp64_after_steps_{scheme}"] = rel_l2(final[(scheme, "fp32")], final[(scheme, "fp64")])
+    del final
+    torch.cuda.empty_cache()
+    for prec in ("fp64", "fp32"):
+        pid = dg.FP32_SPLIT if prec == "fp32" else dg.FP64
+        log(f"[bench] c3: {ncell}^3 k={k} {prec} mesh (rho = c = 1, plane wave)")
+        mesh = dg.Mesh.box(3, ncell, k, 0.05, unit, precision=pid)
+        x = mesh.get(dg.GET_NODE_COORDS)
+        u0 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(W.plane_wave_3d(x, 0.0), -1, 1))).to("cuda")[None]
+        for scheme in ("ader", "lsrk"):
+            u = u0.clone()
+            rep = mesh.solve(u, dg.ADER if scheme == "ader" else dg.LSRK54, t_end=steps * CR[scheme] * mesh.info.dt_unit,
+                             dt=CR[scheme] * mesh.info.dt_unit, use_graph=True)
+            T = rep.steps * rep.dt
+            ex = torch.from_numpy(np.ascontiguousarray(np.moveaxis(W.plane_wave_3d(x, T), -1, 1))).to("cuda")[None]
+            out[f"plane_wave_{scheme}-{prec}"] = {"T": T, "steps": rep.steps, "rel_l2_error_vs_closed_form": rel_l2(u, ex)}
+            log(f"[bench] c3 plane wave {scheme}-{prec}: {out[f'plane_wave_{scheme}-{prec}']}")
+            del u, ex
+        del mesh, u0
+        torch.cuda.empty_cache()
+    return out
+
+
 def ablations(steps=10, warmup=2):
     """The paper's ablations on the c2 workload, FP64: LSRK(5,4) with the
     vector update fused into the operator sweep, merged into one separate pass
@@ -599,12 +700,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 error measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
-    ap.add_argument("--no-serving", action="store_true", help="skip the small serving trace")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving trace (24 requests)")
     ap.add_argument("--serving-full", action="store_true",
-                    help="also serve 200 requests, n in [8, 48], k in 2..8, T in [0.05, 0.2] "
-                         "(about ten minutes; one line per finished request)")
-    ap.add_argument("--batched", action="store_true",
-                    help="also run the 32^3 k=5 batch of 64 point sources (500 ADER steps)")
+                    help="also serve 200 requests, n in [8, 48], k in 2..8, T in [0.1, 1] "
+                         "(about half an hour; one line per finished request)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 32^3 k=5 batch of 64 point sources (500 ADER steps)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the bounded 48^3 k=7 leg")
     ap.add_argument("--ceilings", action="store_true",
                     help="also measure copy/triad/DGEMM, LDS, vector FMA and MFMA ceilings")
     ap.add_argument("--ablations", action="store_true",
@@ -648,7 +750,10 @@ def main():
     traffic = read_traffic(dom, "hex24k5", head["precision"])
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                "algorithmic_bytes_per_launch": bytes_launch, "launch_ms": head["kernels_ms"][dom]}
+                "traffic_over_algorithmic": None if traffic is None else traffic / bytes_launch,
+                "algorithmic_bytes_per_launch": bytes_launch, "launch_ms": head["kernels_ms"][dom],
+                "launch_ms_source": "HIP events around every launch of the kernel on its stream "
+                                    "(dgw_step_profile), mean over the launches of min(steps, 20) steps"}
     kernels = {}
     for key, r in results.items():
         for kname, ms in r["kernels_ms"].items():
@@ -659,18 +764,21 @@ def main():
     if not args.no_extras and "ader-fp32" in results:
         log("[bench] FP32-split error vs FP64")
         extras["fp32_split_rel_err_5_steps"] = fp32_error()
-    if not args.no_serving:
-        log("[bench] serving trace")
-        extras["serving"] = serving()
-        log(f"[bench] serving: {extras['serving']}")
-    if args.serving_full:
-        log("[bench] full serving trace")
-        extras["serving_full"] = serving(nreq=200, seed=7, nmin=8, nmax=48, tmin=0.05, tmax=0.2, progress=True)
-        log(f"[bench] serving full: {extras['serving_full']}")
-    if args.batched:
+    if not args.no_batched:
         log("[bench] batched sources")
         extras["batched_sources"] = batched_sources()
         log(f"[bench] batched: {extras['batched_sources']}")
+    if not args.no_c3:
+        log("[bench] 48^3 k=7 bounded leg")
+        extras["c3"] = c3_bounded()
+    if not args.no_serving:
+        log("[bench] serving trace")
+        extras["serving"] = serving(nreq=24, seed=5, nmin=8, nmax=48, tmin=0.1, tmax=1.0, progress=True)
+        log(f"[bench] serving: {extras['serving']}")
+    if args.serving_full:
+        log("[bench] full serving trace")
+        extras["serving_full"] = serving(nreq=200, seed=7, nmin=8, nmax=48, tmin=0.1, tmax=1.0, progress=True)
+        log(f"[bench] serving full: {extras['serving_full']}")
     if not args.no_fixed_error:
         log("[bench] time to solution at a fixed error")
         extras["fixed_error"] = fixed_error()

@@ -292,6 +292,22 @@ dgw_status dgw_step_lsrk(dgw_mesh* mesh, int scheme, double t0, double dt, int n
 dgw_status dgw_step_ader(dgw_mesh* mesh, int flags, double t0, double dt, int nsteps, double* u,
                          double* work, int B, const dgw_sources* src, void* stream);
 
+/* dgw_step_ader without a work argument and without any device allocation,
+ * for callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same steps, kernels and
+ * results as dgw_step_ader; the work registers (I and the ping-pong state)
+ * live in a 64 MiB static device array that each device running the call
+ * holds until the process ends.  2 * B * state_bytes above 64 MiB (i.e. more
+ * than 4 Mi state values per member times B): DGW_EINVAL before any launch.
+ * Reduction periods other than the default need their reduced levels, which
+ * one dgw_step_ader call with those flags builds; until then
+ * DGW_EUNSUPPORTED.  The array is shared by every call on one device and
+ * keeps the last call's contents (nothing in it needs clearing: each step
+ * writes its registers before reading them), so calls that overlap on one
+ * device race: serialize them (one stream, or events). */
+dgw_status dgw_step_ader_noalloc(dgw_mesh* mesh, int flags, double t0, double dt, int nsteps,
+                                 double* u, int B, const dgw_sources* src, void* stream);
+
 /* Per-kernel timing of nsteps steps (the component breakdown of Sec. 4.3,
  * Table 3): like dgw_step_lsrk / dgw_step_ader, with a HIP event pair on
  * `stream` around every launch.  out->ms[i] is the mean duration of one launch

@@ -123,6 +123,7 @@ _SIGS = {
     "dgw_sources_destroy": ([_vp], None),
     "dgw_step_lsrk": ([_vp, _i, _d, _d, _i, _vp, _vp, _i, _vp, _vp], _i),
     "dgw_step_ader": ([_vp, _i, _d, _d, _i, _vp, _vp, _i, _vp, _vp], _i),
+    "dgw_step_ader_noalloc": ([_vp, _i, _d, _d, _i, _vp, _i, _vp, _vp], _i),
     "dgw_energy": ([_vp, _vp, _i, _dp, _vp], _i),
     "dgw_step_profile": ([_vp, _i, _i, _d, _d, _i, _vp, _vp, _i, _vp, _vp, C.POINTER(Profile)], _i),
     "dgw_autotune": ([_vp, _i, _vp], _i),
@@ -309,6 +310,13 @@ class Mesh:
         work = self.work(B) if work is None else work
         check(lib.dgw_step_ader(self.h, flags, t0, dt, nsteps, _tptr(u), _tptr(work), B,
                                 sources.h if sources else None, _stream(stream)), "dgw_step_ader")
+        return u
+
+    def step_ader_noalloc(self, u, t0, dt, nsteps, sources=None, B=None, flags=ADER_REDUCE, stream=None):
+        """ADER steps with the work registers in the library's static device scratch."""
+        B = B or (u.shape[0] if u.dim() == 4 else 1)
+        check(lib.dgw_step_ader_noalloc(self.h, flags, t0, dt, nsteps, _tptr(u), B,
+                                        sources.h if sources else None, _stream(stream)), "dgw_step_ader_noalloc")
         return u
 
     def profile(self, u, scheme, t0, dt, nsteps, work=None, sources=None, B=None, ader_flags=0, stream=None):

@@ -949,6 +949,70 @@ dgw_status dgw_step_ader(dgw_mesh* m, int flags, double t0, double dt, int nstep
   return DGW_OK;
 }
 
+// ------------------------------------------------------- no-alloc ADER step
+// Work registers of dgw_step_ader_noalloc (the TCK sum I and the ping-pong
+// state of every member) in a static device array: each device that runs the
+// call holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel: its device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static constexpr int64_t kNoAllocScratchBytes = int64_t(64) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / 8];
+
+static dgw_status scratch_address(int device, double** out) {
+  static std::mutex mtx;
+  static std::map<int, double*> addr;
+  std::lock_guard<std::mutex> lk(mtx);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DGW_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = addr.emplace(device, static_cast<double*>(p)).first;
+  }
+  *out = it->second;
+  return DGW_OK;
+}
+
+static bool period_levels_ready(const dgw_mesh* m, int period) {
+  for (int l = 1; l < num_levels_r(m->hs.n, period); ++l)
+    if (!level_metric(m, m->hs.n - period * l)) return false;
+  return true;
+}
+
+dgw_status dgw_step_ader_noalloc(dgw_mesh* m, int flags, double t0, double dt, int nsteps, double* u, int B,
+                                 const dgw_sources* src, void* stream) {
+  dgw_status st = check_ader_flags(flags, src);
+  if (st) return st;
+  if ((st = check_mesh(m))) return st;
+  if (!u) return fail(DGW_EINVAL, "NULL state pointer");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(DGW_EINVAL, "dt must be positive and finite");
+  if (nsteps < 0) return fail(DGW_EINVAL, "nsteps must be >= 0");
+  if ((st = check_batch(m, B, src))) return st;
+  if ((st = check_gl_basis(m, "ADER"))) return st;
+  if ((st = check_hdg_faces(m, flags))) return st;
+  const int64_t ne = state_elems(m) * B;
+  if (2 * ne * (int64_t)sizeof(double) > kNoAllocScratchBytes)
+    return fail(DGW_EINVAL, "dgw_step_ader_noalloc: 2 * B * state bytes = " +
+                                std::to_string(2 * ne * (int64_t)sizeof(double)) + " exceed the " +
+                                std::to_string(kNoAllocScratchBytes) + "-byte device scratch");
+  std::lock_guard<std::mutex> lk(m->mtx);
+  if ((st = set_device(m))) return st;
+  if (!period_levels_ready(m, ader_period(flags)))
+    return fail(DGW_EUNSUPPORTED, "the reduced levels of this reduction period are not built yet "
+                                  "(one dgw_step_ader call with these flags builds them)");
+  double* base = nullptr;
+  if ((st = scratch_address(m->device, &base))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  double* I = base;
+  double* cur = u;
+  double* oth = base + ne;
+  for (int k = 0; k < nsteps; ++k)
+    if ((st = ader_step(m, flags, B, src, t0, dt, k, nullptr, cur, oth, I, s))) return st;
+  if (cur != u) DGW_HIP(hipMemcpyAsync(u, cur, ne * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return DGW_OK;
+}
+
 dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, double dt, int nsteps, double* u,
                             double* work, int B, const dgw_sources* src, void* stream, dgw_profile* out) {
   if (!out) return fail(DGW_EINVAL, "out is NULL");

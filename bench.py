@@ -161,7 +161,8 @@ def run_variant(scheme, precision, steps, warmup):
                ms_per_step=1e3 * wall / steps, dof_steps_per_s=dofs * steps / wall,
                graph_solve_ms_per_step=1e3 * wall_graph / steps,
                kernels_ms={kname: ms for kname, (ms, _) in prof.items()},
-               launch_shape={"operator": mesh.launch_shape(0), "tck": mesh.launch_shape(1)})
+               launch_shape={"operator": mesh.launch_shape(0), "operator_lsrk": mesh.launch_shape(2),
+                             "operator_ader_update": mesh.launch_shape(3), "tck": mesh.launch_shape(1)})
     # steps to T = 0.5 at this Courant number: time to solution
     nsteps_T = int(-(-0.5 // dt))
     res["steps_to_T"] = nsteps_T
@@ -251,7 +252,10 @@ def batched_sources(B=64, steps=500, precision="fp32", ncell=32, k=5, seed=64, u
                        f"{precision}, hipGraph={bool(use_graph)}, autotuned",
            "B": B, "steps": int(rep.steps), "wall_s": rep.wall_s, "dof_steps_per_s": rep.dof_steps_per_s,
            "dofs_total": mesh.info.dofs * B, "energy_member0_end": float(e[0]),
-           "launch_shape": {"operator": mesh.launch_shape(0), "tck": mesh.launch_shape(1)}}
+           "launch_shape": {"operator": mesh.launch_shape(0), "operator_lsrk": mesh.launch_shape(2),
+                            "operator_ader_update": mesh.launch_shape(3), "tck": mesh.launch_shape(1)},
+           "members_per_workgroup": {"operator": mesh.launch_shape(4)[0], "operator_lsrk": mesh.launch_shape(5)[0],
+                                     "operator_ader_update": mesh.launch_shape(6)[0]}}
     del u, work, src, mesh
     torch.cuda.empty_cache()
     return out

@@ -332,13 +332,26 @@ dgw_status dgw_energy(dgw_mesh* mesh, const double* u, int B, double* host_out, 
 
 /* Launch shape of the operator (which = 0) or TCK (which = 1) kernels:
  * cells per workgroup and threads per workgroup.  A positive cells_per_group
- * selects one of the two compiled shapes (the LDS tile must fit 160 KiB);
- * threads are fixed by the kernel and the cell size (256; the operator
- * 1024 for 9^3 points, the TCK 512 for 8^3 and 1024 for 9^3): a positive
- * input must equal that.  The current shape is
- * returned.  dgw_autotune times the candidates on scratch buffers
- * for batch size B and keeps the fastest (cached per dim, k, precision, B,
- * mesh size). */
+ * selects one of the two compiled shapes (the LDS tile must fit 160 KiB) for
+ * the TCK, or for the operator with every epilogue; threads are fixed by the
+ * kernel and the cell size (256; the operator 1024 for 9^3 points, the TCK
+ * 512 for 8^3 and 1024 for 9^3): a positive input must equal that.  The
+ * current shape is returned (for which = 0 the one of the plain operator);
+ * which = 2 and 3 report the shape of the operator with the LSRK and with
+ * the ADER update epilogue, which = 4, 5, 6 the batch members one workgroup
+ * of the operator with the store, LSRK and ADER update epilogue processes (1,
+ * or 8 for the member-block variant that loads a cell's geometry once for 8
+ * members; 3D only) in cells_per_group (input cells_per_group must be 0).
+ * dgw_autotune times the compiled shapes of the operator with each of its
+ * epilogues (and, for B > 1 in 3D, the member-block variant of each) and of
+ * the TCK on scratch buffers for batch size B and keeps
+ * the fastest of each (per process, keyed by device architecture, d, k,
+ * precision, storage basis, B and cell count).  When the environment
+ * variable DGW_AUTOTUNE_CACHE names a file, results are looked up there
+ * first and appended there as JSON lines
+ * ({"key": ..., "op_store": s, "op_lsrk": s, "op_ader_update": s, "tck": 0|1, "ms": {...}},
+ * s = 0..3: bit 0 the cells-per-workgroup choice, bit 1 the member block);
+ * entries that no longer fit the LDS are ignored. */
 dgw_status dgw_launch_shape(dgw_mesh* mesh, int which, int* cells_per_group, int* threads);
 dgw_status dgw_autotune(dgw_mesh* mesh, int B, void* stream);
 

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -249,14 +250,22 @@ static dgw_status check_gl_basis(const dgw_mesh* m, const char* what) {
 
 // The operator launcher for epilogue epi and launch shape sel in the mesh's
 // storage basis (only EPI_STORE and EPI_LSRK exist for the Gauss basis).
-static OpLaunch op_launch(const dgw_mesh* m, int epi, int sel) {
+// Operator launch shape index: bit 0 selects the compiled cells per
+// workgroup, bit 1 the member-block variant (kMemberBlock batch members per
+// workgroup with the geometry loaded once) instead of one member per group.
+static OpLaunch op_launch(const dgw_mesh* m, int epi, int shape) {
+  const int sel = shape & 1;
+  if (shape & 2) return m->basis == DGW_BASIS_GAUSS ? nullptr : m->L->op_mb[epi][sel];
   return m->basis == DGW_BASIS_GAUSS ? m->L->op_gauss[epi][sel] : m->L->op[epi][sel];
 }
 
 // One operator launch; on a mesh with prescribed faces the exterior state
 // of this launch (at p.time, or integrated over the step for the ADER
 // update) is evaluated first on the same stream.
-static hipError_t run_op(const dgw_mesh* m, int epi, int sel, const OpParams& p, hipStream_t s) {
+static hipError_t run_op(const dgw_mesh* m, int epi, int sel, OpParams p, hipStream_t s) {
+  if ((sel & 2) && (p.B == 1 || !op_launch(m, epi, sel))) sel &= 1;  // one member: the plain kernel
+  p.cpw = m->L->cpw[sel & 1];
+  p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
   if (m->d_ext) {
     ExteriorParams q;
     std::memset(&q, 0, sizeof(q));
@@ -275,6 +284,16 @@ static hipError_t run_op(const dgw_mesh* m, int epi, int sel, const OpParams& p,
     if (e != hipSuccess) return e;
   }
   return op_launch(m, epi, sel)(p, s);
+}
+
+// Launch shape of the operator with epilogue epi: the one tuned for that
+// epilogue, else the mesh's operator shape.
+static int op_sel(const dgw_mesh* m, int epi) {
+  const int s = m->op_sel_epi[epi];
+  return s >= 0 ? s : m->op_shape.sel;
+}
+static hipError_t run_op(const dgw_mesh* m, int epi, const OpParams& p, hipStream_t s) {
+  return run_op(m, epi, op_sel(m, epi), p, s);
 }
 
 static dgw_status set_device(const dgw_mesh* m) {
@@ -377,7 +396,7 @@ static dgw_status lsrk_step(dgw_mesh* m, int B, const dgw_sources* src, double t
     p.u = cur;
     p.u_next = oth;
     set_lsrk_stage(p, scheme, i, dt);
-    DGW_HIP(run_op(m, EPI_LSRK, m->op_shape.sel, p, s));
+    DGW_HIP(run_op(m, EPI_LSRK, p, s));
     std::swap(cur, oth);
   }
   return DGW_OK;
@@ -490,7 +509,7 @@ static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* sr
     OpParams w = op_params(m, B, nullptr);
     w.u = cur;
     w.out = I;
-    DGW_HIP(run_op(m, EPI_STORE, m->op_shape.sel, w, s));
+    DGW_HIP(run_op(m, EPI_STORE, w, s));
     tp.u = I;
     tp.u_base = cur;
     DGW_HIP(m->L->tck_hdg[sel](tp, s));
@@ -502,7 +521,7 @@ static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* sr
   p.u_base = cur;
   p.u_next = oth;
   p.time = StepTime{ctr, t0, dt, step_add, 0.0};
-  DGW_HIP(run_op(m, EPI_ADD, m->op_shape.sel, p, s));
+  DGW_HIP(run_op(m, EPI_ADD, p, s));
   std::swap(cur, oth);
   return DGW_OK;
 }
@@ -529,35 +548,128 @@ static dgw_status energy_impl(dgw_mesh* m, const double* u, int B, double* host_
   return DGW_OK;
 }
 
-// Times the candidate launch shapes of the operator and TCK kernels on
-// scratch buffers and keeps the fastest (Sec. 4.4's throughput depends on how
-// many cells share a workgroup; the best choice depends on k, d, precision).
+// Autotuner of the launch shapes (cells per workgroup) of the operator, per
+// epilogue, and of the TCK: each compiled candidate that fits the LDS is
+// timed on scratch buffers of the mesh's size and batch, and the fastest is
+// kept (the paper's throughput depends on how many cells are processed
+// together, Sec. 4.4; the best choice here depends on k, d, precision, the
+// epilogue's register use and the batch).  Results are kept per process and,
+// when the environment variable DGW_AUTOTUNE_CACHE names a file, in that file
+// as JSON lines keyed by device architecture, d, k, precision, storage basis,
+// batch size and cell count, so that later processes skip the timing.
+namespace {
+struct TuneResult {
+  int op[3] = {0, 0, 0};  // store, LSRK, ADER update
+  int tck = 0;
+};
+
+std::string tune_key(const dgw_mesh* m, int B) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, m->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+  }
+  return arch + "|d" + std::to_string(m->hs.dim) + "|k" + std::to_string(m->hs.k) +
+         (m->precision == DGW_FP32_SPLIT ? "|fp32" : "|fp64") + (m->basis == DGW_BASIS_GAUSS ? "|gauss" : "|gl") +
+         "|B" + std::to_string(B) + "|nc" + std::to_string(m->hs.nc);
+}
+
+// integer field `name` of one JSON line, -1 if absent
+int json_int(const std::string& line, const char* name) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t at = line.find(pat);
+  if (at == std::string::npos) return -1;
+  return std::atoi(line.c_str() + at + pat.size());
+}
+
+bool cache_file_lookup(const std::string& key, TuneResult& r) {
+  const char* path = std::getenv("DGW_AUTOTUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char buf[1024];
+  bool found = false;
+  const std::string kpat = "\"key\":\"" + key + "\"";
+  while (std::fgets(buf, sizeof(buf), f)) {
+    std::string line;
+    for (const char* c = buf; *c; ++c)  // keys and values hold no blanks: drop them all
+      if (*c != ' ' && *c != '\t') line += *c;
+    if (line.find(kpat) == std::string::npos) continue;
+    const int v[4] = {json_int(line, "op_store"), json_int(line, "op_lsrk"), json_int(line, "op_ader_update"),
+                      json_int(line, "tck")};
+    if (v[0] < 0 || v[0] > 3 || v[1] < 0 || v[1] > 3 || v[2] < 0 || v[2] > 3 || v[3] < 0 || v[3] > 1) continue;
+    r.op[0] = v[0];
+    r.op[1] = v[1];
+    r.op[2] = v[2];
+    r.tck = v[3];
+    found = true;  // the last matching line wins
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_file_append(const std::string& key, const TuneResult& r, float (&ms)[4][4]) {
+  const char* path = std::getenv("DGW_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  for (auto& row : ms)
+    for (float& t : row)
+      if (t >= 1e29f) t = -1.0f;  // not timed (does not fit, or no such variant)
+  static std::mutex file_mtx;
+  std::lock_guard<std::mutex> lk(file_mtx);
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f,
+               "{\"key\":\"%s\",\"op_store\":%d,\"op_lsrk\":%d,\"op_ader_update\":%d,\"tck\":%d,"
+               "\"ms\":{\"op_store\":[%.4f,%.4f,%.4f,%.4f],\"op_lsrk\":[%.4f,%.4f,%.4f,%.4f],"
+               "\"op_ader_update\":[%.4f,%.4f,%.4f,%.4f],\"tck\":[%.4f,%.4f]}}\n",
+               key.c_str(), r.op[0], r.op[1], r.op[2], r.tck, ms[0][0], ms[0][1], ms[0][2], ms[0][3], ms[1][0],
+               ms[1][1], ms[1][2], ms[1][3], ms[2][0], ms[2][1], ms[2][2], ms[2][3], ms[3][0], ms[3][1]);
+  std::fclose(f);
+}
+
+void apply_tuning(dgw_mesh* m, const TuneResult& r) {
+  for (int e = 0; e < 3; ++e) m->op_sel_epi[e] = r.op[e];
+  m->op_shape.sel = r.op[EPI_STORE] & 1;
+  m->tck_shape.sel = r.tck;
+  m->tuned = true;
+}
+}  // namespace
+
 static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
   static std::mutex cache_mtx;
-  static std::map<std::tuple<int, int, int, int, int64_t>, std::pair<LaunchShape, LaunchShape>> cache;
-  const auto key = std::make_tuple(m->hs.dim, m->hs.k, m->precision, B, m->hs.nc);
+  static std::map<std::string, TuneResult> cache;
+  const std::string key = tune_key(m, B);
   {
     std::lock_guard<std::mutex> lk(cache_mtx);
     auto it = cache.find(key);
-    if (it != cache.end()) {
-      m->op_shape = it->second.first;
-      m->tck_shape = it->second.second;
-      m->tuned = true;
-      return DGW_OK;
+    TuneResult r;
+    if (it != cache.end() || cache_file_lookup(key, r)) {
+      if (it != cache.end()) r = it->second;
+      bool fits = (int64_t)m->L->cpw[r.tck] * m->L->tck_lds_per_cell[2] <= kLdsLimit;
+      for (int e = 0; e < 3; ++e)
+        fits = fits && (int64_t)m->L->cpw[r.op[e] & 1] * m->L->op_lds_per_cell <= kLdsLimit &&
+               op_launch(m, e, r.op[e]) != nullptr;
+      if (fits) {
+        cache[key] = r;
+        apply_tuning(m, r);
+        return DGW_OK;
+      }
     }
   }
   const int64_t ne = state_elems(m) * B;
-  double *a = nullptr, *b = nullptr;
-  DGW_HIP(hipMalloc(&a, ne * sizeof(double)));
-  if (hipMalloc(&b, ne * sizeof(double)) != hipSuccess) {
-    (void)hipFree(a);
-    return fail(DGW_ENOMEM, "autotune scratch");
-  }
-  DGW_HIP(hipMemsetAsync(a, 0, ne * sizeof(double), s));
+  double* buf[3] = {nullptr, nullptr, nullptr};
+  for (auto*& b : buf)
+    if (hipMalloc(&b, ne * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      for (auto* q : buf) (void)hipFree(q);
+      return fail(DGW_ENOMEM, "autotune scratch");
+    }
+  for (auto* b : buf) DGW_HIP(hipMemsetAsync(b, 0, ne * sizeof(double), s));
   hipEvent_t e0, e1;
   DGW_HIP(hipEventCreate(&e0));
   DGW_HIP(hipEventCreate(&e1));
-  const int64_t lds_limit = kLdsLimit;
   auto time_it = [&](auto&& launch) -> float {
     for (int w = 0; w < 2; ++w)
       if (launch() != hipSuccess) return 1e30f;
@@ -567,48 +679,58 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
     (void)hipEventSynchronize(e1);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    return ms;
+    return ms / 5;
   };
-  LaunchShape best_op = m->op_shape, best_tck = m->tck_shape;
-  float t_op = 1e30f, t_tck = 1e30f;
-  for (int sel = 0; sel < 2; ++sel) {
-    const int cpw = m->L->cpw[sel];
-    if ((int64_t)cpw * m->L->op_lds_per_cell <= lds_limit) {
-      OpParams p = op_params(m, B, nullptr);
-      p.cpw = cpw;
-      p.groups = (int)((m->hs.nc + cpw - 1) / cpw);
-      p.u = a;
-      p.out = b;
-      const float t = time_it([&]() { return run_op(m, EPI_STORE, sel, p, s); });
-      if (t < t_op) {
-        t_op = t;
-        best_op.sel = sel;
+  float ms[4][4] = {{1e30f, 1e30f, 1e30f, 1e30f}, {1e30f, 1e30f, 1e30f, 1e30f}, {1e30f, 1e30f, 1e30f, 1e30f},
+                    {1e30f, 1e30f, 1e30f, 1e30f}};
+  const bool gauss = m->basis == DGW_BASIS_GAUSS;
+  const int nshape = B > 1 && !gauss ? 4 : 2;  // member blocks only pay with more than one member
+  for (int shape = 0; shape < nshape; ++shape) {
+    const int sel = shape & 1;
+    if ((int64_t)m->L->cpw[sel] * m->L->op_lds_per_cell <= kLdsLimit) {
+      for (int epi = 0; epi < (gauss ? 2 : 3); ++epi) {
+        if (!op_launch(m, epi, shape)) continue;
+        OpParams p = op_params(m, B, nullptr);
+        p.u = buf[0];
+        if (epi == EPI_STORE) {
+          p.out = buf[1];
+        } else if (epi == EPI_LSRK) {
+          p.du = buf[2];
+          p.u_next = buf[1];
+          p.dt = 1e-3;
+          set_lsrk_stage(p, DGW_SCHEME_LSRK54, 1, 1e-3);  // a stage that reads du
+        } else {
+          p.u_base = buf[2];
+          p.u_next = buf[1];
+          p.dt = 1e-3;
+        }
+        ms[epi][shape] = time_it([&]() { return run_op(m, epi, shape, p, s); });
       }
     }
-    if ((int64_t)cpw * m->L->tck_lds_per_cell[2] <= lds_limit) {
+    if (shape < 2 && !gauss && (int64_t)m->L->cpw[sel] * m->L->tck_lds_per_cell[2] <= kLdsLimit) {
       TckParams p = tck_params(m, B, nullptr);
-      p.cpw = cpw;
-      p.groups = (int)((m->hs.nc + cpw - 1) / cpw);
-      p.u = a;
-      p.I = b;
+      p.cpw = m->L->cpw[sel];
+      p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
+      p.u = buf[0];
+      p.I = buf[1];
       p.dt = 1e-3;
-      const float t = time_it([&]() { return m->L->tck[2][sel](p, s); });
-      if (t < t_tck) {
-        t_tck = t;
-        best_tck.sel = sel;
-      }
+      ms[3][sel] = time_it([&]() { return m->L->tck[2][sel](p, s); });
     }
   }
   (void)hipGetLastError();
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipFree(a);
-  (void)hipFree(b);
-  m->op_shape = best_op;
-  m->tck_shape = best_tck;
-  m->tuned = true;
+  for (auto* b : buf) (void)hipFree(b);
+  TuneResult r;
+  for (int e = 0; e < 3; ++e)
+    for (int sh = 1; sh < 4; ++sh)
+      if (ms[e][sh] < ms[e][r.op[e]]) r.op[e] = sh;
+  if (gauss) r.op[EPI_ADD] = r.op[EPI_STORE];
+  r.tck = ms[3][1] < ms[3][0] ? 1 : 0;
+  apply_tuning(m, r);
   std::lock_guard<std::mutex> lk(cache_mtx);
-  cache[key] = {best_op, best_tck};
+  cache[key] = r;
+  cache_file_append(key, r, ms);
   return DGW_OK;
 }
 
@@ -873,7 +995,7 @@ dgw_status dgw_operator_apply(dgw_mesh* m, const double* u, double* out, int B, 
   OpParams p = op_params(m, B, nullptr);
   p.u = u;
   p.out = out;
-  DGW_HIP(run_op(m, EPI_STORE, m->op_shape.sel, p, (hipStream_t)stream));
+  DGW_HIP(run_op(m, EPI_STORE, p, (hipStream_t)stream));
   return DGW_OK;
 }
 
@@ -915,7 +1037,7 @@ dgw_status dgw_step_lsrk(dgw_mesh* m, int scheme, double t0, double dt, int nste
     for (int k = 0; k < nsteps; ++k)
       for (int i = 0; i < 5; ++i) {
         p.time = StepTime{nullptr, t0, dt, k, kLsrk.C[i] * dt};  // prescribed data at the stage time
-        DGW_HIP(run_op(m, EPI_STORE, m->op_shape.sel, p, s));
+        DGW_HIP(run_op(m, EPI_STORE, p, s));
         if ((st = lsrk_vector_update(scheme, i, dt, u, du, r, state_elems(m) * B, s))) return st;
       }
     return DGW_OK;
@@ -1064,7 +1186,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
       for (int i = 0; i < 5 && !st; ++i) {
         p.time = StepTime{nullptr, t0, dt, k, kLsrk.C[i] * dt};
         st = timed(0, [&]() -> dgw_status {
-          DGW_HIP(run_op(m, EPI_STORE, m->op_shape.sel, p, s));
+          DGW_HIP(run_op(m, EPI_STORE, p, s));
           return DGW_OK;
         });
         if (!st) st = timed(1, [&] { return lsrk_vector_update(scheme, i, dt, u, aux, oth, state_elems(m) * B, s); });
@@ -1079,7 +1201,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
         p.u_next = oth;
         set_lsrk_stage(p, scheme, i, dt);
         st = timed(0, [&]() -> dgw_status {
-          DGW_HIP(run_op(m, EPI_LSRK, m->op_shape.sel, p, s));
+          DGW_HIP(run_op(m, EPI_LSRK, p, s));
           return DGW_OK;
         });
         std::swap(cur, oth);
@@ -1099,7 +1221,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
         w.u = cur;
         w.out = aux;
         st = timed(2, [&]() -> dgw_status {
-          DGW_HIP(run_op(m, EPI_STORE, m->op_shape.sel, w, s));
+          DGW_HIP(run_op(m, EPI_STORE, w, s));
           return DGW_OK;
         });
         tp.u = aux;
@@ -1120,7 +1242,7 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
       p.time = StepTime{nullptr, t0, dt, k, 0.0};
       if (!st)
         st = timed(1, [&]() -> dgw_status {
-          DGW_HIP(run_op(m, EPI_ADD, m->op_shape.sel, p, s));
+          DGW_HIP(run_op(m, EPI_ADD, p, s));
           return DGW_OK;
         });
       std::swap(cur, oth);
@@ -1154,7 +1276,19 @@ dgw_status dgw_autotune(dgw_mesh* m, int B, void* stream) {
 }
 
 dgw_status dgw_launch_shape(dgw_mesh* m, int which, int* cells_per_group, int* threads) {
-  if (!m || !cells_per_group || !threads || (which != 0 && which != 1)) return fail(DGW_EINVAL, "bad argument");
+  if (!m || !cells_per_group || !threads || which < 0 || which > 6) return fail(DGW_EINVAL, "bad argument");
+  if (which >= 4) {  // batch members per workgroup of the store (4), LSRK (5), ADER update (6) operator
+    if (*cells_per_group > 0) return fail(DGW_EINVAL, "which = 4..6 only report a member count");
+    *cells_per_group = (op_sel(m, which - 4) & 2) ? kMemberBlock : 1;
+    *threads = op_threads(m->hs.dim, m->hs.n);
+    return DGW_OK;
+  }
+  if (which >= 2) {  // read the shape of the LSRK (2) or ADER update (3) epilogue
+    if (*cells_per_group > 0) return fail(DGW_EINVAL, "which = 2, 3 only report a shape");
+    *cells_per_group = m->L->cpw[op_sel(m, which == 2 ? EPI_LSRK : EPI_ADD) & 1];
+    *threads = op_threads(m->hs.dim, m->hs.n);
+    return DGW_OK;
+  }
   LaunchShape& sh = which == 0 ? m->op_shape : m->tck_shape;
   if (*cells_per_group > 0) {
     const int per_cell = which == 0 ? m->L->op_lds_per_cell : m->L->tck_lds_per_cell[2];
@@ -1167,6 +1301,8 @@ dgw_status dgw_launch_shape(dgw_mesh* m, int which, int* cells_per_group, int* t
                                   ", " + std::to_string(m->L->cpw[1]) + ") and fit the LDS; threads must be " +
                                   std::to_string(nt));
     sh.sel = sel;
+    if (which == 0)
+      for (int e = 0; e < 3; ++e) m->op_sel_epi[e] = -1;  // every epilogue takes this shape
   }
   *cells_per_group = m->L->cpw[sh.sel];
   *threads = which == 0 ? op_threads(m->hs.dim, m->hs.n) : tck_threads(m->hs.dim, m->hs.n);

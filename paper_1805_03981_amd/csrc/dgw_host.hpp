@@ -96,6 +96,7 @@ struct dgw_mesh {
   double* d_partial = nullptr;  // energy partial sums [max_batch][groups]
   int64_t device_bytes = 0;
   dgw::LaunchShape op_shape, tck_shape;
+  int op_sel_epi[3] = {-1, -1, -1};  // per operator epilogue (store, LSRK, ADER update); -1: op_shape
   bool tuned = false;
   std::mutex mtx;
 };

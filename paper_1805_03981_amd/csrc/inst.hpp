@@ -14,15 +14,27 @@ static hipError_t ensure_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int D, int N, typename T, int EPI, int SEL, bool GB = false>
+template <int D, int N, typename T, int EPI, int SEL, bool GB = false, int MB = 1>
 hipError_t launch_op(const OpParams& p, hipStream_t s) {
   constexpr int CPW = cells_per_group(D, N, SEL);
   if (p.cpw != CPW) return hipErrorInvalidValue;
   const size_t lds = (size_t)CPW * OpLayout<D, N, T>::per_cell * sizeof(T);
-  hipError_t e = ensure_lds(op_kernel<D, N, T, EPI, CPW, GB>, lds);
+  hipError_t e = ensure_lds(op_kernel<D, N, T, EPI, CPW, GB, MB>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((op_kernel<D, N, T, EPI, CPW, GB>), dim3(p.groups * p.B), dim3(op_threads(D, N)), lds, s, p);
+  const int nmb = (p.B + MB - 1) / MB;
+  hipLaunchKernelGGL((op_kernel<D, N, T, EPI, CPW, GB, MB>), dim3(p.groups * nmb), dim3(op_threads(D, N)), lds, s,
+                     p);
   return hipGetLastError();
+}
+
+// Member-block launchers (kMemberBlock batch members per workgroup, the
+// geometry loaded once): 3D, GL storage basis only.
+template <int D, int N, typename T, int EPI, int SEL>
+constexpr OpLaunch member_block_op() {
+  if constexpr (D == 3)
+    return launch_op<D, N, T, EPI, SEL, false, kMemberBlock>;
+  else
+    return nullptr;
 }
 
 // Gauss storage basis launchers: FP64 arithmetic only.
@@ -62,6 +74,9 @@ const Launchers* make_launchers() {
        {launch_op<D, N, T, EPI_ADD, 0>, launch_op<D, N, T, EPI_ADD, 1>}},
       {{gauss_op<D, N, T, EPI_STORE, 0>(), gauss_op<D, N, T, EPI_STORE, 1>()},
        {gauss_op<D, N, T, EPI_LSRK, 0>(), gauss_op<D, N, T, EPI_LSRK, 1>()}},
+      {{member_block_op<D, N, T, EPI_STORE, 0>(), member_block_op<D, N, T, EPI_STORE, 1>()},
+       {member_block_op<D, N, T, EPI_LSRK, 0>(), member_block_op<D, N, T, EPI_LSRK, 1>()},
+       {member_block_op<D, N, T, EPI_ADD, 0>(), member_block_op<D, N, T, EPI_ADD, 1>()}},
       {{launch_tck<D, N, T, 0, 0>, launch_tck<D, N, T, 0, 1>},
        {launch_tck<D, N, T, 1, 0>, launch_tck<D, N, T, 1, 1>},
        {launch_tck<D, N, T, 2, 0>, launch_tck<D, N, T, 2, 1>},

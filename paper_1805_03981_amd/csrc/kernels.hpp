@@ -213,10 +213,14 @@ struct OpLayout {
 // for the TCK below: with one cell point per thread of a 256-thread group,
 // compiled for the waves per SIMD its LDS allows (at most 5); measured 7 %
 // faster at k = 5.  The LSRK and ADER epilogues keep their state operands
-// in registers across the sweep and would spill under that budget.
-template <int D, int N, typename T, int EPI, int CPW>
+// in registers across the sweep and would spill under that budget, and so
+// would the member-block variant (MB > 1), whose geometry registers stay
+// live across its loop over members (measured on the 64-source batch at
+// k = 5 FP32: capped at 5 waves it spills and runs 1.7x slower than one
+// member per workgroup).
+template <int D, int N, typename T, int EPI, int CPW, int MB = 1>
 constexpr int op_waves_per_simd() {
-  if (EPI != EPI_STORE || op_threads(D, N) != 256 || cdiv(CPW * ipow(N, D), 256) > 1) return 1;
+  if (EPI != EPI_STORE || MB != 1 || op_threads(D, N) != 256 || cdiv(CPW * ipow(N, D), 256) > 1) return 1;
   const int wg = (160 * 1024) / (CPW * OpLayout<D, N, T>::per_cell * (int)sizeof(T));
   return wg < 1 ? 1 : (wg > 5 ? 5 : wg);
 }
@@ -319,9 +323,9 @@ __device__ __forceinline__ void op_points(const double (&g)[PS][D * D + 2], cons
 // the Gauss basis and back), true = Lagrange polynomials in the Gauss points
 // (the collocated basis of Sec. 3.1: no basis change, diagonal mass, but a
 // neighbour's trace needs its whole line of values along the face normal).
-template <int D, int N, typename T, int EPI, int CPW, bool GB = false>
+template <int D, int N, typename T, int EPI, int CPW, bool GB = false, int MB = 1>
 __global__ void __launch_bounds__(op_threads(D, N))
-__attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_kernel(OpParams p) {
+__attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>()))) op_kernel(OpParams p) {
   using Lay = OpLayout<D, N, T>;
   constexpr int NC = Lay::NC, NP = Lay::NP, NF = Lay::NF, NFACE = Lay::NFACE, G2 = D * D + 2;
   constexpr int NT = op_threads(D, N);
@@ -337,16 +341,21 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
   const T* tab = ctab<T>(N);
   const int tid = threadIdx.x;
 
+  // workgroup -> (cell group, block of MB batch members): the cell geometry
+  // is loaded once into registers and applied to each member of the block in
+  // turn (members share mesh, geometry and material); MB = 1 makes the batch
+  // a plain grid dimension
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int member = logical % p.B;
-  const int group = logical / p.B;
+  const int nmb = (p.B + MB - 1) / MB;
+  const int mblock = logical % nmb;
+  const int group = logical / nmb;
   const int64_t cell0 = (int64_t)group * CPW;
   const int ncl = (int)min((int64_t)CPW, p.nc - cell0);
-  const int64_t moff = (int64_t)member * p.nc * NC * NP;
-  const int64_t gofs = moff + cell0 * NC * NP;
   const int nel = ncl * NC * NP;
 
-  // ---- A: all global operands, in dependency order
+  // ---- A: all global operands, in dependency order: the neighbour table
+  // and the geometry once, then per member its state, the neighbours' face
+  // nodes and the epilogue operands
   int nbi[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
@@ -355,51 +364,6 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
     if (i < ncl * NFACE * NC * NF) {
       const int cf = i / (NC * NF);  // c * NFACE + f
       nbi[s] = p.nb[cell0 * NFACE + cf];
-    }
-  }
-  double ev[ES];
-#pragma unroll
-  for (int s = 0; s < ES; ++s) {
-    const int i = tid + s * NT;
-    ev[s] = i < nel ? p.u[gofs + i] : 0.0;
-  }
-  double nv[NS];
-  double glf0[GB ? N : 1], glf1[GB ? N : 1];  // Gauss basis: face values of the 1D Lagrange polynomials
-  if constexpr (GB) {
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      glf0[j] = (double)tab[tab_LF0(N) + j];
-      glf1[j] = (double)tab[tab_LF1(N) + j];
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int i = tid + s * NT;
-    nv[s] = 0.0;
-    if (i < ncl * NFACE * NC * NF && nbi[s] >= 0) {  // boundary faces: exterior state built in F
-      const int t = i % NF;
-      const int r = i / NF;
-      const int v = r % NC;
-      const int cf = r / NC;  // c * NFACE + f
-      // GL node of the neighbour's face f' that meets own tangential index t:
-      // f' = f^1 with aligned coordinates unless the mesh gives orientations
-      int fn = (cf % NFACE) ^ 1, tn = t;
-      if (p.fo) {
-        const int code = p.fo[cell0 * NFACE + cf];
-        fn = code >> 3;
-        tn = orient_face<D, N>(code & 7, t);
-      }
-      const int dir = fn >> 1, side = fn & 1;
-      const double* un = p.u + moff + (int64_t)nbi[s] * NC * NP + v * NP;
-      if constexpr (GB) {  // interpolate the neighbour's normal line to its face
-        const int q0 = face_line_base<D, N>(dir, tn), st = dir_stride(N, dir);
-        double acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) acc = fma(side ? glf1[j] : glf0[j], un[q0 + j * st], acc);
-        nv[s] = acc;
-      } else {
-        nv[s] = un[face_line_base<D, N>(dir, tn) + (side ? (N - 1) * dir_stride(N, dir) : 0)];
-      }
     }
   }
   double g[PS][G2];
@@ -427,206 +391,258 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW>()))) op_
 #pragma unroll
     for (int e = 0; e < D + 2; ++e) fg[s][e] = i < ncl * NFACE * NF ? fp[e * NF] : 1.0;
   }
-  double eb[ES];
-#pragma unroll
-  for (int s = 0; s < ES; ++s) {
-    const int i = tid + s * NT;
-    eb[s] = 0.0;
-    if constexpr (EPI == EPI_ADD)
-      if (i < nel) eb[s] = p.u_base[gofs + i];
-    if constexpr (EPI == EPI_LSRK)
-      if (i < nel && (p.two_r ? !p.first : p.acoef != 0.0)) eb[s] = p.du[gofs + i];
-  }
-#pragma unroll
-  for (int s = 0; s < ES; ++s) {
-    const int i = tid + s * NT;
-    if (i < nel) sU[i] = (T)ev[s];
-  }
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int i = tid + s * NT;
-    if (i < ncl * NFACE * NC * NF) sN[i] = (T)nv[s];
-  }
-  __syncthreads();
-
-  // ---- B: GL -> G of the cell tiles; tangential GL -> G of the neighbour traces
-  if constexpr (!GB) {
-    const T* S = tab + tab_S(N);
-    tpass<NT, D, 0, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
-    if constexpr (D == 2) tpass<NT, 1, 0, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
-    if constexpr (D == 3) tpass<NT, 2, 0, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
-    __syncthreads();
-    tpass<NT, D, 1, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
-    if constexpr (D == 3) tpass<NT, 2, 1, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
-    __syncthreads();
-    if constexpr (D == 3) {
-      tpass<NT, D, 2, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
-      __syncthreads();
-    }
-  }
-  // ---- F: numerical fluxes at every face point, written over the neighbour traces
-  {
-    T lf0[N], lf1[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      lf0[j] = tab[tab_LF0(N) + j];
-      lf1[j] = tab[tab_LF1(N) + j];
-    }
-#pragma unroll
-    for (int s = 0; s < FS; ++s) {
-      const int i = tid + s * NT;
-      if (i < ncl * NFACE * NF) {
-        const int cf = i / NF, t = i - (i / NF) * NF;
-        const int c = cf / NFACE, f = cf - c * NFACE;
-        const int dir = f >> 1, side = f & 1;
-        const int st = dir_stride(N, dir);
-        const T* su = sU + c * NC * NP + face_line_base<D, N>(dir, t);
-        double um[NC], up[NC];
-#pragma unroll
-        for (int v = 0; v < NC; ++v) {
-          T acc = 0;
-#pragma unroll
-          for (int j = 0; j < N; ++j) acc = fma(side ? lf1[j] : lf0[j], su[v * NP + j * st], acc);
-          um[v] = (double)acc;
-          up[v] = (double)sN[(cf * NC + v) * NF + t];
-        }
-        double area2 = 0.0, vnm = 0.0, vnp = 0.0;
-#pragma unroll
-        for (int e = 0; e < D; ++e) {
-          area2 = fma(fg[s][e], fg[s][e], area2);
-          vnm = fma(fg[s][e], um[e], vnm);
-          vnp = fma(fg[s][e], up[e], vnp);
-        }
-        const double area = sqrt(area2), inv_area = 1.0 / area;
-        vnm *= inv_area;
-        vnp *= inv_area;
-        double pp = up[D];
-        if (fnb[s] < 0) {  // boundary: mirror state (wall), else zero state (absorbing;
-                           // prescribed data are added below)
-          pp = fnb[s] == kBcWall ? um[D] : 0.0;
-          vnp = fnb[s] == kBcWall ? -vnm : 0.0;
-        }
-        double ps, vs;
-        if (p.central) {
-          ps = 0.5 * (um[D] + pp);
-          vs = 0.5 * (vnm + vnp);
-        } else {
-          const double Zm = fg[s][D], Zp = fg[s][D + 1];
-          const double inv = 1.0 / (Zm + Zp);
-          ps = (Zp * um[D] + Zm * pp + Zm * Zp * (vnm - vnp)) * inv;
-          vs = (Zm * vnm + Zp * vnp + um[D] - pp) * inv;
-        }
-#pragma unroll
-        for (int e = 0; e < D; ++e) sN[(cf * NC + e) * NF + t] = (T)(-fg[s][e] * ps);
-        sN[(cf * NC + D) * NF + t] = (T)(-area * vs);
-      }
-    }
-    // Prescribed faces (device neighbour entry kBcPrescribed - slot): both
-    // fluxes are linear in the exterior state, so the flux of the given data
-    // (p+, v+.n, evaluated for this launch into ext[slot][2][NF]) is added to
-    // the zero-state flux written above.  Same thread as above for each face
-    // point; operands re-read from memory so that this rare path takes no
-    // registers from the loop above.
-    if (p.ext) {
 #pragma unroll 1
-      for (int i = tid; i < ncl * NFACE * NF; i += NT) {
-        const int cf = i / NF, t = i - (i / NF) * NF;
-        const int code = p.nb[cell0 * NFACE + cf];
-        if (code > kBcPrescribed) continue;
-        const double* ex = p.ext + (int64_t)(kBcPrescribed - code) * 2 * NF + t;
-        const double pe = ex[0], vne = ex[NF];
-        const double* fp = p.geo_face + (cell0 * NFACE + cf) * (int64_t)((D + 2) * NF) + t;
-        double area2 = 0.0;
+  for (int mm = 0; mm < MB; ++mm) {
+    const int member = mblock * MB + mm;
+    if (MB > 1 && member >= p.B) break;
+    const int64_t moff = (int64_t)member * p.nc * NC * NP;
+    const int64_t gofs = moff + cell0 * NC * NP;
+    double ev[ES];
 #pragma unroll
-        for (int e = 0; e < D; ++e) area2 = fma(fp[e * NF], fp[e * NF], area2);
-        double dps, dvs;
-        if (p.central) {
-          dps = 0.5 * pe;
-          dvs = 0.5 * vne;
-        } else {
-          const double Zm = fp[D * NF], Zp = fp[(D + 1) * NF];
-          const double inv = 1.0 / (Zm + Zp);
-          dps = (Zm * pe - Zm * Zp * vne) * inv;
-          dvs = (Zp * vne - pe) * inv;
-        }
+    for (int s = 0; s < ES; ++s) {
+      const int i = tid + s * NT;
+      ev[s] = i < nel ? p.u[gofs + i] : 0.0;
+    }
+    double nv[NS];
+    double glf0[GB ? N : 1], glf1[GB ? N : 1];  // Gauss basis: face values of the 1D Lagrange polynomials
+    if constexpr (GB) {
 #pragma unroll
-        for (int e = 0; e < D; ++e) sN[(cf * NC + e) * NF + t] += (T)(-fp[e * NF] * dps);
-        sN[(cf * NC + D) * NF + t] += (T)(-sqrt(area2) * dvs);
+      for (int j = 0; j < N; ++j) {
+        glf0[j] = (double)tab[tab_LF0(N) + j];
+        glf1[j] = (double)tab[tab_LF1(N) + j];
       }
     }
-  }
-  __syncthreads();
-  // ---- C: per direction, pointwise fluxes then lines (derivative + lifts)
-  op_points<D, N, T, PS, 0>(g, sU, sT, ncl);
-  __syncthreads();
-  op_lines<D, N, T, 0>(tab, sT, sN, sR, ncl);
-  __syncthreads();
-  op_points<D, N, T, PS, 1>(g, sU, sT, ncl);
-  __syncthreads();
-  op_lines<D, N, T, 1>(tab, sT, sN, sR, ncl);
-  __syncthreads();
-  if constexpr (D == 3) {
-    op_points<D, N, T, PS, 2>(g, sU, sT, ncl);
-    __syncthreads();
-    op_lines<D, N, T, 2>(tab, sT, sN, sR, ncl);
-    __syncthreads();
-  }
-  // ---- D: inverse mass (pointwise FP64 factors), G -> GL
 #pragma unroll
-  for (int s = 0; s < PS; ++s) {
-    const int i = tid + s * NT;
-    if (i < ncl * NP) {
-      const int c = i / NP, q = i - c * NP;
-      T* r = sR + c * NC * NP + q;
+    for (int s = 0; s < NS; ++s) {
+      const int i = tid + s * NT;
+      nv[s] = 0.0;
+      if (i < ncl * NFACE * NC * NF && nbi[s] >= 0) {  // boundary faces: exterior state built in F
+        const int t = i % NF;
+        const int r = i / NF;
+        const int v = r % NC;
+        const int cf = r / NC;  // c * NFACE + f
+        // GL node of the neighbour's face f' that meets own tangential index t:
+        // f' = f^1 with aligned coordinates unless the mesh gives orientations
+        int fn = (cf % NFACE) ^ 1, tn = t;
+        if (p.fo) {
+          const int code = p.fo[cell0 * NFACE + cf];
+          fn = code >> 3;
+          tn = orient_face<D, N>(code & 7, t);
+        }
+        const int dir = fn >> 1, side = fn & 1;
+        const double* un = p.u + moff + (int64_t)nbi[s] * NC * NP + v * NP;
+        if constexpr (GB) {  // interpolate the neighbour's normal line to its face
+          const int q0 = face_line_base<D, N>(dir, tn), st = dir_stride(N, dir);
+          double acc = 0.0;
 #pragma unroll
-      for (int v = 0; v < NC; ++v) r[v * NP] = (T)(g[s][D * D + (v == D)] * (double)r[v * NP]);
+          for (int j = 0; j < N; ++j) acc = fma(side ? glf1[j] : glf0[j], un[q0 + j * st], acc);
+          nv[s] = acc;
+        } else {
+          nv[s] = un[face_line_base<D, N>(dir, tn) + (side ? (N - 1) * dir_stride(N, dir) : 0)];
+        }
+      }
     }
-  }
-  __syncthreads();
-  if constexpr (!GB) tensor_apply_inplace<NT, D, N, T>(sR, ncl * NC, tab + tab_Sinv(N));
-  // ---- E: epilogue (coalesced, operands prefetched in A)
-  {
-    int scell = -1;
-    if (p.src.cell) scell = p.src.cell[member];
-    const bool has_src = scell >= cell0 && scell < cell0 + ncl;
-    double sval = 0.0;
-    if (has_src) {
-      const double tn = p.time.tn();
-      if constexpr (EPI == EPI_LSRK) sval = ricker_deriv(p.src.wave + 3 * member, tn + p.time.t_off, 0);
-      if constexpr (EPI == EPI_ADD) sval = ricker_integral(p.src.wave + 3 * member, tn, tn + p.time.dt);
+    double eb[ES];
+#pragma unroll
+    for (int s = 0; s < ES; ++s) {
+      const int i = tid + s * NT;
+      eb[s] = 0.0;
+      if constexpr (EPI == EPI_ADD)
+        if (i < nel) eb[s] = p.u_base[gofs + i];
+      if constexpr (EPI == EPI_LSRK)
+        if (i < nel && (p.two_r ? !p.first : p.acoef != 0.0)) eb[s] = p.du[gofs + i];
     }
 #pragma unroll
     for (int s = 0; s < ES; ++s) {
       const int i = tid + s * NT;
-      if (i >= nel) continue;
-      const double val = (double)sR[i];
-      const int64_t gi = gofs + i;
-      if constexpr (EPI == EPI_STORE) {
-        p.out[gi] = val;
-      } else {
-        double add = 0.0;
-        if (has_src) {
-          const int c = i / (NC * NP);
-          const int v = (i / NP) % NC;
-          if (cell0 + c == scell && v == D) add = sval * p.src.gvec[(int64_t)member * NP + (i % NP)];
-        }
-        if constexpr (EPI == EPI_LSRK) {
-          if (p.two_r) {  // accumulated solution in du, next stage state in u_next
-            const double k = p.dt * (val + add);
-            const double un = (p.first ? ev[s] : eb[s]) + p.bcoef * k;
-            p.du[gi] = un;
-            p.u_next[gi] = un + p.acoef * k;
-          } else {
-            const double d = p.acoef * eb[s] + p.dt * (val + add);
-            p.du[gi] = d;
-            p.u_next[gi] = ev[s] + p.bcoef * d;
+      if (i < nel) sU[i] = (T)ev[s];
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = tid + s * NT;
+      if (i < ncl * NFACE * NC * NF) sN[i] = (T)nv[s];
+    }
+    __syncthreads();
+
+    // ---- B: GL -> G of the cell tiles; tangential GL -> G of the neighbour traces
+    if constexpr (!GB) {
+      const T* S = tab + tab_S(N);
+      tpass<NT, D, 0, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
+      if constexpr (D == 2) tpass<NT, 1, 0, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
+      if constexpr (D == 3) tpass<NT, 2, 0, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
+      __syncthreads();
+      tpass<NT, D, 1, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
+      if constexpr (D == 3) tpass<NT, 2, 1, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
+      __syncthreads();
+      if constexpr (D == 3) {
+        tpass<NT, D, 2, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
+        __syncthreads();
+      }
+    }
+    // ---- F: numerical fluxes at every face point, written over the neighbour traces
+    {
+      T lf0[N], lf1[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        lf0[j] = tab[tab_LF0(N) + j];
+        lf1[j] = tab[tab_LF1(N) + j];
+      }
+#pragma unroll
+      for (int s = 0; s < FS; ++s) {
+        const int i = tid + s * NT;
+        if (i < ncl * NFACE * NF) {
+          const int cf = i / NF, t = i - (i / NF) * NF;
+          const int c = cf / NFACE, f = cf - c * NFACE;
+          const int dir = f >> 1, side = f & 1;
+          const int st = dir_stride(N, dir);
+          const T* su = sU + c * NC * NP + face_line_base<D, N>(dir, t);
+          double um[NC], up[NC];
+#pragma unroll
+          for (int v = 0; v < NC; ++v) {
+            T acc = 0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) acc = fma(side ? lf1[j] : lf0[j], su[v * NP + j * st], acc);
+            um[v] = (double)acc;
+            up[v] = (double)sN[(cf * NC + v) * NF + t];
           }
-        } else {
-          p.u_next[gi] = eb[s] + val + add;
+          double area2 = 0.0, vnm = 0.0, vnp = 0.0;
+#pragma unroll
+          for (int e = 0; e < D; ++e) {
+            area2 = fma(fg[s][e], fg[s][e], area2);
+            vnm = fma(fg[s][e], um[e], vnm);
+            vnp = fma(fg[s][e], up[e], vnp);
+          }
+          const double area = sqrt(area2), inv_area = 1.0 / area;
+          vnm *= inv_area;
+          vnp *= inv_area;
+          double pp = up[D];
+          if (fnb[s] < 0) {  // boundary: mirror state (wall), else zero state (absorbing;
+                             // prescribed data are added below)
+            pp = fnb[s] == kBcWall ? um[D] : 0.0;
+            vnp = fnb[s] == kBcWall ? -vnm : 0.0;
+          }
+          double ps, vs;
+          if (p.central) {
+            ps = 0.5 * (um[D] + pp);
+            vs = 0.5 * (vnm + vnp);
+          } else {
+            const double Zm = fg[s][D], Zp = fg[s][D + 1];
+            const double inv = 1.0 / (Zm + Zp);
+            ps = (Zp * um[D] + Zm * pp + Zm * Zp * (vnm - vnp)) * inv;
+            vs = (Zm * vnm + Zp * vnp + um[D] - pp) * inv;
+          }
+#pragma unroll
+          for (int e = 0; e < D; ++e) sN[(cf * NC + e) * NF + t] = (T)(-fg[s][e] * ps);
+          sN[(cf * NC + D) * NF + t] = (T)(-area * vs);
+        }
+      }
+      // Prescribed faces (device neighbour entry kBcPrescribed - slot): both
+      // fluxes are linear in the exterior state, so the flux of the given data
+      // (p+, v+.n, evaluated for this launch into ext[slot][2][NF]) is added to
+      // the zero-state flux written above.  Same thread as above for each face
+      // point; operands re-read from memory so that this rare path takes no
+      // registers from the loop above.
+      if (p.ext) {
+#pragma unroll 1
+        for (int i = tid; i < ncl * NFACE * NF; i += NT) {
+          const int cf = i / NF, t = i - (i / NF) * NF;
+          const int code = p.nb[cell0 * NFACE + cf];
+          if (code > kBcPrescribed) continue;
+          const double* ex = p.ext + (int64_t)(kBcPrescribed - code) * 2 * NF + t;
+          const double pe = ex[0], vne = ex[NF];
+          const double* fp = p.geo_face + (cell0 * NFACE + cf) * (int64_t)((D + 2) * NF) + t;
+          double area2 = 0.0;
+#pragma unroll
+          for (int e = 0; e < D; ++e) area2 = fma(fp[e * NF], fp[e * NF], area2);
+          double dps, dvs;
+          if (p.central) {
+            dps = 0.5 * pe;
+            dvs = 0.5 * vne;
+          } else {
+            const double Zm = fp[D * NF], Zp = fp[(D + 1) * NF];
+            const double inv = 1.0 / (Zm + Zp);
+            dps = (Zm * pe - Zm * Zp * vne) * inv;
+            dvs = (Zp * vne - pe) * inv;
+          }
+#pragma unroll
+          for (int e = 0; e < D; ++e) sN[(cf * NC + e) * NF + t] += (T)(-fp[e * NF] * dps);
+          sN[(cf * NC + D) * NF + t] += (T)(-sqrt(area2) * dvs);
         }
       }
     }
-  }
+    __syncthreads();
+    // ---- C: per direction, pointwise fluxes then lines (derivative + lifts)
+    op_points<D, N, T, PS, 0>(g, sU, sT, ncl);
+    __syncthreads();
+    op_lines<D, N, T, 0>(tab, sT, sN, sR, ncl);
+    __syncthreads();
+    op_points<D, N, T, PS, 1>(g, sU, sT, ncl);
+    __syncthreads();
+    op_lines<D, N, T, 1>(tab, sT, sN, sR, ncl);
+    __syncthreads();
+    if constexpr (D == 3) {
+      op_points<D, N, T, PS, 2>(g, sU, sT, ncl);
+      __syncthreads();
+      op_lines<D, N, T, 2>(tab, sT, sN, sR, ncl);
+      __syncthreads();
+    }
+    // ---- D: inverse mass (pointwise FP64 factors), G -> GL
+#pragma unroll
+    for (int s = 0; s < PS; ++s) {
+      const int i = tid + s * NT;
+      if (i < ncl * NP) {
+        const int c = i / NP, q = i - c * NP;
+        T* r = sR + c * NC * NP + q;
+#pragma unroll
+        for (int v = 0; v < NC; ++v) r[v * NP] = (T)(g[s][D * D + (v == D)] * (double)r[v * NP]);
+      }
+    }
+    __syncthreads();
+    if constexpr (!GB) tensor_apply_inplace<NT, D, N, T>(sR, ncl * NC, tab + tab_Sinv(N));
+    // ---- E: epilogue (coalesced, operands prefetched in A)
+    {
+      int scell = -1;
+      if (p.src.cell) scell = p.src.cell[member];
+      const bool has_src = scell >= cell0 && scell < cell0 + ncl;
+      double sval = 0.0;
+      if (has_src) {
+        const double tn = p.time.tn();
+        if constexpr (EPI == EPI_LSRK) sval = ricker_deriv(p.src.wave + 3 * member, tn + p.time.t_off, 0);
+        if constexpr (EPI == EPI_ADD) sval = ricker_integral(p.src.wave + 3 * member, tn, tn + p.time.dt);
+      }
+#pragma unroll
+      for (int s = 0; s < ES; ++s) {
+        const int i = tid + s * NT;
+        if (i >= nel) continue;
+        const double val = (double)sR[i];
+        const int64_t gi = gofs + i;
+        if constexpr (EPI == EPI_STORE) {
+          p.out[gi] = val;
+        } else {
+          double add = 0.0;
+          if (has_src) {
+            const int c = i / (NC * NP);
+            const int v = (i / NP) % NC;
+            if (cell0 + c == scell && v == D) add = sval * p.src.gvec[(int64_t)member * NP + (i % NP)];
+          }
+          if constexpr (EPI == EPI_LSRK) {
+            if (p.two_r) {  // accumulated solution in du, next stage state in u_next
+              const double k = p.dt * (val + add);
+              const double un = (p.first ? ev[s] : eb[s]) + p.bcoef * k;
+              p.du[gi] = un;
+              p.u_next[gi] = un + p.acoef * k;
+            } else {
+              const double d = p.acoef * eb[s] + p.dt * (val + add);
+              p.du[gi] = d;
+              p.u_next[gi] = ev[s] + p.bcoef * d;
+            }
+          } else {
+            p.u_next[gi] = eb[s] + val + add;
+          }
+        }
+      }
+    }
+  }  // member
 }
 
 // ------------------------------------------------------------------------
@@ -877,6 +893,146 @@ struct Tck {
     }
   }
 
+  // ---- final phase in FP64: I_GL = sum_l Q_l^(x d) A_l, with Q_l (N x m_l)
+  // the level-l Gauss interpolant evaluated at the GL nodes (the embeddings
+  // to level 0 and S^-1 in one matrix per level).  One pass per direction
+  // over all levels at once; the last pass sums the levels and stores I.
+  static constexpr int NLV_ALL = Regs::NLV;
+  static constexpr int mlev(int L) { return N - RP * L; }
+  static constexpr int fin_elems(int stage) {  // FP64 elements per cell and component of A / T / U
+    int e = 0;
+    for (int L = 0; L < NLV_ALL; ++L) {
+      const int m = mlev(L);
+      e += stage == 0 ? ipow(m, D) : (stage == 1 ? N * ipow(m, D - 1) : N * N * ipow(m, D - 2));
+    }
+    return e;
+  }
+  static constexpr int fin_off(int stage, int L) {  // offset of level L inside stage `stage`
+    int e = 0;
+    for (int j = 0; j < L; ++j) {
+      const int m = mlev(j);
+      e += stage == 0 ? ipow(m, D) : (stage == 1 ? N * ipow(m, D - 1) : N * N * ipow(m, D - 2));
+    }
+    return e;
+  }
+  // LDS use of the final phase (bytes per cell): A and T at once, then T and U
+  static constexpr int fin_bytes() {
+    const int a = fin_elems(0), t = fin_elems(1), u = D == 3 ? fin_elems(2) : 0;
+    const int p1 = a + t, p2 = t + u;
+    return 8 * NC * (p1 > p2 ? p1 : p2);
+  }
+  static constexpr bool FUSED_FINAL = sizeof(T) == 8 && !Regs::ACC_LDS &&
+                                      fin_bytes() <= TckLayout<D, N, T>::bytes_per_cell(RP);
+
+  // level L's 1D matrix of the final phase (N x m_L): S^-1 for level 0
+  __device__ static __forceinline__ const double* qmat(int L) {
+    return L == 0 ? ctab<double>(N) + tab_Sinv(N) : ctab<double>(N) + tab_level_Q(N, L, RP);
+  }
+
+  template <int L>
+  __device__ static __forceinline__ void fin_write_A(double* A, Regs& R, int ncl) {
+    if constexpr (L < NLV_ALL) {
+      constexpr int NPL = ipow(mlev(L), D);
+      double* a = A + CPW * NC * fin_off(0, L);
+#pragma unroll
+      for (int s = 0; s < psl(L); ++s) {
+        const int i = threadIdx.x + s * NT;
+        if (i < ncl * NPL) {
+          const int c = i / NPL, q = i - c * NPL;
+#pragma unroll
+          for (int v = 0; v < NC; ++v) a[(c * NC + v) * NPL + q] = R.A[L][s][v];
+        }
+      }
+      fin_write_A<L + 1>(A, R, ncl);
+    }
+  }
+
+  // pass along DIR (0: x, 1: y) of every level, from stage DIR to stage DIR+1
+  template <int DIR, int L>
+  __device__ static __forceinline__ void fin_pass(const double* in, double* out, int ncl) {
+    if constexpr (L < NLV_ALL) {
+      constexpr int m = mlev(L);
+      // extents of the input: direction < DIR already N, the others m
+      using P = Pass<D, DIR, m, N, (DIR > 0 ? N : m), (DIR > 1 ? N : m), m>;
+      const double* src0 = in + CPW * NC * fin_off(DIR, L);
+      double* dst0 = out + CPW * NC * fin_off(DIR + 1, L);
+      const double* Q = qmat(L);
+      for (int w = threadIdx.x; w < ncl * NC * P::NL; w += NT) {
+        const int sl = w / P::NL;
+        const int Ln = w - sl * P::NL;
+        int bi, bo;
+        P::base(Ln, bi, bo);
+        const double* src = src0 + sl * P::SIN + bi;
+        double* dst = dst0 + sl * P::SOUT + bo;
+        double x[m];
+#pragma unroll
+        for (int j = 0; j < m; ++j) x[j] = src[j * P::STEP_IN];
+        double acc[N];
+        contract<m, N>(Q, x, acc);
+#pragma unroll
+        for (int i = 0; i < N; ++i) dst[i * P::STEP_OUT] = acc[i];
+      }
+      fin_pass<DIR, L + 1>(in, out, ncl);
+    }
+  }
+
+  // last direction: sum over the levels of Q_L along D-1, into acc
+  template <int L>
+  __device__ static __forceinline__ void fin_last(const double* in, int sl, int t, double (&acc)[N]) {
+    if constexpr (L < NLV_ALL) {
+      constexpr int m = mlev(L);
+      constexpr int SL = ipow(N, D - 1) * m;  // elements of one slice of this level
+      const double* src = in + CPW * NC * fin_off(D - 1, L) + sl * SL + t;
+      const double* Q = qmat(L);
+#pragma unroll
+      for (int j = 0; j < m; ++j) {
+        const double xj = src[j * ipow(N, D - 1)];
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] = fma(Q[i * m + j], xj, acc[i]);
+      }
+      fin_last<L + 1>(in, sl, t, acc);
+    }
+  }
+
+  // the whole final phase; smem holds at least fin_bytes() per cell
+  template <bool HDG_ADD>
+  __device__ static __forceinline__ void final_fused(const TckParams& p, double* sm, Regs& R, int ncl,
+                                                     int64_t gofs) {
+    constexpr int EA = fin_elems(0), ET = fin_elems(1), EU = D == 3 ? fin_elems(2) : 0;
+    constexpr int LOW = (EA > EU ? EA : EU) * CPW * NC;  // A and U share the start, T follows
+    double* A = sm;
+    double* Tt = sm + LOW;
+    double* U = sm;
+    fin_write_A<0>(A, R, ncl);
+    __syncthreads();
+    fin_pass<0, 0>(A, Tt, ncl);
+    __syncthreads();
+    const double* last = Tt;
+    if constexpr (D == 3) {
+      fin_pass<1, 0>(Tt, U, ncl);
+      __syncthreads();
+      last = U;
+    }
+    // one thread per output line along the last direction: (cell, component, tangential t)
+    constexpr int NT1 = ipow(N, D - 1);
+    constexpr int ST = ipow(N, D - 1);
+    for (int w = threadIdx.x; w < ncl * NC * NT1; w += NT) {
+      const int sl = w / NT1;
+      const int t = w - sl * NT1;
+      double acc[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc[i] = 0.0;
+      fin_last<0>(last, sl, t, acc);
+      const int64_t g0 = gofs + (int64_t)sl * NP + t;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double val = acc[i];
+        if constexpr (HDG_ADD) val += p.dt * p.u_base[g0 + i * ST];
+        p.I[g0 + i * ST] = val;
+      }
+    }
+  }
+
   // I_G = A_0 + E(A_1 + E(A_2 + ...)): from the coarsest level L upwards,
   // leaving level L-1's partial sum in tile C
   template <int L>
@@ -988,27 +1144,31 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck
   else
     K::template step<1, 0>(p, C, Db, R, cell0, ncl, member);
   __syncthreads();  // the last accumulation may still read C
-  // collapse the coarser levels into level 0, add A_0 in FP64, then G -> GL in FP64
-  K::template collapse<Regs::NLV - 1>(p, C, Db, R, ncl);
-  double* sI = reinterpret_cast<double*>(Db[0]);  // FP64 tile over the derivative tiles
+  if constexpr (K::FUSED_FINAL) {
+    K::template final_fused<HDG>(p, reinterpret_cast<double*>(smem), R, ncl, gofs);
+  } else {
+    // collapse the coarser levels into level 0, add A_0 in FP64, then G -> GL in FP64
+    K::template collapse<Regs::NLV - 1>(p, C, Db, R, ncl);
+    double* sI = reinterpret_cast<double*>(Db[0]);  // FP64 tile over the derivative tiles
 #pragma unroll
-  for (int s = 0; s < PS0; ++s) {
-    const int i = threadIdx.x + s * NT;
-    if (i < ncl * NP) {
-      const int c = i / NP, q = i - c * NP;
+    for (int s = 0; s < PS0; ++s) {
+      const int i = threadIdx.x + s * NT;
+      if (i < ncl * NP) {
+        const int c = i / NP, q = i - c * NP;
 #pragma unroll
-      for (int v = 0; v < NC; ++v) {
-        const double lower = Regs::NLV > 1 ? (double)C[(c * NC + v) * NP + q] : 0.0;
-        sI[(c * NC + v) * NP + q] = R.A[0][s][v] + lower;
+        for (int v = 0; v < NC; ++v) {
+          const double lower = Regs::NLV > 1 ? (double)C[(c * NC + v) * NP + q] : 0.0;
+          sI[(c * NC + v) * NP + q] = R.A[0][s][v] + lower;
+        }
       }
     }
-  }
-  __syncthreads();
-  tensor_apply_inplace<NT, D, N, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
-  if constexpr (HDG) {
-    for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i] + p.dt * p.u_base[gofs + i];
-  } else {
-    for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i];
+    __syncthreads();
+    tensor_apply_inplace<NT, D, N, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
+    if constexpr (HDG) {
+      for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i] + p.dt * p.u_base[gofs + i];
+    } else {
+      for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i];
+    }
   }
 }
 

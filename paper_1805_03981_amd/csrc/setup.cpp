@@ -141,6 +141,10 @@ std::vector<double> build_tables(int n) {
           t[tab_level_E(n, l, r) + q * m + a] = (double)lagrange_value(rm.x, a, rp.x[q]);
       for (int q = 0; q < m; ++q)
         for (int j = 0; j < n; ++j) t[tab_level_F(n, l, r) + q * n + j] = (double)lagrange_value(g.x, j, rm.x[q]);
+      // level-l Gauss interpolant at the GL nodes: the embeddings back to
+      // level 0 (exact on the lower degree) followed by S^-1, in one matrix
+      for (int i = 0; i < n; ++i)
+        for (int a = 0; a < m; ++a) t[tab_level_Q(n, l, r) + i * m + a] = (double)lagrange_value(rm.x, a, gl.x[i]);
     }
   return t;
 }

@@ -146,6 +146,72 @@ def test_launch_shapes_give_identical_bits(gpu_lib, k):
     assert torch.equal(gm.apply(to_dev(U)), res[shapes.index(c)][0])
 
 
+def test_autotune_cache_file(gpu_lib, tmp_path, monkeypatch):
+    """The autotuner appends its choice per (architecture, d, k, precision,
+    basis, B, cells) to the JSON-lines file named by DGW_AUTOTUNE_CACHE and
+    takes a matching line from there instead of timing."""
+    import json
+    say("autotune cache file")
+    B = gpu_lib
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("DGW_AUTOTUNE_CACHE", str(path))
+    mat = W.FourierMaterial(1, dim=3)
+    gm = B.Mesh(3, 3, W.box_nodes(3, 5, 3, 0.05), W.box_neighbors(3, 5), mat)
+    gm.autotune(1)
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert len(lines) == 1 and lines[0]["key"].endswith("|d3|k3|fp64|gl|B1|nc125")
+    rec = lines[0]
+    cpw = {0: 4, 1: 8}  # the two compiled shapes of 4^3-point cells
+    assert gm.launch_shape(0)[0] == cpw[rec["op_store"]] and gm.launch_shape(1)[0] == cpw[rec["tck"]]
+    assert gm.launch_shape(2)[0] == cpw[rec["op_lsrk"]] and gm.launch_shape(3)[0] == cpw[rec["op_ader_update"]]
+    # a line for another mesh size, written by hand, is taken as it is
+    key = rec["key"].replace("nc125", "nc216")
+    with open(path, "a") as f:
+        f.write(json.dumps({"key": key, "op_store": 1, "op_lsrk": 0, "op_ader_update": 1, "tck": 0}) + "\n")
+    g6 = B.Mesh(3, 3, W.box_nodes(3, 6, 3, 0.05), W.box_neighbors(3, 6), mat)
+    g6.autotune(1)
+    assert [g6.launch_shape(w)[0] for w in range(4)] == [8, 4, 4, 8]
+    assert len(path.read_text().splitlines()) == 2  # nothing timed, nothing appended
+
+
+@pytest.mark.parametrize("Bn", [3, 10])
+def test_member_block_operator_equals_grid_batch(gpu_lib, tmp_path, monkeypatch, Bn):
+    """The member-block operator (8 batch members per workgroup, geometry
+    loaded once) against the plain batch (one member per workgroup), selected
+    through an autotune cache line: operator, LSRK and ADER steps agree to
+    rounding; B = 10 leaves a ragged last block."""
+    import json
+    say("member block", Bn)
+    B = gpu_lib
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("DGW_AUTOTUNE_CACHE", str(path))
+    gm = B.Mesh(3, 3, W.box_nodes(3, 3, 3, 0.05), W.box_neighbors(3, 3), W.FourierMaterial(3, dim=3, rho_amp=0.3),
+                max_batch=Bn)
+    U = W.random_state(40 + Bn, (Bn,) + gm.shape)
+    src = B.Sources(gm, W.random_points(41, Bn, 3), frequency=5.0)
+    dt = 0.25 * gm.info.dt_unit
+
+    def run():
+        a = gm.apply(to_dev(U), B=Bn)
+        ul = to_dev(U)
+        gm.step_lsrk(ul, 0.1, dt, 2, sources=src, B=Bn)
+        ua = to_dev(U)
+        gm.step_ader(ua, 0.1, dt, 2, sources=src, B=Bn)
+        torch.cuda.synchronize()
+        return a, ul, ua
+
+    plain = run()
+    key = f"gfx950|d3|k3|fp64|gl|B{Bn}|nc27"
+    path.write_text(json.dumps({"key": key, "op_store": 2, "op_lsrk": 3, "op_ader_update": 2, "tck": 0}) + "\n")
+    gm.autotune(Bn)
+    assert [gm.launch_shape(w)[0] for w in (4, 5, 6)] == [8, 8, 8]
+    block = run()
+    for name, x, y in zip(("operator", "lsrk", "ader"), plain, block):
+        d = ((x - y).abs().max() / x.abs().max()).item()
+        say(f"member block B={Bn}: {name} max difference {d:.1e}")
+        assert d < 1e-14
+
+
 def test_watchdog_checks_every_member(gpu_lib):
     """Member 0 at rest and member 1 unstable: the watchdog trips (it checks
     every member); a source-driven solve from rest at a stable step runs

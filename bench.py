@@ -305,7 +305,7 @@ def serving(nreq=24, seed=5, load=0.8, nmin=6, nmax=20, tmin=0.05, tmax=0.2, pro
             "capacity_dof_steps_per_s": cap.dof_steps_per_s, "wall_s": rep.wall_s}
 
 
-def fixed_error(target=1e-6, T=0.5, iters=3, max_run_s=12.0):
+def fixed_error(target=1e-5, T=0.5, iters=3, max_run_s=12.0):
     """Time to solution at a fixed error, against two FP64 references on the
     same mesh at 1/8 of their steps (0.9 of the critical Courant number):
     ADER, and LSRK(5,4) (which converges at fourth order to the semi-discrete
@@ -315,7 +315,11 @@ def fixed_error(target=1e-6, T=0.5, iters=3, max_run_s=12.0):
     coefficient 2-norm over the GL nodes): the step is halved until the
     target is met, then bisected in log(dt).  Runs are shared between the two
     searches where the steps coincide; runs longer than `max_run_s` are not
-    started; a search that stops converging reports the smallest error."""
+    started; a search that stops converging reports the smallest error.  The
+    target (1e-5) sits above the distance between the two references
+    (about 1e-6: the ADER solution approaches the semi-discrete one at first
+    order in dt, its predictor being cell-local), which is reported beside
+    it, so that neither reference favours its own scheme."""
     from paper_1805_03981_amd import binding as dg
     refs, out = {}, {"target_rel_l2_p": target, "T": T, "references": {}}
     for rs in ("ader", "lsrk"):
@@ -380,6 +384,23 @@ def fixed_error(target=1e-6, T=0.5, iters=3, max_run_s=12.0):
         out[key] = res
         log(f"[bench] fixed error {key}: {res}")
         del m
+    return out
+
+
+def fixed_summary(fe):
+    """Time to solution of each variant at the fixed error, against the FP64
+    LSRK(5,4) reference, for the top of the line (None if not measured)."""
+    if not fe:
+        return None
+    out = {"target_rel_l2_p": fe["target_rel_l2_p"], "T": fe["T"],
+           "reference_distance_ader_vs_lsrk": fe["references"].get("ader_vs_lsrk_rel_l2_p")}
+    for key, res in fe.items():
+        if not isinstance(res, dict) or "vs_lsrk" not in res:
+            continue
+        r = res["vs_lsrk"]
+        out[key] = ({"time_to_solution_s": r["time_to_solution_s"], "dof_steps_per_s": r["dof_steps_per_s"],
+                     "courant": r["courant"], "rel_l2_p": r["rel_l2_p"], "limited_by": r["limited_by"]}
+                    if r.get("reached") else {"reached": False, "error_floor": r.get("smallest_error")})
     return out
 
 
@@ -821,6 +842,8 @@ def main():
                          "kernels_ms": r["kernels_ms"], "launch_shape": r["launch_shape"]}
                      for k, r in results.items()},
         "kernels": kernels,
+        "fixed_error_summary": fixed_summary(extras.get("fixed_error")),
+        "fp32_split_error_vs_fp64": extras.get("fp32_split_rel_err_5_steps"),
         "extras": extras,
         "kernel_sources_sha256_16": kernel_hash(),
     }

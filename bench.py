@@ -20,12 +20,13 @@ against the closed form), a serving trace of 24 requests drawn like the
 serving workload (n^3 cells, n in [8, 48], k in 2..8, T in [0.1, 1], Poisson
 arrivals at 0.8 x capacity, p50/p99), the time to solution at a fixed
 pressure error (1e-6 relative at T = 0.5) against FP64 ADER and FP64 LSRK
-references, and the CPU FP64 oracle timed on a bounded sample of the same
+references, the measured device ceilings (copy, triad, DGEMM, LDS, vector
+FMA, MFMA) and the CPU FP64 oracle timed on a bounded sample of the same
 workload.  Optional: the 200-request serving trace, the degree sweep
-k = 1..8 on the paper's cube sizes, measured device ceilings, ablations.
+k = 1..8 on the paper's cube sizes, ablations.
 
     python bench.py [--steps K] [--warmup W] [--variants ader-fp64,...]
-                    [--no-fixed-error] [--ablations] [--c3] [--sweep] [--ceilings] [--no-batched] [--no-c3]
+                    [--no-fixed-error] [--ablations] [--c3] [--sweep] [--no-ceilings] [--no-batched] [--no-c3]
                     [--no-serving] [--serving-full]
 """
 from __future__ import annotations
@@ -732,8 +733,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 32^3 k=5 batch of 64 point sources (500 ADER steps)")
     ap.add_argument("--no-c3", action="store_true", help="skip the bounded 48^3 k=7 leg")
-    ap.add_argument("--ceilings", action="store_true",
-                    help="also measure copy/triad/DGEMM, LDS, vector FMA and MFMA ceilings")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the copy/triad/DGEMM, LDS, vector FMA and MFMA ceilings")
     ap.add_argument("--ablations", action="store_true",
                     help="also run the fused / merged / standard LSRK vector updates and ADER without reduction")
     ap.add_argument("--c3", action="store_true",
@@ -816,8 +817,12 @@ def main():
     if args.sweep:
         log("[bench] degree sweep")
         extras["degree_sweep"] = degree_sweep()
-    if args.ceilings:
+    if not args.no_ceilings:
+        log("[bench] ceilings")
         extras["ceilings"] = ceilings()
+        # beside the published peak: the fraction of this box's measured device copy
+        roofline["measured_copy_GBps"] = extras["ceilings"]["copy_GBps"]
+        roofline["frac_of_measured_copy"] = achieved / extras["ceilings"]["copy_GBps"]
         log(f"[bench] ceilings: {extras['ceilings']}")
     cpu = None
     if not args.no_cpu_baseline:

@@ -116,6 +116,10 @@ int64_t dgw_request_footprint(const dgw_request* r) {
 
 namespace {
 
+// DoF-steps per stepping call of a live request (about a millisecond of
+// GPU time at the solver's rates)
+constexpr int64_t kChunkDofSteps = 10000000;
+
 struct Live {
   int idx = -1;
   dgw_mesh* mesh = nullptr;
@@ -309,19 +313,25 @@ dgw_status dgw_serve(const dgw_server_desc* desc, const dgw_request* reqs, int n
       }
       continue;
     }
-    // one step of every live request, each on its own stream
+    // a chunk of steps of every live request, each on its own stream: about
+    // kChunkDofSteps of work per call, so that a small request does not
+    // pay a host round trip per step while a large one advances one step
+    // per round (its steps are long enough to keep the GPU busy)
     for (auto& L : live) {
       const dgw_request& r = reqs[L.idx];
       const double t0 = (double)L.done * L.dt;
-      const dgw_status st = r.scheme == DGW_SCHEME_ADER
-                                ? dgw_step_ader(L.mesh, 0, t0, L.dt, 1, L.u, L.work, 1, nullptr, L.stream)
-                                : dgw_step_lsrk(L.mesh, r.scheme, t0, L.dt, 1, L.u, L.work, 1, nullptr, L.stream);
+      const int64_t chunk =
+          std::max<int64_t>(1, std::min<int64_t>(L.steps - L.done, kChunkDofSteps / std::max<int64_t>(1, L.dofs)));
+      const dgw_status st =
+          r.scheme == DGW_SCHEME_ADER
+              ? dgw_step_ader(L.mesh, 0, t0, L.dt, (int)chunk, L.u, L.work, 1, nullptr, L.stream)
+              : dgw_step_lsrk(L.mesh, r.scheme, t0, L.dt, (int)chunk, L.u, L.work, 1, nullptr, L.stream);
       if (st) {
         L.done = -1 - L.done;  // mark failed
         continue;
       }
-      ++L.done;
-      dof_steps += L.dofs;
+      L.done += chunk;
+      dof_steps += L.dofs * chunk;
     }
     // retire finished or failed requests (query streams without blocking others)
     for (size_t j = 0; j < live.size();) {

@@ -7,10 +7,12 @@
 #include <complex>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <new>
 #include <tuple>
+#include <vector>
 
 #include "dgw_exterior.hpp"
 #include "dgw_host.hpp"
@@ -670,19 +672,15 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
   hipEvent_t e0, e1;
   DGW_HIP(hipEventCreate(&e0));
   DGW_HIP(hipEventCreate(&e1));
-  auto time_it = [&](auto&& launch) -> float {
-    for (int w = 0; w < 2; ++w)
-      if (launch() != hipSuccess) return 1e30f;
-    (void)hipEventRecord(e0, s);
-    for (int r = 0; r < 5; ++r) (void)launch();
-    (void)hipEventRecord(e1, s);
-    (void)hipEventSynchronize(e1);
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    return ms / 5;
-  };
   float ms[4][4] = {{1e30f, 1e30f, 1e30f, 1e30f}, {1e30f, 1e30f, 1e30f, 1e30f}, {1e30f, 1e30f, 1e30f, 1e30f},
                     {1e30f, 1e30f, 1e30f, 1e30f}};
+  // every candidate (kernel, shape) with the slot of its time
+  struct Cand {
+    float* slot;
+    std::function<hipError_t()> launch;
+    bool ok;
+  };
+  std::vector<Cand> cands;
   const bool gauss = m->basis == DGW_BASIS_GAUSS;
   const int nshape = B > 1 && !gauss ? 4 : 2;  // member blocks only pay with more than one member
   for (int shape = 0; shape < nshape; ++shape) {
@@ -704,7 +702,7 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
           p.u_next = buf[1];
           p.dt = 1e-3;
         }
-        ms[epi][shape] = time_it([&]() { return run_op(m, epi, shape, p, s); });
+        cands.push_back({&ms[epi][shape], [=]() { return run_op(m, epi, shape, p, s); }, true});
       }
     }
     if (shape < 2 && !gauss && (int64_t)m->L->cpw[sel] * m->L->tck_lds_per_cell[2] <= kLdsLimit) {
@@ -714,9 +712,25 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
       p.u = buf[0];
       p.I = buf[1];
       p.dt = 1e-3;
-      ms[3][sel] = time_it([&]() { return m->L->tck[2][sel](p, s); });
+      cands.push_back({&ms[3][sel], [=]() { return m->L->tck[2][sel](p, s); }, true});
     }
   }
+  // round robin over the candidates, keeping each one's fastest round: a
+  // clock ramp or a noisy neighbour then does not favour whichever shape
+  // happens to be timed last
+  constexpr int kRounds = 3, kLaunches = 3;
+  for (int round = 0; round < kRounds; ++round)
+    for (auto& c : cands) {
+      if (round == 0) c.ok = c.launch() == hipSuccess;  // warm-up
+      if (!c.ok) continue;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < kLaunches; ++r) (void)c.launch();
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float t = 0;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      *c.slot = std::min(*c.slot, t / kLaunches);
+    }
   (void)hipGetLastError();
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -13,7 +13,8 @@
 //   C  per direction b: volume fluxes w detJ J^-1 applied pointwise in FP64,
 //      transposed collocation derivative (Sec. 3, collocation), and the two
 //      faces normal to b (own trace by contraction with l^G(0), l^G(1);
-//      upwind flux; lift, rank one in the normal direction)
+//      upwind flux; lift, rank one in the normal direction); the residual
+//      is summed over the directions in registers of the point's thread
 //   D  inverse mass in the collocated basis: pointwise 1/(w detJ rho),
 //      rho c^2/(w detJ), then G -> GL (Sec. 3.1, inverse via basis change)
 //   E  epilogue: store, fused low-storage Runge-Kutta update, or ADER update
@@ -195,34 +196,37 @@ __device__ inline double ricker_integral(const double* w, double t1, double t2) 
 // ------------------------------------------------------------------------
 // Fused operator sweep: L u = -M^-1 K u with an epilogue.
 //
-// Every global operand of the workgroup (its state tile, the neighbours' GL
-// face nodes, the metric and mass factors of every point, the face area
-// vectors and impedances, and the epilogue's state operands) is requested
-// in one batch at the start.  The geometry stays in registers of the thread
-// that owns the point (thread-per-point phases) or the face point, so its
-// memory latency overlaps the basis-change passes and only one memory round
-// trip per workgroup is exposed.
+// Every global operand of the sweep (the workgroup's state tile, the
+// neighbours' GL face nodes, the metric and mass factors of every point, the
+// face area vectors and impedances) is requested in one batch at the start.
+// The geometry stays in registers of the thread that owns the point
+// (thread-per-point phases) or the face point, so its memory latency
+// overlaps the basis-change passes and only one memory round trip per
+// workgroup is exposed before the sweep; the epilogue's second state
+// operand is requested after the sweep, its latency hidden by phase D.
 // ------------------------------------------------------------------------
 template <int D, int N, typename T>
 struct OpLayout {
   static constexpr int NC = D + 1, NP = ipow(N, D), NF = ipow(N, D - 1), NFACE = 2 * D;
-  static constexpr int per_cell = 3 * NC * NP + NFACE * NC * NF;  // elements of T
+  // state and flux tiles, neighbour traces (elements of T); the residual
+  // is accumulated in registers of the point's thread
+  static constexpr int per_cell = 2 * NC * NP + NFACE * NC * NF;
 };
 
-// Register budget of the operator sweep with the plain store epilogue, as
-// for the TCK below: with one cell point per thread of a 256-thread group,
-// compiled for the waves per SIMD its LDS allows (at most 5); measured 7 %
-// faster at k = 5.  The LSRK and ADER epilogues keep their state operands
-// in registers across the sweep and would spill under that budget, and so
-// would the member-block variant (MB > 1), whose geometry registers stay
-// live across its loop over members (measured on the 64-source batch at
-// k = 5 FP32: capped at 5 waves it spills and runs 1.7x slower than one
-// member per workgroup).
+// Register budget of the operator sweep: with one cell point per thread of
+// a 256-thread group it is compiled for the waves per SIMD that its LDS
+// allows, capped at 6 (80 VGPRs) and at 5 (96 VGPRs) for the FP64 LSRK
+// epilogue, which keeps the stage state in registers across the sweep (at 6
+// it would spill 44 bytes per lane).  The member-block variant (MB > 1)
+// keeps its geometry registers live across its loop over members and gets
+// no budget (measured on the 64-source batch at k = 5 FP32: capped at 5
+// waves it spills and runs 1.7x slower than one member per workgroup).
 template <int D, int N, typename T, int EPI, int CPW, int MB = 1>
 constexpr int op_waves_per_simd() {
-  if (EPI != EPI_STORE || MB != 1 || op_threads(D, N) != 256 || cdiv(CPW * ipow(N, D), 256) > 1) return 1;
+  if (MB != 1 || op_threads(D, N) != 256 || cdiv(CPW * ipow(N, D), 256) > 1) return 1;
   const int wg = (160 * 1024) / (CPW * OpLayout<D, N, T>::per_cell * (int)sizeof(T));
-  return wg < 1 ? 1 : (wg > 5 ? 5 : wg);
+  const int cap = (EPI == EPI_LSRK && sizeof(T) == 8) ? 5 : 6;
+  return wg < 1 ? 1 : (wg > cap ? cap : wg);
 }
 
 __device__ __forceinline__ int dir_stride(int n, int dir) { return dir == 0 ? 1 : (dir == 1 ? n : n * n); }
@@ -254,10 +258,12 @@ __device__ __forceinline__ int orient_face(int o, int t) {
   return i + N * j;
 }
 
-// C2 of the operator: R (+)= D_b^T F along the b-lines, plus the lifts of the
-// two face fluxes of direction b (rank one in the normal direction).
+// C2 of the operator: D_b^T F along the b-lines plus the lifts of the two
+// face fluxes of direction b (rank one in the normal direction), written
+// over F in sT (a line is read whole before it is written; lines are
+// disjoint).  The point phase that follows adds it to the residual.
 template <int D, int N, typename T, int DIR>
-__device__ __forceinline__ void op_lines(const T* __restrict__ tab, const T* sT, const T* sN, T* sR, int ncl) {
+__device__ __forceinline__ void op_lines(const T* __restrict__ tab, T* sT, const T* sN, int ncl) {
   constexpr int NC = D + 1, NP = ipow(N, D), NF = ipow(N, D - 1), NFACE = 2 * D;
   using P = Pass<D, DIR, N, N, N, N, N>;
   const T* Dm = tab + tab_D(N);
@@ -270,12 +276,12 @@ __device__ __forceinline__ void op_lines(const T* __restrict__ tab, const T* sT,
     const int c = sl / NC, v = sl - c * NC;
     int bq, bq2;
     P::base(L, bq, bq2);
+    T* ln = sT + sl * NP + bq;
     T F[N];
 #pragma unroll
-    for (int j = 0; j < N; ++j) F[j] = sT[sl * NP + bq + j * P::STEP_IN];
+    for (int j = 0; j < N; ++j) F[j] = ln[j * P::STEP_IN];
     const T f0 = sN[((c * NFACE + 2 * DIR) * NC + v) * NF + L];
     const T f1 = sN[((c * NFACE + 2 * DIR + 1) * NC + v) * NF + L];
-    T* r = sR + sl * NP + bq;
     T acc[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[i] = fma(LF1[i], f1, LF0[i] * f0);
@@ -284,19 +290,17 @@ __device__ __forceinline__ void op_lines(const T* __restrict__ tab, const T* sT,
 #pragma unroll
       for (int i = 0; i < N; ++i) acc[i] = fma(Dm[j * N + i], F[j], acc[i]);
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      if constexpr (DIR == 0)
-        r[i * P::STEP_IN] = acc[i];
-      else
-        r[i * P::STEP_IN] += acc[i];
-    }
+    for (int i = 0; i < N; ++i) ln[i * P::STEP_IN] = acc[i];
   }
 }
 
-// C1 of the operator: the pointwise volume fluxes of direction b in FP64,
-// F_{v_a} = G_{ba} p, F_p = sum_a G_{ba} v_a, with G = w det J J^-1.
+// C1 of the operator: the residual of the previous direction's lines (in sT
+// at the point) is added to the registers R, then the pointwise volume
+// fluxes of direction b in FP64, F_{v_a} = G_{ba} p, F_p = sum_a G_{ba} v_a
+// with G = w det J J^-1, are written over it.
 template <int D, int N, typename T, int PS, int DIR>
-__device__ __forceinline__ void op_points(const double (&g)[PS][D * D + 2], const T* sU, T* sT, int ncl) {
+__device__ __forceinline__ void op_points(const double (&g)[PS][D * D + 2], const T* sU, T* sT, T (&R)[PS][D + 1],
+                                          int ncl) {
   constexpr int NC = D + 1, NP = ipow(N, D), NT = op_threads(D, N);
 #pragma unroll
   for (int s = 0; s < PS; ++s) {
@@ -305,6 +309,13 @@ __device__ __forceinline__ void op_points(const double (&g)[PS][D * D + 2], cons
       const int c = i / NP, q = i - c * NP;
       const T* su = sU + c * NC * NP + q;
       T* st = sT + c * NC * NP + q;
+      if constexpr (DIR == 1) {
+#pragma unroll
+        for (int v = 0; v < NC; ++v) R[s][v] = st[v * NP];
+      } else if constexpr (DIR > 1) {
+#pragma unroll
+        for (int v = 0; v < NC; ++v) R[s][v] += st[v * NP];
+      }
       const double pq = (double)su[D * NP];
       double fp = 0.0;
 #pragma unroll
@@ -335,8 +346,7 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>())))
   constexpr int NS = cdiv(CPW * NFACE * NC * NF, NT);  // neighbour trace values per thread
   extern __shared__ __align__(16) unsigned char smem[];
   T* sU = reinterpret_cast<T*>(smem);
-  T* sR = sU + CPW * NC * NP;
-  T* sT = sR + CPW * NC * NP;
+  T* sT = sU + CPW * NC * NP;
   T* sN = sT + CPW * NC * NP;
   const T* tab = ctab<T>(N);
   const int tid = threadIdx.x;
@@ -353,9 +363,9 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>())))
   const int ncl = (int)min((int64_t)CPW, p.nc - cell0);
   const int nel = ncl * NC * NP;
 
-  // ---- A: all global operands, in dependency order: the neighbour table
-  // and the geometry once, then per member its state, the neighbours' face
-  // nodes and the epilogue operands
+  // ---- A: the sweep's global operands, in dependency order: the neighbour
+  // table and the geometry once, then per member its state and the
+  // neighbours' face nodes
   int nbi[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
@@ -441,16 +451,6 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>())))
           nv[s] = un[face_line_base<D, N>(dir, tn) + (side ? (N - 1) * dir_stride(N, dir) : 0)];
         }
       }
-    }
-    double eb[ES];
-#pragma unroll
-    for (int s = 0; s < ES; ++s) {
-      const int i = tid + s * NT;
-      eb[s] = 0.0;
-      if constexpr (EPI == EPI_ADD)
-        if (i < nel) eb[s] = p.u_base[gofs + i];
-      if constexpr (EPI == EPI_LSRK)
-        if (i < nel && (p.two_r ? !p.first : p.acoef != 0.0)) eb[s] = p.du[gofs + i];
     }
 #pragma unroll
     for (int s = 0; s < ES; ++s) {
@@ -571,35 +571,53 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>())))
       }
     }
     __syncthreads();
-    // ---- C: per direction, pointwise fluxes then lines (derivative + lifts)
-    op_points<D, N, T, PS, 0>(g, sU, sT, ncl);
+    // ---- C: per direction, pointwise fluxes then lines (derivative + lifts);
+    // the residual of each direction is added in the next point phase
+    T R[PS][NC];
+    op_points<D, N, T, PS, 0>(g, sU, sT, R, ncl);
     __syncthreads();
-    op_lines<D, N, T, 0>(tab, sT, sN, sR, ncl);
+    op_lines<D, N, T, 0>(tab, sT, sN, ncl);
     __syncthreads();
-    op_points<D, N, T, PS, 1>(g, sU, sT, ncl);
+    op_points<D, N, T, PS, 1>(g, sU, sT, R, ncl);
     __syncthreads();
-    op_lines<D, N, T, 1>(tab, sT, sN, sR, ncl);
+    op_lines<D, N, T, 1>(tab, sT, sN, ncl);
     __syncthreads();
     if constexpr (D == 3) {
-      op_points<D, N, T, PS, 2>(g, sU, sT, ncl);
+      op_points<D, N, T, PS, 2>(g, sU, sT, R, ncl);
       __syncthreads();
-      op_lines<D, N, T, 2>(tab, sT, sN, sR, ncl);
+      op_lines<D, N, T, 2>(tab, sT, sN, ncl);
       __syncthreads();
     }
-    // ---- D: inverse mass (pointwise FP64 factors), G -> GL
+    // the epilogue's second state operand, requested after the sweep so that
+    // its registers are free during it; its latency overlaps phase D
+    double eb[ES];
+#pragma unroll
+    for (int s = 0; s < ES; ++s) {
+      const int i = tid + s * NT;
+      eb[s] = 0.0;
+      if constexpr (EPI == EPI_ADD)
+        if (i < nel) eb[s] = p.u_base[gofs + i];
+      if constexpr (EPI == EPI_LSRK)
+        if (i < nel && (p.two_r ? !p.first : p.acoef != 0.0)) eb[s] = p.du[gofs + i];
+    }
+    // ---- D: last direction's residual, inverse mass (pointwise FP64
+    // factors) into sT, G -> GL
 #pragma unroll
     for (int s = 0; s < PS; ++s) {
       const int i = tid + s * NT;
       if (i < ncl * NP) {
         const int c = i / NP, q = i - c * NP;
-        T* r = sR + c * NC * NP + q;
+        T* r = sT + c * NC * NP + q;
 #pragma unroll
-        for (int v = 0; v < NC; ++v) r[v * NP] = (T)(g[s][D * D + (v == D)] * (double)r[v * NP]);
+        for (int v = 0; v < NC; ++v) {
+          const T rv = R[s][v] + r[v * NP];
+          r[v * NP] = (T)(g[s][D * D + (v == D)] * (double)rv);
+        }
       }
     }
     __syncthreads();
-    if constexpr (!GB) tensor_apply_inplace<NT, D, N, T>(sR, ncl * NC, tab + tab_Sinv(N));
-    // ---- E: epilogue (coalesced, operands prefetched in A)
+    if constexpr (!GB) tensor_apply_inplace<NT, D, N, T>(sT, ncl * NC, tab + tab_Sinv(N));
+    // ---- E: epilogue (coalesced; u from A, the second operand from D)
     {
       int scell = -1;
       if (p.src.cell) scell = p.src.cell[member];
@@ -614,7 +632,7 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>())))
       for (int s = 0; s < ES; ++s) {
         const int i = tid + s * NT;
         if (i >= nel) continue;
-        const double val = (double)sR[i];
+        const double val = (double)sT[i];
         const int64_t gi = gofs + i;
         if constexpr (EPI == EPI_STORE) {
           p.out[gi] = val;

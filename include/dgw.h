@@ -133,10 +133,12 @@ typedef struct dgw_plane_wave {
  * Gauss points in the same lexicographic order, the mass matrix is diagonal,
  * but a face trace needs the neighbour's whole line of values along the face
  * normal.  Same discrete operator: L_Gauss = S L_GL S^-1 with S the
- * tensor-product interpolation from the GL nodes to the Gauss points.  A
- * Gauss-basis mesh supports dgw_operator_apply and dgw_step_lsrk (no sources)
- * and dgw_step_profile for LSRK, with DGW_FP64 only; every other call on it
- * returns DGW_EUNSUPPORTED. */
+ * tensor-product interpolation from the GL nodes to the Gauss points.  Every
+ * call accepts either basis, in both precisions: states, sums and source
+ * vectors are in the mesh's storage basis.  With DGW_BASIS_GAUSS the ADER TCK
+ * needs no basis change on the way in and evaluates the reduced levels
+ * directly at the Gauss points on the way out, and the energy needs none
+ * either; dgw_mesh_get(DGW_GET_NODE_COORDS) still returns the GL nodes. */
 #define DGW_BASIS_GL 0
 #define DGW_BASIS_GAUSS 1
 

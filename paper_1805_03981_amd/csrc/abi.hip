@@ -242,23 +242,20 @@ static dgw_status check_hdg_faces(const dgw_mesh* m, int flags) {
   return DGW_OK;
 }
 
-// Calls that assume the GL storage basis (the ADER sweeps, sources, energy,
-// the solver loop) reject a Gauss-basis mesh.
-static dgw_status check_gl_basis(const dgw_mesh* m, const char* what) {
-  if (m->basis != DGW_BASIS_GL)
-    return fail(DGW_EUNSUPPORTED, std::string(what) + " needs the GL storage basis (DGW_BASIS_GL)");
-  return DGW_OK;
+// The kernels of the mesh's storage basis.
+static const BasisLaunchers& basis_launchers(const dgw_mesh* m) {
+  return m->L->basis[m->basis == DGW_BASIS_GAUSS ? 1 : 0];
 }
 
 // The operator launcher for epilogue epi and launch shape sel in the mesh's
-// storage basis (only EPI_STORE and EPI_LSRK exist for the Gauss basis).
-// Operator launch shape index: bit 0 selects the compiled cells per
-// workgroup, bit 1 the member-block variant (kMemberBlock batch members per
-// workgroup with the geometry loaded once) instead of one member per group.
+// storage basis.  Operator launch shape index: bit 0 selects the compiled
+// cells per workgroup, bit 1 the member-block variant (kMemberBlock batch
+// members per workgroup with the geometry loaded once; GL storage basis
+// only) instead of one member per group.
 static OpLaunch op_launch(const dgw_mesh* m, int epi, int shape) {
   const int sel = shape & 1;
   if (shape & 2) return m->basis == DGW_BASIS_GAUSS ? nullptr : m->L->op_mb[epi][sel];
-  return m->basis == DGW_BASIS_GAUSS ? m->L->op_gauss[epi][sel] : m->L->op[epi][sel];
+  return basis_launchers(m).op[epi][sel];
 }
 
 // One operator launch; on a mesh with prescribed faces the exterior state
@@ -514,9 +511,9 @@ static dgw_status ader_step(dgw_mesh* m, int flags, int B, const dgw_sources* sr
     DGW_HIP(run_op(m, EPI_STORE, w, s));
     tp.u = I;
     tp.u_base = cur;
-    DGW_HIP(m->L->tck_hdg[sel](tp, s));
+    DGW_HIP(basis_launchers(m).tck_hdg[sel](tp, s));
   } else {
-    DGW_HIP(m->L->tck[period][sel](tp, s));
+    DGW_HIP(basis_launchers(m).tck[period][sel](tp, s));
   }
   OpParams p = op_params(m, B, src);
   p.u = I;
@@ -538,7 +535,7 @@ static dgw_status energy_impl(dgw_mesh* m, const double* u, int B, double* host_
   p.cpw = std::max(1, std::min(16, 16384 / m->L->energy_lds_per_cell));
   p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
   p.B = B;
-  DGW_HIP(m->L->energy(p, s));
+  DGW_HIP(basis_launchers(m).energy(p, s));
   std::vector<double> part((size_t)B * p.groups);
   DGW_HIP(hipMemcpyAsync(part.data(), m->d_partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   DGW_HIP(hipStreamSynchronize(s));
@@ -686,7 +683,7 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
   for (int shape = 0; shape < nshape; ++shape) {
     const int sel = shape & 1;
     if ((int64_t)m->L->cpw[sel] * m->L->op_lds_per_cell <= kLdsLimit) {
-      for (int epi = 0; epi < (gauss ? 2 : 3); ++epi) {
+      for (int epi = 0; epi < 3; ++epi) {
         if (!op_launch(m, epi, shape)) continue;
         OpParams p = op_params(m, B, nullptr);
         p.u = buf[0];
@@ -705,14 +702,14 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
         cands.push_back({&ms[epi][shape], [=]() { return run_op(m, epi, shape, p, s); }, true});
       }
     }
-    if (shape < 2 && !gauss && (int64_t)m->L->cpw[sel] * m->L->tck_lds_per_cell[2] <= kLdsLimit) {
+    if (shape < 2 && (int64_t)m->L->cpw[sel] * m->L->tck_lds_per_cell[2] <= kLdsLimit) {
       TckParams p = tck_params(m, B, nullptr);
       p.cpw = m->L->cpw[sel];
       p.groups = (int)((m->hs.nc + p.cpw - 1) / p.cpw);
       p.u = buf[0];
       p.I = buf[1];
       p.dt = 1e-3;
-      cands.push_back({&ms[3][sel], [=]() { return m->L->tck[2][sel](p, s); }, true});
+      cands.push_back({&ms[3][sel], [=]() { return basis_launchers(m).tck[2][sel](p, s); }, true});
     }
   }
   // round robin over the candidates, keeping each one's fastest round: a
@@ -739,7 +736,6 @@ static dgw_status autotune(dgw_mesh* m, int B, hipStream_t s) {
   for (int e = 0; e < 3; ++e)
     for (int sh = 1; sh < 4; ++sh)
       if (ms[e][sh] < ms[e][r.op[e]]) r.op[e] = sh;
-  if (gauss) r.op[EPI_ADD] = r.op[EPI_STORE];
   r.tck = ms[3][1] < ms[3][0] ? 1 : 0;
   apply_tuning(m, r);
   std::lock_guard<std::mutex> lk(cache_mtx);
@@ -893,8 +889,6 @@ dgw_status dgw_mesh_create(const dgw_mesh_desc* desc, dgw_mesh** out) {
   if (desc->n_cells > (int64_t)1 << 30) return fail(DGW_EUNSUPPORTED, "too many cells");
   if (desc->storage_basis != DGW_BASIS_GL && desc->storage_basis != DGW_BASIS_GAUSS)
     return fail(DGW_EINVAL, "storage_basis must be DGW_BASIS_GL or DGW_BASIS_GAUSS");
-  if (desc->storage_basis == DGW_BASIS_GAUSS && desc->precision != DGW_FP64)
-    return fail(DGW_EUNSUPPORTED, "the Gauss storage basis is built for DGW_FP64 only");
   std::unique_ptr<dgw_mesh> m(new (std::nothrow) dgw_mesh);
   if (!m) return fail(DGW_ENOMEM, "host allocation");
   m->precision = desc->precision;
@@ -1070,7 +1064,6 @@ dgw_status dgw_step_ader(dgw_mesh* m, int flags, double t0, double dt, int nstep
   dgw_status st = check_ader_flags(flags, src);
   if (st) return st;
   if ((st = check_step(m, dt, nsteps, u, work, B, src))) return st;
-  if ((st = check_gl_basis(m, "ADER"))) return st;
   if ((st = check_hdg_faces(m, flags))) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
@@ -1125,7 +1118,6 @@ dgw_status dgw_step_ader_noalloc(dgw_mesh* m, int flags, double t0, double dt, i
   if (!(dt > 0) || !std::isfinite(dt)) return fail(DGW_EINVAL, "dt must be positive and finite");
   if (nsteps < 0) return fail(DGW_EINVAL, "nsteps must be >= 0");
   if ((st = check_batch(m, B, src))) return st;
-  if ((st = check_gl_basis(m, "ADER"))) return st;
   if ((st = check_hdg_faces(m, flags))) return st;
   const int64_t ne = state_elems(m) * B;
   if (2 * ne * (int64_t)sizeof(double) > kNoAllocScratchBytes)
@@ -1163,7 +1155,6 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
   }
   dgw_status st = check_step(m, dt, nsteps, u, work, B, src);
   if (st) return st;
-  if (scheme == DGW_SCHEME_ADER && (st = check_gl_basis(m, "ADER"))) return st;
   if (scheme == DGW_SCHEME_ADER && (st = check_hdg_faces(m, flags))) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
@@ -1244,9 +1235,9 @@ dgw_status dgw_step_profile(dgw_mesh* m, int scheme, int flags, double t0, doubl
       if (!st)
         st = timed(0, [&]() -> dgw_status {
           if (hdg)
-            DGW_HIP(m->L->tck_hdg[sel](tp, s));
+            DGW_HIP(basis_launchers(m).tck_hdg[sel](tp, s));
           else
-            DGW_HIP(m->L->tck[period][sel](tp, s));
+            DGW_HIP(basis_launchers(m).tck[period][sel](tp, s));
           return DGW_OK;
         });
       OpParams p = op_params(m, B, src);
@@ -1328,7 +1319,6 @@ dgw_status dgw_energy(dgw_mesh* m, const double* u, int B, double* host_out, voi
   if (st) return st;
   if (!u || !host_out) return fail(DGW_EINVAL, "NULL argument");
   if ((st = check_batch(m, B, nullptr))) return st;
-  if ((st = check_gl_basis(m, "the energy"))) return st;
   std::lock_guard<std::mutex> lk(m->mtx);
   if ((st = set_device(m))) return st;
   return energy_impl(m, u, B, host_out, (hipStream_t)stream);
@@ -1340,7 +1330,6 @@ dgw_status dgw_sources_create(dgw_mesh* m, const dgw_source_desc* desc, dgw_sour
   *out = nullptr;
   dgw_status st = check_mesh(m);
   if (st) return st;
-  if ((st = check_gl_basis(m, "point sources"))) return st;
   if (!desc || desc->n < 1 || !desc->position || !desc->frequency) return fail(DGW_EINVAL, "bad source desc");
   const auto& hs = m->hs;
   const int d = hs.dim, n = hs.n, np = m->np, ng = ipw(hs.q + 1, d);
@@ -1428,7 +1417,8 @@ dgw_status dgw_sources_create(dgw_mesh* m, const dgw_source_desc* desc, dgw_sour
     DGW_HIP(hipSetDevice(m->device));
     DGW_HIP(hipMemcpy(mu.data(), m->d_cell + ((size_t)found * (d * d + 2) + d * d + 1) * np, np * sizeof(double),
                       hipMemcpyDeviceToHost));
-    // g in the collocated basis: mu_p * l^G(xi_s) / (rho c^2); then S^-1 to GL
+    // g in the collocated basis: mu_p * l^G(xi_s) / (rho c^2); then S^-1 to
+    // GL unless the state is stored at the Gauss points
     std::vector<double> lg((size_t)d * n);
     for (int a = 0; a < d; ++a)
       for (int j = 0; j < n; ++j) lg[a * n + j] = (double)lagrange_value(g.x, j, (long double)xi[a]);
@@ -1469,7 +1459,7 @@ dgw_status dgw_sources_create(dgw_mesh* m, const dgw_source_desc* desc, dgw_sour
       }
       return cur;
     };
-    const std::vector<double> gl = apply(gG, n, tab.data() + tab_Sinv(n), n);
+    const std::vector<double> gl = m->basis == DGW_BASIS_GAUSS ? gG : apply(gG, n, tab.data() + tab_Sinv(n), n);
     std::copy(gl.begin(), gl.end(), gvec.begin() + (size_t)i * np);
     std::copy(gG.begin(), gG.end(), glev[0].begin() + (size_t)i * np);
     for (int l = 1; l < m->nlev; ++l) {
@@ -1511,7 +1501,6 @@ dgw_status dgw_solve_batch(dgw_mesh* m, const dgw_solve_desc* desc, double* u, d
   if (!desc) return fail(DGW_EINVAL, "desc is NULL");
   dgw_status st = check_mesh(m);
   if (st) return st;
-  if ((st = check_gl_basis(m, "dgw_solve_batch (energy watchdog)"))) return st;
   if (desc->scheme != DGW_SCHEME_LSRK54 && desc->scheme != DGW_SCHEME_LSRK59 && desc->scheme != DGW_SCHEME_ADER)
     return fail(DGW_EINVAL, "bad scheme");
   if (desc->scheme == DGW_SCHEME_ADER && (st = check_ader_flags(desc->ader_flags, desc->sources))) return st;

@@ -37,52 +37,49 @@ constexpr OpLaunch member_block_op() {
     return nullptr;
 }
 
-// Gauss storage basis launchers: FP64 arithmetic only.
-template <int D, int N, typename T, int EPI, int SEL>
-constexpr OpLaunch gauss_op() {
-  if constexpr (std::is_same_v<T, double>)
-    return launch_op<D, N, T, EPI, SEL, true>;
-  else
-    return nullptr;
-}
-
-template <int D, int N, typename T, int R, int SEL, bool HDG = false>
+template <int D, int N, typename T, int R, int SEL, bool HDG = false, bool GS = false>
 hipError_t launch_tck(const TckParams& p, hipStream_t s) {
   constexpr int CPW = cells_per_group(D, N, SEL);
   if (p.cpw != CPW) return hipErrorInvalidValue;
   const size_t lds = (size_t)CPW * TckLayout<D, N, T>::bytes_per_cell(R);
-  hipError_t e = ensure_lds(tck_kernel<D, N, T, R, CPW, HDG>, lds);
+  hipError_t e = ensure_lds(tck_kernel<D, N, T, R, CPW, HDG, GS>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((tck_kernel<D, N, T, R, CPW, HDG>), dim3(p.groups * p.B), dim3(tck_threads(D, N)), lds, s, p);
+  hipLaunchKernelGGL((tck_kernel<D, N, T, R, CPW, HDG, GS>), dim3(p.groups * p.B), dim3(tck_threads(D, N)), lds, s,
+                     p);
   return hipGetLastError();
 }
 
-template <int D, int N, typename T>
+template <int D, int N, typename T, bool GS = false>
 hipError_t launch_energy(const EnergyParams& p, hipStream_t s) {
   const size_t lds = (size_t)p.cpw * (D + 1) * ipow(N, D) * sizeof(T);
-  hipError_t e = ensure_lds(energy_kernel<D, N, T>, lds);
+  hipError_t e = ensure_lds(energy_kernel<D, N, T, GS>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((energy_kernel<D, N, T>), dim3(p.groups * p.B), dim3(op_threads(D, N)), lds, s, p);
+  hipLaunchKernelGGL((energy_kernel<D, N, T, GS>), dim3(p.groups * p.B), dim3(op_threads(D, N)), lds, s, p);
   return hipGetLastError();
+}
+
+// Launchers of one storage basis (GS: Gauss): the operator per epilogue, the
+// TCK per reduction period, HDG-ADER and the energy.
+template <int D, int N, typename T, bool GS>
+constexpr BasisLaunchers basis_launchers() {
+  return {{{launch_op<D, N, T, EPI_STORE, 0, GS>, launch_op<D, N, T, EPI_STORE, 1, GS>},
+           {launch_op<D, N, T, EPI_LSRK, 0, GS>, launch_op<D, N, T, EPI_LSRK, 1, GS>},
+           {launch_op<D, N, T, EPI_ADD, 0, GS>, launch_op<D, N, T, EPI_ADD, 1, GS>}},
+          {{launch_tck<D, N, T, 0, 0, false, GS>, launch_tck<D, N, T, 0, 1, false, GS>},
+           {launch_tck<D, N, T, 1, 0, false, GS>, launch_tck<D, N, T, 1, 1, false, GS>},
+           {launch_tck<D, N, T, 2, 0, false, GS>, launch_tck<D, N, T, 2, 1, false, GS>},
+           {launch_tck<D, N, T, 3, 0, false, GS>, launch_tck<D, N, T, 3, 1, false, GS>}},
+          {launch_tck<D, N, T, 2, 0, true, GS>, launch_tck<D, N, T, 2, 1, true, GS>},
+          launch_energy<D, N, T, GS>};
 }
 
 template <int D, int N, typename T>
 const Launchers* make_launchers() {
   static const Launchers L = {
-      {{launch_op<D, N, T, EPI_STORE, 0>, launch_op<D, N, T, EPI_STORE, 1>},
-       {launch_op<D, N, T, EPI_LSRK, 0>, launch_op<D, N, T, EPI_LSRK, 1>},
-       {launch_op<D, N, T, EPI_ADD, 0>, launch_op<D, N, T, EPI_ADD, 1>}},
-      {{gauss_op<D, N, T, EPI_STORE, 0>(), gauss_op<D, N, T, EPI_STORE, 1>()},
-       {gauss_op<D, N, T, EPI_LSRK, 0>(), gauss_op<D, N, T, EPI_LSRK, 1>()}},
+      {basis_launchers<D, N, T, false>(), basis_launchers<D, N, T, true>()},
       {{member_block_op<D, N, T, EPI_STORE, 0>(), member_block_op<D, N, T, EPI_STORE, 1>()},
        {member_block_op<D, N, T, EPI_LSRK, 0>(), member_block_op<D, N, T, EPI_LSRK, 1>()},
        {member_block_op<D, N, T, EPI_ADD, 0>(), member_block_op<D, N, T, EPI_ADD, 1>()}},
-      {{launch_tck<D, N, T, 0, 0>, launch_tck<D, N, T, 0, 1>},
-       {launch_tck<D, N, T, 1, 0>, launch_tck<D, N, T, 1, 1>},
-       {launch_tck<D, N, T, 2, 0>, launch_tck<D, N, T, 2, 1>},
-       {launch_tck<D, N, T, 3, 0>, launch_tck<D, N, T, 3, 1>}},
-      {launch_tck<D, N, T, 2, 0, true>, launch_tck<D, N, T, 2, 1, true>},
-      launch_energy<D, N, T>,
       {cells_per_group(D, N, 0), cells_per_group(D, N, 1)},
       (int)(OpLayout<D, N, T>::per_cell * sizeof(T)),
       {TckLayout<D, N, T>::bytes_per_cell(0), TckLayout<D, N, T>::bytes_per_cell(1),

@@ -727,7 +727,11 @@ __device__ __forceinline__ void tck_load_geo(TckRegs<D, N, CPW, RP>& R, const Tc
   }
 }
 
-template <int D, int N, typename T, int RP, int CPW>
+// GS: the state u and the sum I in the Gauss storage basis (values at the
+// Gauss points, Sec. 3.1): no basis change on the way in, and the final
+// phase evaluates the reduced levels at the level-0 Gauss points instead of
+// the GL nodes, level 0 itself needing no pass.
+template <int D, int N, typename T, int RP, int CPW, bool GS = false>
 struct Tck {
   static constexpr int NC = D + 1, NP = ipow(N, D), G2 = D * D + 2, NT = tck_threads(D, N);
   using Regs = TckRegs<D, N, CPW, RP>;
@@ -942,8 +946,20 @@ struct Tck {
   static constexpr bool FUSED_FINAL = sizeof(T) == 8 && !Regs::ACC_LDS &&
                                       fin_bytes() <= TckLayout<D, N, T>::bytes_per_cell(RP);
 
-  // level L's 1D matrix of the final phase (N x m_L): S^-1 for level 0
+  // first level that the final passes map (the GS level 0 is already at
+  // the level-0 Gauss points)
+  static constexpr int LB = GS ? 1 : 0;
+  // offset of level L in stage `stage` of the final phase: the A stage holds
+  // every level, the later stages the levels from LB on
+  static constexpr int stage_off(int stage, int L) {
+    return CPW * NC * (fin_off(stage, L) - (stage == 0 ? 0 : fin_off(stage, LB)));
+  }
+
+  // level L's 1D matrix of the final phase (N x m_L): S^-1 for level 0; in
+  // the Gauss storage basis the level-L Gauss interpolant at the level-0
+  // Gauss points
   __device__ static __forceinline__ const double* qmat(int L) {
+    if constexpr (GS) return ctab<double>(N) + tab_level_G(N, L, RP);
     return L == 0 ? ctab<double>(N) + tab_Sinv(N) : ctab<double>(N) + tab_level_Q(N, L, RP);
   }
 
@@ -951,7 +967,7 @@ struct Tck {
   __device__ static __forceinline__ void fin_write_A(double* A, Regs& R, int ncl) {
     if constexpr (L < NLV_ALL) {
       constexpr int NPL = ipow(mlev(L), D);
-      double* a = A + CPW * NC * fin_off(0, L);
+      double* a = A + stage_off(0, L);
 #pragma unroll
       for (int s = 0; s < psl(L); ++s) {
         const int i = threadIdx.x + s * NT;
@@ -965,15 +981,16 @@ struct Tck {
     }
   }
 
-  // pass along DIR (0: x, 1: y) of every level, from stage DIR to stage DIR+1
+  // pass along DIR (0: x, 1: y) of every level from LB on, from stage DIR to
+  // stage DIR+1
   template <int DIR, int L>
   __device__ static __forceinline__ void fin_pass(const double* in, double* out, int ncl) {
     if constexpr (L < NLV_ALL) {
       constexpr int m = mlev(L);
       // extents of the input: direction < DIR already N, the others m
       using P = Pass<D, DIR, m, N, (DIR > 0 ? N : m), (DIR > 1 ? N : m), m>;
-      const double* src0 = in + CPW * NC * fin_off(DIR, L);
-      double* dst0 = out + CPW * NC * fin_off(DIR + 1, L);
+      const double* src0 = in + stage_off(DIR, L);
+      double* dst0 = out + stage_off(DIR + 1, L);
       const double* Q = qmat(L);
       for (int w = threadIdx.x; w < ncl * NC * P::NL; w += NT) {
         const int sl = w / P::NL;
@@ -994,13 +1011,13 @@ struct Tck {
     }
   }
 
-  // last direction: sum over the levels of Q_L along D-1, into acc
+  // last direction: sum over the levels from LB on of Q_L along D-1, into acc
   template <int L>
   __device__ static __forceinline__ void fin_last(const double* in, int sl, int t, double (&acc)[N]) {
     if constexpr (L < NLV_ALL) {
       constexpr int m = mlev(L);
       constexpr int SL = ipow(N, D - 1) * m;  // elements of one slice of this level
-      const double* src = in + CPW * NC * fin_off(D - 1, L) + sl * SL + t;
+      const double* src = in + stage_off(D - 1, L) + sl * SL + t;
       const double* Q = qmat(L);
 #pragma unroll
       for (int j = 0; j < m; ++j) {
@@ -1012,22 +1029,35 @@ struct Tck {
     }
   }
 
-  // the whole final phase; smem holds at least fin_bytes() per cell
+  // stage layout of the final phase (elements per cell and component):
+  // GL: A and U share the start, T follows; GS: A (with level 0, read at
+  // the end), then T and U of the levels from 1 on
+  static constexpr int fin_T_at() {
+    const int EA = fin_elems(0), EU = D == 3 ? fin_elems(2) : 0;
+    return GS ? EA : (EA > EU ? EA : EU);
+  }
+  static constexpr int fin_U_at() { return GS ? fin_elems(0) + fin_elems(1) - fin_off(1, 1) : 0; }
+  static constexpr int fin_used() {
+    if (!GS) return fin_bytes() / (8 * NC);
+    return fin_U_at() + (D == 3 ? fin_elems(2) - fin_off(2, 1) : 0);
+  }
+  static_assert(!FUSED_FINAL || 8 * NC * fin_used() <= TckLayout<D, N, T>::bytes_per_cell(RP),
+                "final phase stages exceed the LDS of the cell");
+
+  // the whole final phase; smem holds fin_used() elements per cell and component
   template <bool HDG_ADD>
   __device__ static __forceinline__ void final_fused(const TckParams& p, double* sm, Regs& R, int ncl,
                                                      int64_t gofs) {
-    constexpr int EA = fin_elems(0), ET = fin_elems(1), EU = D == 3 ? fin_elems(2) : 0;
-    constexpr int LOW = (EA > EU ? EA : EU) * CPW * NC;  // A and U share the start, T follows
     double* A = sm;
-    double* Tt = sm + LOW;
-    double* U = sm;
+    double* Tt = sm + fin_T_at() * CPW * NC;
+    double* U = sm + fin_U_at() * CPW * NC;
     fin_write_A<0>(A, R, ncl);
     __syncthreads();
-    fin_pass<0, 0>(A, Tt, ncl);
+    fin_pass<0, LB>(A, Tt, ncl);
     __syncthreads();
     const double* last = Tt;
     if constexpr (D == 3) {
-      fin_pass<1, 0>(Tt, U, ncl);
+      fin_pass<1, LB>(Tt, U, ncl);
       __syncthreads();
       last = U;
     }
@@ -1040,7 +1070,11 @@ struct Tck {
       double acc[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) acc[i] = 0.0;
-      fin_last<0>(last, sl, t, acc);
+      fin_last<LB>(last, sl, t, acc);
+      if constexpr (GS) {  // level 0 is already at the Gauss points
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] += A[sl * NP + t + i * ST];
+      }
       const int64_t g0 = gofs + (int64_t)sl * NP + t;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
@@ -1100,11 +1134,12 @@ constexpr int tck_waves_per_simd() {
 // HDG = true: the HDG-ADER variant (Sec. 2.4, eq. hdg-ader).  p.u holds the
 // DG derivative W = L u (the first time derivative), the recursion starts at
 // the second derivative, and I = dt u + sum_{m>=1} dt^{m+1}/(m+1)! ut^m with
-// the dt u term added in the GL basis from p.u_base.
-template <int D, int N, typename T, int RP, int CPW, bool HDG = false>
+// the dt u term added in the storage basis from p.u_base.  GS: u and I in
+// the Gauss storage basis (no basis change in, none out).
+template <int D, int N, typename T, int RP, int CPW, bool HDG = false, bool GS = false>
 __global__ void __launch_bounds__(tck_threads(D, N))
 __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck_kernel(TckParams p) {
-  using K = Tck<D, N, T, RP, CPW>;
+  using K = Tck<D, N, T, RP, CPW, GS>;
   using Regs = TckRegs<D, N, CPW, RP>;
   constexpr int NC = D + 1, NP = ipow(N, D), NT = tck_threads(D, N);
   constexpr int ES = cdiv(CPW * NC * NP, NT);
@@ -1145,7 +1180,7 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck
     if (i < nel) C[i] = (T)ev[s];
   }
   __syncthreads();
-  tensor_apply_inplace<NT, D, N, T>(C, ncl * NC, tab + tab_S(N));
+  if constexpr (!GS) tensor_apply_inplace<NT, D, N, T>(C, ncl * NC, tab + tab_S(N));
   // first term of the sum: dt u_G (ADER), dt^2/2 W_G (HDG-ADER)
   const double c0 = HDG ? 0.5 * p.dt * p.dt : p.dt;
 #pragma unroll
@@ -1165,7 +1200,8 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck
   if constexpr (K::FUSED_FINAL) {
     K::template final_fused<HDG>(p, reinterpret_cast<double*>(smem), R, ncl, gofs);
   } else {
-    // collapse the coarser levels into level 0, add A_0 in FP64, then G -> GL in FP64
+    // collapse the coarser levels into level 0, add A_0 in FP64, then G -> GL
+    // in FP64 (GL storage basis)
     K::template collapse<Regs::NLV - 1>(p, C, Db, R, ncl);
     double* sI = reinterpret_cast<double*>(Db[0]);  // FP64 tile over the derivative tiles
 #pragma unroll
@@ -1181,7 +1217,7 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck
       }
     }
     __syncthreads();
-    tensor_apply_inplace<NT, D, N, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
+    if constexpr (!GS) tensor_apply_inplace<NT, D, N, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
     if constexpr (HDG) {
       for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i] + p.dt * p.u_base[gofs + i];
     } else {
@@ -1191,9 +1227,10 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck
 }
 
 // ------------------------------------------------------------------------
-// Energy sum_q |v|^2 / mu_v + p^2 / mu_p at the Gauss points (per group).
+// Energy sum_q |v|^2 / mu_v + p^2 / mu_p at the Gauss points (per group);
+// GS: the state is already at the Gauss points.
 // ------------------------------------------------------------------------
-template <int D, int N, typename T>
+template <int D, int N, typename T, bool GS = false>
 __global__ void __launch_bounds__(op_threads(D, N)) energy_kernel(EnergyParams p) {
   constexpr int NC = D + 1, NP = ipow(N, D), NT = op_threads(D, N);
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1208,7 +1245,7 @@ __global__ void __launch_bounds__(op_threads(D, N)) energy_kernel(EnergyParams p
   const int64_t gofs = (int64_t)member * p.nc * NC * NP + cell0 * NC * NP;
   for (int i = threadIdx.x; i < ncl * NC * NP; i += NT) sU[i] = (T)p.u[gofs + i];
   __syncthreads();
-  tensor_apply_inplace<NT, D, N, T>(sU, ncl * NC, tab + tab_S(N));
+  if constexpr (!GS) tensor_apply_inplace<NT, D, N, T>(sU, ncl * NC, tab + tab_S(N));
   double acc = 0.0;
   for (int i = threadIdx.x; i < ncl * NC * NP; i += NT) {
     const int q = i % NP;

@@ -263,19 +263,118 @@ def test_lsrk_gauss_basis_fp64(gpu_lib, scheme):
     close(u[0].cpu().numpy(), want, TOL)
 
 
-def test_gauss_basis_rejects_gl_only_calls(gpu_lib):
-    say("gauss rejects")
+GAUSS_ADER_CASES = [(3, 3, 4, "reduce", None), (3, 2, 5, "reduce", ("wall", "periodic", "absorbing")),
+                    (2, 3, 3, "reduce", None), (3, 2, 5, "noreduce", None), (3, 2, 5, "every_step", None),
+                    (3, 2, 6, "every_third", None), (3, 2, 7, "reduce", None), (3, 2, 8, "reduce", None),
+                    (2, 3, 1, "reduce", None), (3, 2, 3, "hdg", None), (2, 3, 5, "hdg", None)]
+
+
+def _ader_variant(B, variant):
+    """(step flags, oracle step) of an ADER variant"""
+    if variant == "hdg":
+        return B.ADER_HDG, lambda om, x, dt: ader.hdg_ader_step(om, x, dt)
+    flags = {"reduce": 0, "noreduce": B.ADER_NOREDUCE, "every_step": B.ADER_REDUCE_EVERY_STEP,
+             "every_third": B.ADER_REDUCE_EVERY_THIRD}[variant]
+    kw = {"reduce": {}, "noreduce": {"reduce": False}, "every_step": {"period": 1},
+          "every_third": {"period": 3}}[variant]
+    return flags, lambda om, x, dt: ader.ader_step(om, x, dt, **kw)
+
+
+@pytest.mark.parametrize("dim,nc,k,variant,bc", GAUSS_ADER_CASES)
+def test_ader_gauss_basis_fp64(gpu_lib, dim, nc, k, variant, bc):
+    """ADER with the state stored at the Gauss points (Sec. 3.1: the TCK needs
+    no basis change in or out, the update sweep reads the neighbours' normal
+    lines): two steps from the Gauss values of a state against the oracle's
+    GL steps mapped to the Gauss points by its own S.  Every reduction period,
+    HDG-ADER, the fused (k <= 5) and unfused (k = 7, 8) final phases."""
+    say("ader gauss", dim, nc, k, variant, bc)
     B = gpu_lib
-    gm, om = build_gauss(B, 3, 2, 3, None, False, 0)
-    u = to_dev(np.zeros((1,) + gm.shape))
-    for call in (lambda: gm.step_ader(u, 0.0, 0.01, 1), lambda: gm.energy(u),
-                 lambda: gm.solve(u, B.LSRK54, 0.01, dt=0.005), lambda: B.Sources(gm, [[0.5, 0.5, 0.5]], 8.0),
-                 lambda: gm.profile(u, B.ADER, 0.0, 0.01, 1)):
-        with pytest.raises(B.DgwError) as e:
-            call()
-        assert e.value.status == B.EUNSUPPORTED
-    prof = gm.profile(u, B.LSRK54, 0.0, 0.01, 1)  # LSRK profiling works
-    assert prof is not None
+    gm, om = build_gauss(B, dim, nc, k, bc, False, 0)
+    U = om.interpolate(lambda x: W.gaussian_pulse(x, [0.6] * dim, 0.15))
+    U = U + 0.01 * W.random_state(41 + k, U.shape)
+    dt = 0.2 * gm.info.dt_unit
+    flags, step = _ader_variant(B, variant)
+    u = to_dev(gl_to_gauss(om, U))[None]
+    gm.step_ader(u, 0.0, dt, 2, flags=flags)
+    want = U
+    for s in range(2):
+        want = step(om, want, dt)
+    close(u[0].cpu().numpy(), gl_to_gauss(om, want), TOL)
+
+
+def test_gauss_basis_sources_energy_solver(gpu_lib):
+    """The Gauss storage basis through every entry point: the energy of the
+    same polynomial, point sources in LSRK and ADER steps against the oracle,
+    the solver loop (hipGraph replay, energy watchdog) equal to the eager
+    steps bitwise, and the per-kernel profile."""
+    say("gauss sources energy solver")
+    B = gpu_lib
+    dim, nc, k, Bn = 3, 3, 3, 2
+    mat = W.FourierMaterial(11, dim=dim, rho_amp=RHO_AMP)
+    nodes, nb = W.box_nodes(dim, nc, k, 0.05), W.box_neighbors(dim, nc, None)
+    gm = B.Mesh(dim, k, nodes, nb, mat, max_batch=Bn, storage_basis=B.BASIS_GAUSS)
+    om = OMesh(dim, k, nodes, nb, mat)
+    U = W.random_state(5, (om.nc, dim + 1, om.np_))
+    e = gm.energy(to_dev(gl_to_gauss(om, U))[None])[0]
+    assert abs(e - norms.energy_norm2(om, U)) < 1e-12 * abs(e)
+    pos = W.random_points(31, Bn, dim)
+    src = B.Sources(gm, pos, frequency=4.0, amplitude=[1.0, 2.5])
+    dt, t0 = 0.2 * gm.info.dt_unit, 0.25
+    for scheme in ("lsrk", "ader"):
+        u = to_dev(np.zeros((Bn, om.nc, dim + 1, om.np_)))
+        if scheme == "lsrk":
+            gm.step_lsrk(u, t0, dt, 2, sources=src, B=Bn)
+        else:
+            gm.step_ader(u, t0, dt, 2, sources=src, B=Bn)
+        for b in range(Bn):
+            ps = osrc.PointSource(om, pos[b], osrc.Ricker(f=4.0, amp=[1.0, 2.5][b]))
+            want = np.zeros((om.nc, dim + 1, om.np_))
+            for s in range(2):
+                t = t0 + s * dt
+                if scheme == "lsrk":
+                    want = ts.lsrk_step(lambda x, tt: apply_operator(om, x) + ps.rhs(om, tt), want, t, dt)
+                else:
+                    want = ader.ader_step(om, want, dt, source=ps, t=t)
+            assert np.abs(want).max() > 0
+            close(u[b].cpu().numpy(), gl_to_gauss(om, want), 1e-11, f"gauss sources {scheme} {b}")
+    V = gl_to_gauss(om, om.interpolate(lambda x: W.gaussian_pulse(x, [0.4] * dim, 0.15)))
+    a = to_dev(V)[None]
+    c = to_dev(V)[None]
+    gm.step_ader(a, 0.0, dt, 4)
+    rep = gm.solve(c, B.ADER, t_end=4 * dt, dt=dt, use_graph=True, watchdog_every=2)
+    assert rep.steps == 4
+    assert torch.equal(a, c)
+    prof = gm.profile(to_dev(V)[None], B.ADER, 0.0, dt, 1)
+    assert set(prof) == {"tck", "operator_ader_update"}
+
+
+def test_gauss_basis_fp32_split_error_stated(gpu_lib):
+    """FP32-split arithmetic with the state at the Gauss points: parity
+    unpinned, the error of three ADER and three LSRK(5,4) steps against the
+    oracle's FP64 steps (mapped by S) stays at the single-precision level."""
+    say("gauss fp32 split")
+    B = gpu_lib
+    dim, nc, k = 3, 3, 4
+    mat = W.FourierMaterial(17, dim=dim, rho_amp=RHO_AMP)
+    nodes, nb = W.box_nodes(dim, nc, k, 0.05), W.box_neighbors(dim, nc, None)
+    gm = B.Mesh(dim, k, nodes, nb, mat, precision=B.FP32_SPLIT, storage_basis=B.BASIS_GAUSS)
+    om = OMesh(dim, k, nodes, nb, mat)
+    U = om.interpolate(lambda x: W.gaussian_pulse(x, [0.5] * dim, 0.2))
+    dt = 0.2 * gm.info.dt_unit
+    for scheme in ("ader", "lsrk"):
+        u = to_dev(gl_to_gauss(om, U))[None]
+        w = U
+        if scheme == "ader":
+            gm.step_ader(u, 0.0, dt, 3)
+            for s in range(3):
+                w = ader.ader_step(om, w, dt)
+        else:
+            gm.step_lsrk(u, 0.0, dt, 3)
+            for s in range(3):
+                w = ts.lsrk_step(lambda x, t: apply_operator(om, x), w, s * dt, dt)
+        err = rel(u[0].cpu().numpy(), gl_to_gauss(om, w))
+        say(f"gauss fp32 split {scheme} 3 steps rel err", err)
+        assert 0 < err < 1e-6
 
 
 def _pw(dim):

@@ -559,7 +559,7 @@ def ablations(steps=10, warmup=2):
     operator (Sec. 3.1): GL nodes with the basis change inside the kernel
     against Lagrange polynomials in the Gauss points (no basis change,
     diagonal mass, whole neighbour lines read for the face traces), for the
-    operator alone and for the LSRK step.  Per variant: ms per step
+    operator alone, the LSRK step and the ADER step.  Per variant: ms per step
     and the mean duration of each component."""
     import torch
     from paper_1805_03981_amd import binding as dg
@@ -609,19 +609,23 @@ def ablations(steps=10, warmup=2):
         log(f"[bench] ablation operator_{basis_name}_basis: {out[f'operator_{basis_name}_basis']}")
         if sb == dg.BASIS_GAUSS:
             w2 = m2.work(1)
-            dt = CR["lsrk"] * m2.info.dt_unit
-            u = v0.clone()
-            m2.step_lsrk(u, 0.0, dt, warmup, work=w2)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            m2.step_lsrk(u, 0.0, dt, steps, work=w2)
-            torch.cuda.synchronize()
-            ms = 1e3 * (time.perf_counter() - t0) / steps
-            prof = m2.profile(v0.clone(), dg.LSRK54, 0.0, dt, 3, work=w2)
-            out["lsrk_fused_gauss_basis"] = {"ms_per_step": ms, "dof_steps_per_s": m2.info.dofs / (ms * 1e-3),
-                                             "components_ms": {k: v[0] for k, v in prof.items()},
-                                             "launches_per_step": {k: v[1] / 3 for k, v in prof.items()}}
-            log(f"[bench] ablation lsrk_fused_gauss_basis: {out['lsrk_fused_gauss_basis']}")
+            # the fused LSRK step and the ADER step with the state at the Gauss points
+            for name, scheme in (("lsrk_fused_gauss_basis", dg.LSRK54), ("ader_gauss_basis", dg.ADER)):
+                dt = CR["ader" if scheme == dg.ADER else "lsrk"] * m2.info.dt_unit
+                u = v0.clone()
+                step = (lambda n: m2.step_ader(u, 0.0, dt, n, work=w2)) if scheme == dg.ADER else \
+                    (lambda n: m2.step_lsrk(u, 0.0, dt, n, work=w2))
+                step(warmup)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                step(steps)
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0) / steps
+                prof = m2.profile(v0.clone(), scheme, 0.0, dt, 3, work=w2)
+                out[name] = {"ms_per_step": ms, "dof_steps_per_s": m2.info.dofs / (ms * 1e-3),
+                             "components_ms": {k: v[0] for k, v in prof.items()},
+                             "launches_per_step": {k: v[1] / 3 for k, v in prof.items()}}
+                log(f"[bench] ablation {name}: {out[name]}")
             del m2, v0, u, w2, r
             torch.cuda.empty_cache()
     return out

@@ -134,11 +134,13 @@ typedef struct dgw_plane_wave {
  * but a face trace needs the neighbour's whole line of values along the face
  * normal.  Same discrete operator: L_Gauss = S L_GL S^-1 with S the
  * tensor-product interpolation from the GL nodes to the Gauss points.  Every
- * call accepts either basis, in both precisions: states, sums and source
- * vectors are in the mesh's storage basis.  With DGW_BASIS_GAUSS the ADER TCK
- * needs no basis change on the way in and evaluates the reduced levels
- * directly at the Gauss points on the way out, and the energy needs none
- * either; dgw_mesh_get(DGW_GET_NODE_COORDS) still returns the GL nodes. */
+ * call accepts either basis, in both precisions: states and source vectors
+ * are in the mesh's storage basis.  With DGW_BASIS_GAUSS the ADER TCK reads
+ * u without a basis change, its sum I (in the work buffer) stays in the GL
+ * basis so that the update sweep gathers the neighbours' face nodes as with
+ * GL storage, and the update writes u at the Gauss points without the final
+ * basis change; the energy needs none either.
+ * dgw_mesh_get(DGW_GET_NODE_COORDS) returns the GL nodes in both cases. */
 #define DGW_BASIS_GL 0
 #define DGW_BASIS_GAUSS 1
 

@@ -92,7 +92,7 @@ using EnergyLaunch = hipError_t (*)(const EnergyParams&, hipStream_t);
 
 // Kernels are compiled for two launch shapes (sel 0/1: cells per workgroup
 // cpw[sel]); p.cpw must equal cpw[sel] of the launcher that is called.
-// the kernels of one storage basis
+// The kernels of one storage basis.
 struct BasisLaunchers {
   OpLaunch op[3][2];      // [Epilogue][sel]
   TckLaunch tck[4][2];    // [reduction period 0 (none), 1, 2 (Alg. 3), 3][sel]
@@ -119,8 +119,7 @@ const Launchers* launchers(int dim, int n, int precision);
 // collocation derivative, P_l (m x mp) projection from level l-1, E_l
 // (mp x m) interpolation back to level l-1, F_l (m x n) evaluation of a
 // level-0 Gauss polynomial at the level-l points, Q_l (n x m) evaluation of
-// a level-l Gauss polynomial at the n GL nodes, G_l (n x m) its evaluation
-// at the n level-0 Gauss points.
+// a level-l Gauss polynomial at the n GL nodes.
 __host__ __device__ constexpr int tab_S(int) { return 0; }
 __host__ __device__ constexpr int tab_Sinv(int n) { return n * n; }
 __host__ __device__ constexpr int tab_D(int n) { return 2 * n * n; }
@@ -132,7 +131,7 @@ __host__ __device__ constexpr int levels_block(int n, int r) {
   int sz = 0;
   for (int l = 1; l < num_levels_r(n, r); ++l) {
     const int m = n - r * l, mp = m + r;
-    sz += m * m + m * mp + mp * m + 3 * m * n;
+    sz += m * m + m * mp + mp * m + 2 * m * n;
   }
   return sz;
 }
@@ -144,7 +143,7 @@ __host__ __device__ constexpr int tab_level(int n, int l, int r = 2) {
   int off = tab_levels_start(n, r);
   for (int j = 1; j < l; ++j) {
     const int m = n - r * j, mp = m + r;
-    off += m * m + m * mp + mp * m + 3 * m * n;
+    off += m * m + m * mp + mp * m + 2 * m * n;
   }
   return off;
 }
@@ -159,7 +158,6 @@ __host__ __device__ constexpr int tab_level_F(int n, int l, int r = 2) {
   return tab_level_E(n, l, r) + (n - r * (l - 1)) * (n - r * l);
 }
 __host__ __device__ constexpr int tab_level_Q(int n, int l, int r = 2) { return tab_level_F(n, l, r) + (n - r * l) * n; }
-__host__ __device__ constexpr int tab_level_G(int n, int l, int r = 2) { return tab_level_Q(n, l, r) + n * (n - r * l); }
 __host__ __device__ constexpr int num_levels(int n) { return num_levels_r(n, 2); }  // n, n-2, ... >= 1
 __host__ __device__ constexpr int tab_size(int n) { return tab_levels_start(n, 3) + levels_block(n, 3); }
 // All degrees share one constant-memory table: n = 2..9 back to back.

@@ -14,16 +14,16 @@ static hipError_t ensure_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int D, int N, typename T, int EPI, int SEL, bool GB = false, int MB = 1>
+template <int D, int N, typename T, int EPI, int SEL, bool GB = false, int MB = 1, bool GOUT = GB>
 hipError_t launch_op(const OpParams& p, hipStream_t s) {
   constexpr int CPW = cells_per_group(D, N, SEL);
   if (p.cpw != CPW) return hipErrorInvalidValue;
   const size_t lds = (size_t)CPW * OpLayout<D, N, T>::per_cell * sizeof(T);
-  hipError_t e = ensure_lds(op_kernel<D, N, T, EPI, CPW, GB, MB>, lds);
+  hipError_t e = ensure_lds(op_kernel<D, N, T, EPI, CPW, GB, MB, GOUT>, lds);
   if (e != hipSuccess) return e;
   const int nmb = (p.B + MB - 1) / MB;
-  hipLaunchKernelGGL((op_kernel<D, N, T, EPI, CPW, GB, MB>), dim3(p.groups * nmb), dim3(op_threads(D, N)), lds, s,
-                     p);
+  hipLaunchKernelGGL((op_kernel<D, N, T, EPI, CPW, GB, MB, GOUT>), dim3(p.groups * nmb), dim3(op_threads(D, N)),
+                     lds, s, p);
   return hipGetLastError();
 }
 
@@ -59,12 +59,14 @@ hipError_t launch_energy(const EnergyParams& p, hipStream_t s) {
 }
 
 // Launchers of one storage basis (GS: Gauss): the operator per epilogue, the
-// TCK per reduction period, HDG-ADER and the energy.
+// TCK per reduction period, HDG-ADER and the energy.  In the Gauss basis the
+// ADER update reads the TCK sum I in the GL basis (the face nodes of the
+// neighbours, as with GL storage) and writes u at the Gauss points.
 template <int D, int N, typename T, bool GS>
 constexpr BasisLaunchers basis_launchers() {
   return {{{launch_op<D, N, T, EPI_STORE, 0, GS>, launch_op<D, N, T, EPI_STORE, 1, GS>},
            {launch_op<D, N, T, EPI_LSRK, 0, GS>, launch_op<D, N, T, EPI_LSRK, 1, GS>},
-           {launch_op<D, N, T, EPI_ADD, 0, GS>, launch_op<D, N, T, EPI_ADD, 1, GS>}},
+           {launch_op<D, N, T, EPI_ADD, 0, false, 1, GS>, launch_op<D, N, T, EPI_ADD, 1, false, 1, GS>}},
           {{launch_tck<D, N, T, 0, 0, false, GS>, launch_tck<D, N, T, 0, 1, false, GS>},
            {launch_tck<D, N, T, 1, 0, false, GS>, launch_tck<D, N, T, 1, 1, false, GS>},
            {launch_tck<D, N, T, 2, 0, false, GS>, launch_tck<D, N, T, 2, 1, false, GS>},

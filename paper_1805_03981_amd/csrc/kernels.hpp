@@ -329,12 +329,15 @@ __device__ __forceinline__ void op_points(const double (&g)[PS][D * D + 2], cons
   }
 }
 
-// GB selects the storage basis of u and of the result: false = Lagrange
-// polynomials in the GL points (nodes on the faces; the operator changes to
-// the Gauss basis and back), true = Lagrange polynomials in the Gauss points
-// (the collocated basis of Sec. 3.1: no basis change, diagonal mass, but a
-// neighbour's trace needs its whole line of values along the face normal).
-template <int D, int N, typename T, int EPI, int CPW, bool GB = false, int MB = 1>
+// GB selects the storage basis of u: false = Lagrange polynomials in the GL
+// points (nodes on the faces; the operator changes to the Gauss basis and
+// back), true = Lagrange polynomials in the Gauss points (the collocated
+// basis of Sec. 3.1: no basis change, diagonal mass, but a neighbour's trace
+// needs its whole line of values along the face normal).  GOUT: the result
+// (and the epilogue's other state operands) at the Gauss points, without
+// the final G -> GL passes; the ADER update of a Gauss-basis mesh reads the
+// TCK sum I in the GL basis and writes u at the Gauss points.
+template <int D, int N, typename T, int EPI, int CPW, bool GB = false, int MB = 1, bool GOUT = GB>
 __global__ void __launch_bounds__(op_threads(D, N))
 __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>()))) op_kernel(OpParams p) {
   using Lay = OpLayout<D, N, T>;
@@ -616,7 +619,7 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>())))
       }
     }
     __syncthreads();
-    if constexpr (!GB) tensor_apply_inplace<NT, D, N, T>(sT, ncl * NC, tab + tab_Sinv(N));
+    if constexpr (!GOUT) tensor_apply_inplace<NT, D, N, T>(sT, ncl * NC, tab + tab_Sinv(N));
     // ---- E: epilogue (coalesced; u from A, the second operand from D)
     {
       int scell = -1;
@@ -727,11 +730,7 @@ __device__ __forceinline__ void tck_load_geo(TckRegs<D, N, CPW, RP>& R, const Tc
   }
 }
 
-// GS: the state u and the sum I in the Gauss storage basis (values at the
-// Gauss points, Sec. 3.1): no basis change on the way in, and the final
-// phase evaluates the reduced levels at the level-0 Gauss points instead of
-// the GL nodes, level 0 itself needing no pass.
-template <int D, int N, typename T, int RP, int CPW, bool GS = false>
+template <int D, int N, typename T, int RP, int CPW>
 struct Tck {
   static constexpr int NC = D + 1, NP = ipow(N, D), G2 = D * D + 2, NT = tck_threads(D, N);
   using Regs = TckRegs<D, N, CPW, RP>;
@@ -946,20 +945,8 @@ struct Tck {
   static constexpr bool FUSED_FINAL = sizeof(T) == 8 && !Regs::ACC_LDS &&
                                       fin_bytes() <= TckLayout<D, N, T>::bytes_per_cell(RP);
 
-  // first level that the final passes map (the GS level 0 is already at
-  // the level-0 Gauss points)
-  static constexpr int LB = GS ? 1 : 0;
-  // offset of level L in stage `stage` of the final phase: the A stage holds
-  // every level, the later stages the levels from LB on
-  static constexpr int stage_off(int stage, int L) {
-    return CPW * NC * (fin_off(stage, L) - (stage == 0 ? 0 : fin_off(stage, LB)));
-  }
-
-  // level L's 1D matrix of the final phase (N x m_L): S^-1 for level 0; in
-  // the Gauss storage basis the level-L Gauss interpolant at the level-0
-  // Gauss points
+  // level L's 1D matrix of the final phase (N x m_L): S^-1 for level 0
   __device__ static __forceinline__ const double* qmat(int L) {
-    if constexpr (GS) return ctab<double>(N) + tab_level_G(N, L, RP);
     return L == 0 ? ctab<double>(N) + tab_Sinv(N) : ctab<double>(N) + tab_level_Q(N, L, RP);
   }
 
@@ -967,7 +954,7 @@ struct Tck {
   __device__ static __forceinline__ void fin_write_A(double* A, Regs& R, int ncl) {
     if constexpr (L < NLV_ALL) {
       constexpr int NPL = ipow(mlev(L), D);
-      double* a = A + stage_off(0, L);
+      double* a = A + CPW * NC * fin_off(0, L);
 #pragma unroll
       for (int s = 0; s < psl(L); ++s) {
         const int i = threadIdx.x + s * NT;
@@ -981,16 +968,15 @@ struct Tck {
     }
   }
 
-  // pass along DIR (0: x, 1: y) of every level from LB on, from stage DIR to
-  // stage DIR+1
+  // pass along DIR (0: x, 1: y) of every level, from stage DIR to stage DIR+1
   template <int DIR, int L>
   __device__ static __forceinline__ void fin_pass(const double* in, double* out, int ncl) {
     if constexpr (L < NLV_ALL) {
       constexpr int m = mlev(L);
       // extents of the input: direction < DIR already N, the others m
       using P = Pass<D, DIR, m, N, (DIR > 0 ? N : m), (DIR > 1 ? N : m), m>;
-      const double* src0 = in + stage_off(DIR, L);
-      double* dst0 = out + stage_off(DIR + 1, L);
+      const double* src0 = in + CPW * NC * fin_off(DIR, L);
+      double* dst0 = out + CPW * NC * fin_off(DIR + 1, L);
       const double* Q = qmat(L);
       for (int w = threadIdx.x; w < ncl * NC * P::NL; w += NT) {
         const int sl = w / P::NL;
@@ -1011,13 +997,13 @@ struct Tck {
     }
   }
 
-  // last direction: sum over the levels from LB on of Q_L along D-1, into acc
+  // last direction: sum over the levels of Q_L along D-1, into acc
   template <int L>
   __device__ static __forceinline__ void fin_last(const double* in, int sl, int t, double (&acc)[N]) {
     if constexpr (L < NLV_ALL) {
       constexpr int m = mlev(L);
       constexpr int SL = ipow(N, D - 1) * m;  // elements of one slice of this level
-      const double* src = in + stage_off(D - 1, L) + sl * SL + t;
+      const double* src = in + CPW * NC * fin_off(D - 1, L) + sl * SL + t;
       const double* Q = qmat(L);
 #pragma unroll
       for (int j = 0; j < m; ++j) {
@@ -1029,35 +1015,22 @@ struct Tck {
     }
   }
 
-  // stage layout of the final phase (elements per cell and component):
-  // GL: A and U share the start, T follows; GS: A (with level 0, read at
-  // the end), then T and U of the levels from 1 on
-  static constexpr int fin_T_at() {
-    const int EA = fin_elems(0), EU = D == 3 ? fin_elems(2) : 0;
-    return GS ? EA : (EA > EU ? EA : EU);
-  }
-  static constexpr int fin_U_at() { return GS ? fin_elems(0) + fin_elems(1) - fin_off(1, 1) : 0; }
-  static constexpr int fin_used() {
-    if (!GS) return fin_bytes() / (8 * NC);
-    return fin_U_at() + (D == 3 ? fin_elems(2) - fin_off(2, 1) : 0);
-  }
-  static_assert(!FUSED_FINAL || 8 * NC * fin_used() <= TckLayout<D, N, T>::bytes_per_cell(RP),
-                "final phase stages exceed the LDS of the cell");
-
-  // the whole final phase; smem holds fin_used() elements per cell and component
+  // the whole final phase; smem holds at least fin_bytes() per cell
   template <bool HDG_ADD>
   __device__ static __forceinline__ void final_fused(const TckParams& p, double* sm, Regs& R, int ncl,
                                                      int64_t gofs) {
+    constexpr int EA = fin_elems(0), ET = fin_elems(1), EU = D == 3 ? fin_elems(2) : 0;
+    constexpr int LOW = (EA > EU ? EA : EU) * CPW * NC;  // A and U share the start, T follows
     double* A = sm;
-    double* Tt = sm + fin_T_at() * CPW * NC;
-    double* U = sm + fin_U_at() * CPW * NC;
+    double* Tt = sm + LOW;
+    double* U = sm;
     fin_write_A<0>(A, R, ncl);
     __syncthreads();
-    fin_pass<0, LB>(A, Tt, ncl);
+    fin_pass<0, 0>(A, Tt, ncl);
     __syncthreads();
     const double* last = Tt;
     if constexpr (D == 3) {
-      fin_pass<1, LB>(Tt, U, ncl);
+      fin_pass<1, 0>(Tt, U, ncl);
       __syncthreads();
       last = U;
     }
@@ -1070,11 +1043,7 @@ struct Tck {
       double acc[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) acc[i] = 0.0;
-      fin_last<LB>(last, sl, t, acc);
-      if constexpr (GS) {  // level 0 is already at the Gauss points
-#pragma unroll
-        for (int i = 0; i < N; ++i) acc[i] += A[sl * NP + t + i * ST];
-      }
+      fin_last<0>(last, sl, t, acc);
       const int64_t g0 = gofs + (int64_t)sl * NP + t;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
@@ -1134,12 +1103,14 @@ constexpr int tck_waves_per_simd() {
 // HDG = true: the HDG-ADER variant (Sec. 2.4, eq. hdg-ader).  p.u holds the
 // DG derivative W = L u (the first time derivative), the recursion starts at
 // the second derivative, and I = dt u + sum_{m>=1} dt^{m+1}/(m+1)! ut^m with
-// the dt u term added in the storage basis from p.u_base.  GS: u and I in
-// the Gauss storage basis (no basis change in, none out).
+// the dt u term added from p.u_base.  GS: u (and u_base) in the Gauss
+// storage basis, so no basis change on the way in; I always leaves in the GL
+// basis, whose face nodes the update sweep gathers from the neighbours (the
+// HDG dt u term then joins the level-0 sum before its S^-1).
 template <int D, int N, typename T, int RP, int CPW, bool HDG = false, bool GS = false>
 __global__ void __launch_bounds__(tck_threads(D, N))
 __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck_kernel(TckParams p) {
-  using K = Tck<D, N, T, RP, CPW, GS>;
+  using K = Tck<D, N, T, RP, CPW>;
   using Regs = TckRegs<D, N, CPW, RP>;
   constexpr int NC = D + 1, NP = ipow(N, D), NT = tck_threads(D, N);
   constexpr int ES = cdiv(CPW * NC * NP, NT);
@@ -1189,7 +1160,10 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck
     if (i < ncl * NP) {
       const int c = i / NP, q = i - c * NP;
 #pragma unroll
-      for (int v = 0; v < NC; ++v) R.A[0][s][v] = c0 * (double)C[(c * NC + v) * NP + q];
+      for (int v = 0; v < NC; ++v) {
+        R.A[0][s][v] = c0 * (double)C[(c * NC + v) * NP + q];
+        if constexpr (HDG && GS) R.A[0][s][v] += p.dt * p.u_base[gofs + (c * NC + v) * NP + q];
+      }
     }
   }
   if constexpr (HDG)
@@ -1198,10 +1172,10 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck
     K::template step<1, 0>(p, C, Db, R, cell0, ncl, member);
   __syncthreads();  // the last accumulation may still read C
   if constexpr (K::FUSED_FINAL) {
-    K::template final_fused<HDG>(p, reinterpret_cast<double*>(smem), R, ncl, gofs);
+    K::template final_fused<HDG && !GS>(p, reinterpret_cast<double*>(smem), R, ncl, gofs);
   } else {
     // collapse the coarser levels into level 0, add A_0 in FP64, then G -> GL
-    // in FP64 (GL storage basis)
+    // in FP64
     K::template collapse<Regs::NLV - 1>(p, C, Db, R, ncl);
     double* sI = reinterpret_cast<double*>(Db[0]);  // FP64 tile over the derivative tiles
 #pragma unroll
@@ -1217,8 +1191,8 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck
       }
     }
     __syncthreads();
-    if constexpr (!GS) tensor_apply_inplace<NT, D, N, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
-    if constexpr (HDG) {
+    tensor_apply_inplace<NT, D, N, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
+    if constexpr (HDG && !GS) {
       for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i] + p.dt * p.u_base[gofs + i];
     } else {
       for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i];

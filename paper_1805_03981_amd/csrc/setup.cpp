@@ -145,9 +145,6 @@ std::vector<double> build_tables(int n) {
       // level 0 (exact on the lower degree) followed by S^-1, in one matrix
       for (int i = 0; i < n; ++i)
         for (int a = 0; a < m; ++a) t[tab_level_Q(n, l, r) + i * m + a] = (double)lagrange_value(rm.x, a, gl.x[i]);
-      // the same interpolant at the level-0 Gauss points (Gauss storage basis)
-      for (int i = 0; i < n; ++i)
-        for (int a = 0; a < m; ++a) t[tab_level_G(n, l, r) + i * m + a] = (double)lagrange_value(rm.x, a, g.x[i]);
     }
   return t;
 }

@@ -47,6 +47,12 @@ KERNEL_SOURCES = ["paper_1805_03981_amd/csrc/kernels.hpp", "paper_1805_03981_amd
 # Critical Courant numbers of the paper's Table 2 (3D, k = 4 and k = 7) bracket
 # k = 5; the runs use 0.9 of the smaller value.
 CR = {"lsrk": 0.9 * 0.44, "lsrk59": 0.9 * 0.57, "ader": 0.9 * 0.18}
+# storage basis of the state per scheme (0 = GL nodes, 1 = Gauss points,
+# Sec. 3.1): the faster one on MI355X, measured both ways in the ablations.
+# ADER: the TCK reads u at the Gauss points without a basis change and the
+# update writes it there; LSRK: GL nodes (the Gauss-basis stage reads the
+# neighbours' whole normal lines for its face traces).
+BASIS = {"ader": 1, "lsrk": 0, "lsrk59": 0}
 
 
 def kernel_hash():
@@ -99,6 +105,24 @@ def read_traffic(kernel, workload, precision):
     return float(t.group(1))
 
 
+def basis_map(u, n, what):
+    """Apply the library's 1D matrix `what` (4: S, GL -> Gauss points; 5:
+    S^-1) along the three directions of a device state [..., n^3] (x
+    fastest)."""
+    import torch
+    from paper_1805_03981_amd import binding as dg
+    M = torch.from_numpy(dg.basis_1d(n, what)).to(u.device)
+    a = u.reshape(u.shape[:-1] + (n, n, n))
+    for ax in (-1, -2, -3):
+        a = torch.movedim(torch.matmul(torch.movedim(a, ax, -1).contiguous(), M.T.contiguous()), -1, ax)
+    return a.reshape(u.shape).contiguous()
+
+
+def to_gl_nodes(u, n):
+    """Values at the Gauss points -> GL coefficients of the same polynomial."""
+    return basis_map(u, n, 5)
+
+
 def make_c2(B, precision, ncell=24, k=5, seed=1805, storage_basis=0):
     import numpy as np
     import torch
@@ -131,7 +155,7 @@ def run_variant(scheme, precision, steps, warmup):
     that timing) is reported beside it."""
     import torch
     from paper_1805_03981_amd import binding as dg
-    mesh, u0, wl = make_c2(1, precision)
+    mesh, u0, wl = make_c2(1, precision, storage_basis=BASIS[scheme])
     mesh.autotune(1)
     dt = CR[scheme] * mesh.info.dt_unit
     sid = {"ader": dg.ADER, "lsrk": dg.LSRK54, "lsrk59": dg.LSRK59}[scheme]
@@ -182,8 +206,8 @@ def fp32_error(steps=5):
     import torch
     out = {}
     for scheme in ("ader", "lsrk"):
-        m64, u64, _ = make_c2(1, "fp64")
-        m32, u32, _ = make_c2(1, "fp32")
+        m64, u64, _ = make_c2(1, "fp64", storage_basis=BASIS[scheme])
+        m32, u32, _ = make_c2(1, "fp32", storage_basis=BASIS[scheme])
         dt = CR[scheme] * m64.info.dt_unit
         for m, u in ((m64, u64), (m32, u32)):
             (m.step_ader if scheme == "ader" else m.step_lsrk)(u, 0.0, dt, steps)
@@ -241,7 +265,8 @@ def batched_sources(B=64, steps=500, precision="fp32", ncell=32, k=5, seed=64, u
     wl = W.c2_workload(ncell, k, 1805)
     mesh = dg.Mesh(3, k, W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell),
                    dg.fourier_material_struct(wl["material"]),
-                   precision=dg.FP32_SPLIT if precision == "fp32" else dg.FP64, max_batch=B)
+                   precision=dg.FP32_SPLIT if precision == "fp32" else dg.FP64, max_batch=B,
+                   storage_basis=BASIS["ader"])
     src = dg.Sources(mesh, W.random_points(seed, B, 3), frequency=8.0)
     u = torch.zeros((B,) + mesh.shape, dtype=torch.float64, device="cuda")
     work = mesh.work(B)
@@ -250,7 +275,8 @@ def batched_sources(B=64, steps=500, precision="fp32", ncell=32, k=5, seed=64, u
                      work=work, B=B)
     e = mesh.energy(u, B=B)
     out = {"workload": f"{ncell}^3 curved hexes, k={k}, {B} Ricker sources (f=8) as batch members, ADER, "
-                       f"{precision}, hipGraph={bool(use_graph)}, autotuned",
+                       f"{precision}, state at the {'Gauss points' if BASIS['ader'] else 'GL nodes'}, "
+                       f"hipGraph={bool(use_graph)}, autotuned",
            "B": B, "steps": int(rep.steps), "wall_s": rep.wall_s, "dof_steps_per_s": rep.dof_steps_per_s,
            "dofs_total": mesh.info.dofs * B, "energy_member0_end": float(e[0]),
            "launch_shape": {"operator": mesh.launch_shape(0), "operator_lsrk": mesh.launch_shape(2),
@@ -313,7 +339,8 @@ def fixed_error(target=1e-5, T=0.5, iters=3, max_run_s=12.0):
     solution).  For each scheme and precision and each reference, the largest
     step (at most that Courant number, rounded down to T/n) whose pressure at
     T differs from the reference by at most `target` (relative, plain
-    coefficient 2-norm over the GL nodes): the step is halved until the
+    coefficient 2-norm over the GL nodes, states kept at the Gauss points
+    mapped there first): the step is halved until the
     target is met, then bisected in log(dt).  Runs are shared between the two
     searches where the steps coincide; runs longer than `max_run_s` are not
     started; a search that stops converging reports the smallest error.  The
@@ -324,19 +351,19 @@ def fixed_error(target=1e-5, T=0.5, iters=3, max_run_s=12.0):
     from paper_1805_03981_amd import binding as dg
     refs, out = {}, {"target_rel_l2_p": target, "T": T, "references": {}}
     for rs in ("ader", "lsrk"):
-        mesh, u0, _ = make_c2(1, "fp64")
+        mesh, u0, _ = make_c2(1, "fp64", storage_basis=BASIS[rs])
         mesh.autotune(1)
         u = u0.clone()
         rep = mesh.solve(u, dg.ADER if rs == "ader" else dg.LSRK54, t_end=T,
                          dt=CR[rs] * mesh.info.dt_unit / 8, use_graph=True)
-        refs[rs] = u[0, :, 3, :].clone()
+        refs[rs] = (to_gl_nodes(u, 6) if BASIS[rs] else u)[0, :, 3, :].clone()
         out["references"][rs] = {"precision": "fp64", "dt": rep.dt, "steps": rep.steps}
         log(f"[bench] fixed error: {rs} reference, {rep.steps} steps in {rep.wall_s:.2f} s")
         del mesh, u, u0
     out["references"]["ader_vs_lsrk_rel_l2_p"] = rel_l2(refs["ader"], refs["lsrk"])
     for scheme, prec in (("ader", "fp64"), ("lsrk", "fp64"), ("lsrk59", "fp64"), ("ader", "fp32"), ("lsrk", "fp32")):
         key = f"{scheme}-{prec}"
-        m, v0, _ = make_c2(1, prec)
+        m, v0, _ = make_c2(1, prec, storage_basis=BASIS[scheme])
         m.autotune(1)
         sid = {"ader": dg.ADER, "lsrk": dg.LSRK54, "lsrk59": dg.LSRK59}[scheme]
         dt_max = CR[scheme] * m.info.dt_unit
@@ -346,7 +373,8 @@ def fixed_error(target=1e-5, T=0.5, iters=3, max_run_s=12.0):
             if dt not in runs:
                 v = v0.clone()
                 r = m.solve(v, sid, t_end=T, dt=dt, use_graph=True)
-                errs = {rs: rel_l2(v[0, :, 3, :], ref) for rs, ref in refs.items()}
+                p = (to_gl_nodes(v, 6) if BASIS[scheme] else v)[0, :, 3, :]
+                errs = {rs: rel_l2(p, ref) for rs, ref in refs.items()}
                 runs[dt] = (r.dt, r.steps, r.wall_s, r.dof_steps_per_s, errs)
                 log(f"[bench] fixed error {key}: dt {r.dt:.3e} ({r.steps} steps, {r.wall_s:.2f} s): rel L2(p) "
                     + ", ".join(f"vs {rs} {e:.3e}" for rs, e in errs.items()))
@@ -486,15 +514,20 @@ def c3_bounded(steps=8, ncell=48, k=7, nsample=6):
     om = None
     cells = None
     final = {}
+    n = k + 1
     for prec in ("fp64", "fp32"):
         pid = dg.FP32_SPLIT if prec == "fp32" else dg.FP64
-        log(f"[bench] c3: {ncell}^3 k={k} {prec} mesh (Fourier material)")
-        mesh = dg.Mesh.box(3, ncell, k, 0.05, dg.fourier_material_struct(wl["material"]), precision=pid)
-        mesh.autotune(1)
-        x = mesh.get(dg.GET_NODE_COORDS)
-        U = np.ascontiguousarray(np.moveaxis(wl["ic"](x), -1, 1))
-        u0 = torch.from_numpy(U).to("cuda")[None]
         for scheme in ("ader", "lsrk"):
+            log(f"[bench] c3: {ncell}^3 k={k} {prec} mesh (Fourier material), {scheme}, "
+                f"state at the {'Gauss points' if BASIS[scheme] else 'GL nodes'}")
+            mesh = dg.Mesh.box(3, ncell, k, 0.05, dg.fourier_material_struct(wl["material"]), precision=pid,
+                               storage_basis=BASIS[scheme])
+            mesh.autotune(1)
+            x = mesh.get(dg.GET_NODE_COORDS)
+            U = np.ascontiguousarray(np.moveaxis(wl["ic"](x), -1, 1))
+            u0 = torch.from_numpy(U).to("cuda")[None]
+            if BASIS[scheme]:
+                u0 = basis_map(u0, n, 4)
             u = u0.clone()
             rep = mesh.solve(u, dg.ADER if scheme == "ader" else dg.LSRK54, t_end=steps * CR[scheme] * mesh.info.dt_unit,
                              dt=CR[scheme] * mesh.info.dt_unit, use_graph=True)
@@ -502,50 +535,56 @@ def c3_bounded(steps=8, ncell=48, k=7, nsample=6):
                                        "dof_steps_per_s": rep.dof_steps_per_s}
             final[(scheme, prec)] = u
             log(f"[bench] c3 {scheme}-{prec}: {out[f'{scheme}-{prec}']}")
-        # one ADER step from the pulse, sampled cells against the oracle
-        if om is None:
-            om = OMesh(3, k, W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell), wl["material"], cache=False)
-            cells = np.unique(np.concatenate([rng.choice(om.nc, nsample, replace=False), [0, om.nc - 1]]))
-            nbrs = np.unique(np.concatenate([cells, om.neighbors[cells].ravel()]))
-            dt1 = CR["ader"] * mesh.info.dt_unit
-            t0 = time.perf_counter()
-            # the oracle's own interpolant of the pulse on the cells it needs
-            Uo = np.zeros_like(U)
-            Uo[nbrs] = om.interpolate(wl["ic"], cells=nbrs)
-            I = np.zeros_like(U)
-            I[nbrs] = ader.tck(om, Uo, dt1, cells=nbrs)
-            want = Uo[cells] + apply_operator(om, I, cells=cells)
-            out["oracle_sampled_step_s"] = time.perf_counter() - t0
-        u = u0.clone()
-        mesh.step_ader(u, 0.0, dt1, 1)
-        got = u[0].cpu().numpy()[cells]
-        out[f"ader_step_vs_oracle_{prec}"] = {
-            "cells": len(cells), "rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
-            "max_abs_over_max": float(np.abs(got - want).max() / np.abs(want).max())}
-        log(f"[bench] c3 ader step vs oracle {prec}: {out[f'ader_step_vs_oracle_{prec}']}")
-        del mesh, u0, u
-        torch.cuda.empty_cache()
+            if scheme != "ader":
+                del mesh, u0, u
+                torch.cuda.empty_cache()
+                continue
+            # one ADER step from the pulse, sampled cells against the oracle
+            if om is None:
+                om = OMesh(3, k, W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell), wl["material"], cache=False)
+                cells = np.unique(np.concatenate([rng.choice(om.nc, nsample, replace=False), [0, om.nc - 1]]))
+                nbrs = np.unique(np.concatenate([cells, om.neighbors[cells].ravel()]))
+                dt1 = CR["ader"] * mesh.info.dt_unit
+                t0 = time.perf_counter()
+                # the oracle's own interpolant of the pulse on the cells it needs
+                Uo = np.zeros_like(U)
+                Uo[nbrs] = om.interpolate(wl["ic"], cells=nbrs)
+                I = np.zeros_like(U)
+                I[nbrs] = ader.tck(om, Uo, dt1, cells=nbrs)
+                want = Uo[cells] + apply_operator(om, I, cells=cells)
+                out["oracle_sampled_step_s"] = time.perf_counter() - t0
+            u = u0.clone()
+            mesh.step_ader(u, 0.0, dt1, 1)
+            got = (to_gl_nodes(u, n) if BASIS["ader"] else u)[0].cpu().numpy()[cells]
+            out[f"ader_step_vs_oracle_{prec}"] = {
+                "cells": len(cells), "rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+                "max_abs_over_max": float(np.abs(got - want).max() / np.abs(want).max())}
+            log(f"[bench] c3 ader step vs oracle {prec}: {out[f'ader_step_vs_oracle_{prec}']}")
+            del mesh, u0, u
+            torch.cuda.empty_cache()
     for scheme in ("ader", "lsrk"):
         out[f"fp32_vs_fp64_after_steps_{scheme}"] = rel_l2(final[(scheme, "fp32")], final[(scheme, "fp64")])
     del final
     torch.cuda.empty_cache()
     for prec in ("fp64", "fp32"):
         pid = dg.FP32_SPLIT if prec == "fp32" else dg.FP64
-        log(f"[bench] c3: {ncell}^3 k={k} {prec} mesh (rho = c = 1, plane wave)")
-        mesh = dg.Mesh.box(3, ncell, k, 0.05, unit, precision=pid)
-        x = mesh.get(dg.GET_NODE_COORDS)
-        u0 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(W.plane_wave_3d(x, 0.0), -1, 1))).to("cuda")[None]
         for scheme in ("ader", "lsrk"):
-            u = u0.clone()
+            log(f"[bench] c3: {ncell}^3 k={k} {prec} mesh (rho = c = 1, plane wave), {scheme}")
+            mesh = dg.Mesh.box(3, ncell, k, 0.05, unit, precision=pid, storage_basis=BASIS[scheme])
+            x = mesh.get(dg.GET_NODE_COORDS)
+            u = torch.from_numpy(np.ascontiguousarray(np.moveaxis(W.plane_wave_3d(x, 0.0), -1, 1))).to("cuda")[None]
+            if BASIS[scheme]:
+                u = basis_map(u, n, 4)
             rep = mesh.solve(u, dg.ADER if scheme == "ader" else dg.LSRK54, t_end=steps * CR[scheme] * mesh.info.dt_unit,
                              dt=CR[scheme] * mesh.info.dt_unit, use_graph=True)
             T = rep.steps * rep.dt
             ex = torch.from_numpy(np.ascontiguousarray(np.moveaxis(W.plane_wave_3d(x, T), -1, 1))).to("cuda")[None]
-            out[f"plane_wave_{scheme}-{prec}"] = {"T": T, "steps": rep.steps, "rel_l2_error_vs_closed_form": rel_l2(u, ex)}
+            got = to_gl_nodes(u, n) if BASIS[scheme] else u
+            out[f"plane_wave_{scheme}-{prec}"] = {"T": T, "steps": rep.steps,
+                                                  "rel_l2_error_vs_closed_form": rel_l2(got, ex)}
             log(f"[bench] c3 plane wave {scheme}-{prec}: {out[f'plane_wave_{scheme}-{prec}']}")
-            del u, ex
-        del mesh, u0
-        torch.cuda.empty_cache()
+            del u, ex, got, mesh
+            torch.cuda.empty_cache()
     return out
 
 
@@ -634,16 +673,18 @@ def ablations(steps=10, warmup=2):
 def degree_sweep(steps=5, warmup=1):
     """FP64 DoF-steps/s of both schemes against the degree on the paper's
     cube sizes: 40^3 slightly curved hexes (80^3 for k <= 3), the c2 material
-    and pulse, 0.9 of the critical Courant number."""
+    and pulse, 0.9 of the critical Courant number, each scheme in its
+    storage basis."""
     import torch
     out = {}
     for k in range(1, 9):
         ncell = 80 if k <= 3 else 40
-        mesh, u0, _ = make_c2(1, "fp64", ncell=ncell, k=k)
-        mesh.autotune(1)
-        row = {"ncell": ncell, "dofs": mesh.info.dofs}
-        work = mesh.work(1)
+        row = {"ncell": ncell}
         for scheme in ("lsrk", "ader"):
+            mesh, u0, _ = make_c2(1, "fp64", ncell=ncell, k=k, storage_basis=BASIS[scheme])
+            mesh.autotune(1)
+            row["dofs"] = mesh.info.dofs
+            work = mesh.work(1)
             dt = CR[scheme] * mesh.info.dt_unit
             u = u0.clone()
             step = mesh.step_ader if scheme == "ader" else mesh.step_lsrk
@@ -653,10 +694,10 @@ def degree_sweep(steps=5, warmup=1):
             step(u, 0.0, dt, steps, work=work)
             torch.cuda.synchronize()
             row[scheme] = mesh.info.dofs * steps / (time.perf_counter() - t0)
+            del mesh, u0, work, u
+            torch.cuda.empty_cache()
         log(f"[bench] sweep k={k}: {row}")
         out[k] = row
-        del mesh, u0, work, u
-        torch.cuda.empty_cache()
     return out
 
 
@@ -842,13 +883,15 @@ def main():
                                "(1.19e7 DoF), rho=1, c = 8-mode Fourier field (seed 1805), upwind, "
                                "Gaussian pressure pulse width 0.05",
                    "scheme": head["scheme"], "precision": head["precision"], "dt": head["dt"],
-                   "courant": CR[head["scheme"]]},
+                   "courant": CR[head["scheme"]],
+                   "storage_basis": "gauss points" if BASIS[head["scheme"]] else "gl nodes"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": {k: {"dof_steps_per_s": r["dof_steps_per_s"], "ms_per_step": r["ms_per_step"],
                          "steps_to_T_0.5": r["steps_to_T"], "time_to_T_0.5_s": r["time_to_T_s"],
                          "graph_solve_ms_per_step": r["graph_solve_ms_per_step"],
-                         "kernels_ms": r["kernels_ms"], "launch_shape": r["launch_shape"]}
+                         "kernels_ms": r["kernels_ms"], "launch_shape": r["launch_shape"],
+                         "storage_basis": "gauss points" if BASIS[r["scheme"]] else "gl nodes"}
                      for k, r in results.items()},
         "kernels": kernels,
         "fixed_error_summary": fixed_summary(extras.get("fixed_error")),

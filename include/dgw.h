@@ -198,10 +198,12 @@ dgw_status dgw_mesh_create(const dgw_mesh_desc* desc, dgw_mesh** out);
 
 /* Convenience: the periodic unit box [0,1]^dim with ncell^dim cells, each node
  * X moved to X + amp prod_j sin(2 pi X_j) in every coordinate, geometry degree
- * q = k, neighbours by periodic wrap.  Other fields as in dgw_mesh_desc. */
+ * q = k, neighbours by periodic wrap.  Other fields (storage_basis included)
+ * as in dgw_mesh_desc. */
 dgw_status dgw_mesh_create_box(int dim, int ncell, int degree, double deform_amp,
                                dgw_material_fn material, void* material_ctx, int flux,
-                               int precision, int device, int max_batch, dgw_mesh** out);
+                               int precision, int device, int max_batch, int storage_basis,
+                               dgw_mesh** out);
 
 /* A ready material: rho = rho0, c(x) = clamp(c0 + amp nmodes^-1/2 sum_i
  * a_i cos(2 pi m_i.x + phi_i), cmin, cmax).  Pass dgw_material_fourier with a

@@ -114,7 +114,7 @@ class ServeReport(C.Structure):
 _vp, _dp, _i, _d, _i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_double, C.c_int64
 _SIGS = {
     "dgw_mesh_create": ([C.POINTER(MeshDesc), C.POINTER(_vp)], _i),
-    "dgw_mesh_create_box": ([_i, _i, _i, _d, MATERIAL_FN, _vp, _i, _i, _i, _i, C.POINTER(_vp)], _i),
+    "dgw_mesh_create_box": ([_i, _i, _i, _d, MATERIAL_FN, _vp, _i, _i, _i, _i, _i, C.POINTER(_vp)], _i),
     "dgw_mesh_destroy": ([_vp], None),
     "dgw_mesh_info_get": ([_vp, C.POINTER(MeshInfo)], _i),
     "dgw_mesh_get": ([_vp, _i, _dp, _i64], _i),
@@ -236,7 +236,8 @@ class Mesh:
         self._finish()
 
     @classmethod
-    def box(cls, dim, ncell, degree, amp, material, flux=FLUX_UPWIND, precision=FP64, device=0, max_batch=1):
+    def box(cls, dim, ncell, degree, amp, material, flux=FLUX_UPWIND, precision=FP64, device=0, max_batch=1,
+            storage_basis=BASIS_GL):
         self = cls.__new__(cls)
         if isinstance(material, FourierMaterial):
             self._ctx = material
@@ -247,7 +248,7 @@ class Mesh:
             ctx = None
         h = C.c_void_p()
         check(lib.dgw_mesh_create_box(dim, ncell, degree, amp, self._cb, ctx, flux, precision, device, max_batch,
-                                      C.byref(h)), "dgw_mesh_create_box")
+                                      storage_basis, C.byref(h)), "dgw_mesh_create_box")
         self.h = h
         self._finish()
         return self

@@ -39,7 +39,7 @@ void dgw_material_fourier(const double* x, int64_t npts, int dim, double* rho, d
 
 dgw_status dgw_mesh_create_box(int dim, int ncell, int degree, double amp, dgw_material_fn material,
                                void* material_ctx, int flux, int precision, int device, int max_batch,
-                               dgw_mesh** out) {
+                               int storage_basis, dgw_mesh** out) {
   if (dim != 2 && dim != 3) return fail(DGW_EUNSUPPORTED, "dim must be 2 or 3");
   if (ncell < 1 || ncell > 1024) return fail(DGW_EINVAL, "ncell must be in 1..1024");
   if (degree < 1 || degree > 8) return fail(DGW_EUNSUPPORTED, "degree must be in 1..8");
@@ -91,6 +91,7 @@ dgw_status dgw_mesh_create_box(int dim, int ncell, int degree, double amp, dgw_m
   d.precision = precision;
   d.device = device;
   d.max_batch = max_batch;
+  d.storage_basis = storage_basis;
   return dgw_mesh_create(&d, out);
 }
 
@@ -175,7 +176,7 @@ std::shared_ptr<Prep> prepare(const dgw_request& r, int idx, int64_t fp, int dev
   P->done = std::async(std::launch::async, [P, r, device]() -> dgw_status {
     dgw_fourier_material mat = r.material;  // read during the setup only
     const dgw_status st = dgw_mesh_create_box(r.dim, r.ncell, r.degree, r.deform_amp, dgw_material_fourier, &mat,
-                                              DGW_FLUX_UPWIND, r.precision, device, 1, &P->mesh);
+                                              DGW_FLUX_UPWIND, r.precision, device, 1, DGW_BASIS_GL, &P->mesh);
     if (st) return st;
     initial_state(P->mesh, r, P->u0);
     return DGW_OK;

@@ -704,7 +704,8 @@ def degree_sweep(steps=5, warmup=1):
 def ceilings():
     """Measured ceilings: device copy and triad bandwidth, FP64 GEMM rate, LDS
     read bandwidth (8- and 16-byte lanes, contiguous and at the 48-byte stride
-    of 6-point FP64 lines), vector FMA and matrix-core rates."""
+    of 6-point FP64 lines), vector FMA and matrix-core rates, and the k = 5
+    FP32 line contraction on the vector units and on the matrix cores."""
     import torch
     n = (1 << 30) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -747,6 +748,10 @@ def ceilings():
     out["fp32_vector_fma_TFLOPs"] = rate(lib.dgw_ceiling_vector_fma, 0) / 1e12
     out["fp64_mfma_TFLOPs"] = rate(lib.dgw_ceiling_mfma, 1) / 1e12
     out["fp32_mfma_TFLOPs"] = rate(lib.dgw_ceiling_mfma, 0) / 1e12
+    # the k = 5 FP32 line contraction itself, vector FMAs against matrix cores
+    out["contract6_fp32_valu_Glines_per_s"] = rate(lib.dgw_ceiling_contract6, 0) / 1e9
+    out["contract6_fp32_mfma_Glines_per_s"] = rate(lib.dgw_ceiling_contract6, 1) / 1e9
+    out["contract6_mfma_vs_valu_max_rel_diff"] = rate(lib.dgw_ceiling_contract6_check)
     return out
 
 

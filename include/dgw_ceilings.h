@@ -28,6 +28,19 @@ int dgw_ceiling_vector_fma(int fp64, double* out);
  * v_mfma_f32_32x32x2_f32 (fp64 = 0). */
 int dgw_ceiling_mfma(int fp64, double* out);
 
+/* The 1D contraction of the k = 5 kernels in FP32 (a 6 x 6 matrix along
+ * lines of 6 values held in LDS, one workgroup barrier per pass), in lines
+ * per second over the device: one line per lane on the vector FMA units
+ * (mfma = 0, 36 FMAs per line) or 16 lines per wave with
+ * v_mfma_f32_16x16x4f32 (mfma = 1, two instructions per 16 lines, 6 of 16
+ * outputs and 6 of 8 summation terms used). */
+int dgw_ceiling_contract6(int mfma, double* out);
+
+/* The largest difference between the two contractions above after three
+ * passes on the same tile, relative to the largest value (the check that
+ * the matrix-core form computes the same product). */
+int dgw_ceiling_contract6_check(double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -88,6 +88,87 @@ __global__ void __launch_bounds__(NT) mfma_f32(float* out, float a, int iters) {
   out[blockIdx.x * NT + threadIdx.x] = s;
 }
 
+// The 1D contraction of the DG kernels at k = 5 in FP32: a 6 x 6 matrix
+// applied along x-lines of 6 values, lines held in LDS (stride 8 floats, the
+// last two zero), two tiles of CLINES lines ping-ponged, one workgroup
+// barrier per pass as between the kernels' phases.  Lane-per-line on the
+// vector FMA units, or 16 lines per wave on the matrix cores.
+constexpr int CLINES = 1024;  // lines per tile: 2 tiles x 1024 x 8 floats = 64 KiB
+
+__device__ __forceinline__ void contract_init(float* t0, float* t1) {
+  for (int i = threadIdx.x; i < CLINES * 8; i += NT) {
+    const int c = i & 7;
+    t0[i] = c < 6 ? 1e-3f * (float)((i * 37) % 101 - 50) : 0.0f;
+    t1[i] = 0.0f;
+  }
+  __syncthreads();
+}
+
+// one line per lane, 36 FMAs with the matrix entries uniform over the wave
+__global__ void __launch_bounds__(NT) contract6_valu(float* out, const float* __restrict__ M, int iters) {
+  __shared__ float tile[2][CLINES * 8];
+  contract_init(tile[0], tile[1]);
+  float m[36];
+#pragma unroll
+  for (int e = 0; e < 36; ++e) m[e] = M[e];
+  for (int it = 0; it < iters; ++it) {
+    const float* src = tile[it & 1];
+    float* dst = tile[(it & 1) ^ 1];
+    for (int l = threadIdx.x; l < CLINES; l += NT) {
+      float x[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) x[j] = src[l * 8 + j];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        float acc = m[i * 6] * x[0];
+#pragma unroll
+        for (int j = 1; j < 6; ++j) acc = fmaf(m[i * 6 + j], x[j], acc);
+        dst[l * 8 + i] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < CLINES * 8; i += NT) out[(size_t)blockIdx.x * CLINES * 8 + i] = tile[iters & 1][i];
+}
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// 16 lines per wave and v_mfma_f32_16x16x4f32: A = the lines (16 x 4, lane l
+// holds line l % 16, entry 4 kk + l / 16), B = M^T (4 x 16, lane l holds
+// entry 4 kk + l / 16 of output l % 16; zero outside 6 x 6), D = 16 x 16
+// (lane l holds lines 4 (l / 16) + r, output l % 16); K = 6 takes two
+// instructions (the last two entries zero), 6 of 16 outputs are used.
+__global__ void __launch_bounds__(NT) contract6_mfma(float* out, const float* __restrict__ M, int iters) {
+  __shared__ float tile[2][CLINES * 8];
+  contract_init(tile[0], tile[1]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  float b[2];
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk) {
+    const int k = 4 * kk + g;
+    b[kk] = (k < 6 && r16 < 6) ? M[r16 * 6 + k] : 0.0f;
+  }
+  for (int it = 0; it < iters; ++it) {
+    const float* src = tile[it & 1];
+    float* dst = tile[(it & 1) ^ 1];
+    for (int blk = wave; blk < CLINES / 16; blk += NT / 64) {
+      f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        const float a = src[(blk * 16 + r16) * 8 + 4 * kk + g];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[kk], acc, 0, 0, 0);
+      }
+      if (r16 < 8) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[(blk * 16 + 4 * g + r) * 8 + r16] = acc[r];
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < CLINES * 8; i += NT) out[(size_t)blockIdx.x * CLINES * 8 + i] = tile[iters & 1][i];
+}
+
 int n_cus() {
   int dev = 0, n = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
@@ -184,4 +265,73 @@ extern "C" int dgw_ceiling_mfma(int fp64, double* out) {
   const double flop_per_iter_wave = fp64 ? 4 * 2.0 * 16 * 16 * 4 : 2 * 2.0 * 32 * 32 * 2;
   *out = flop_per_iter_wave * (double)blocks * (NT / 64) * iters / sec;
   return 0;
+}
+
+// M: a fixed, well-conditioned 6 x 6 matrix (entries of order 0.3), so that
+// repeated passes neither overflow nor vanish
+static int contract_setup(float** dM) {
+  float hM[36];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) hM[i * 6 + j] = (i == j ? 0.55f : 0.0f) + 0.05f * (float)((i * 7 + j * 3) % 5 - 2);
+  if (hipMalloc(dM, sizeof(hM)) != hipSuccess) return -1;
+  if (hipMemcpy(*dM, hM, sizeof(hM), hipMemcpyHostToDevice) != hipSuccess) return -1;
+  return 0;
+}
+
+extern "C" int dgw_ceiling_contract6(int mfma, double* out) {
+  if (!out) return -1;
+  const int ncu = n_cus();
+  if (ncu <= 0) return -1;
+  const int blocks = ncu * 2, iters = 2000;  // 64 KiB of LDS per workgroup: two per CU
+  float *dM = nullptr, *buf = nullptr;
+  if (contract_setup(&dM)) return -1;
+  if (hipMalloc(&buf, (size_t)blocks * CLINES * 8 * sizeof(float)) != hipSuccess) {
+    (void)hipFree(dM);
+    return -1;
+  }
+  double sec = 0;
+  auto launch = [&](int it) {
+    if (mfma)
+      hipLaunchKernelGGL(contract6_mfma, dim3(blocks), dim3(NT), 0, 0, buf, dM, it);
+    else
+      hipLaunchKernelGGL(contract6_valu, dim3(blocks), dim3(NT), 0, 0, buf, dM, it);
+  };
+  const int rc = time_launch(launch, iters, &sec);
+  (void)hipFree(buf);
+  (void)hipFree(dM);
+  if (rc || sec <= 0) return -1;
+  *out = (double)blocks * CLINES * iters / sec;
+  return 0;
+}
+
+extern "C" int dgw_ceiling_contract6_check(double* out) {
+  if (!out) return -1;
+  float *dM = nullptr, *b0 = nullptr, *b1 = nullptr;
+  if (contract_setup(&dM)) return -1;
+  const size_t n = (size_t)CLINES * 8;
+  if (hipMalloc(&b0, n * sizeof(float)) != hipSuccess || hipMalloc(&b1, n * sizeof(float)) != hipSuccess) {
+    (void)hipFree(dM);
+    (void)hipFree(b0);
+    return -1;
+  }
+  hipLaunchKernelGGL(contract6_valu, dim3(1), dim3(NT), 0, 0, b0, dM, 3);
+  hipLaunchKernelGGL(contract6_mfma, dim3(1), dim3(NT), 0, 0, b1, dM, 3);
+  int rc = hipDeviceSynchronize() == hipSuccess ? 0 : -1;
+  float* h = new float[2 * n];
+  if (!rc && (hipMemcpy(h, b0, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+              hipMemcpy(h + n, b1, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess))
+    rc = -1;
+  if (!rc) {
+    double mx = 0, dmax = 0;
+    for (size_t i = 0; i < n; ++i) {
+      mx = fmax(mx, fabs((double)h[i]));
+      dmax = fmax(dmax, fabs((double)h[i] - (double)h[n + i]));
+    }
+    *out = mx > 0 ? dmax / mx : -1.0;
+  }
+  delete[] h;
+  (void)hipFree(b0);
+  (void)hipFree(b1);
+  (void)hipFree(dM);
+  return rc;
 }

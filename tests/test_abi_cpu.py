@@ -42,7 +42,8 @@ def test_ceilings_library_exports_its_header():
     text = open(os.path.join(ROOT, "include", "dgw_ceilings.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = sorted(set(re.findall(r"\b(dgw_[a-z0-9_]+)\s*\(", text)))
-    assert names == ["dgw_ceiling_lds_read", "dgw_ceiling_mfma", "dgw_ceiling_vector_fma"]
+    assert names == ["dgw_ceiling_contract6", "dgw_ceiling_contract6_check", "dgw_ceiling_lds_read", "dgw_ceiling_mfma",
+                     "dgw_ceiling_vector_fma"]
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1805_03981_amd", "libdgw_ceilings.so"))
     for n in names:
         assert hasattr(lib, n), n

@@ -418,9 +418,10 @@ typedef struct dgw_serve_report {
 } dgw_serve_report;
 /* Replays a request trace: a request is admitted once it has arrived and its
  * device footprint fits the budget; admitted requests run concurrently on
- * their own streams, one step per scheduling round each, and retire when
- * done.  Requests larger than the whole budget fail with DGW_ENOMEM in their
- * result; the others continue.  Synchronous. */
+ * their own streams, a chunk of about 1e7 DoF-steps per scheduling round
+ * each, and retire when done; states at the GL nodes.  Requests larger than
+ * the whole budget fail with DGW_ENOMEM in their result; the others
+ * continue.  Synchronous. */
 dgw_status dgw_serve(const dgw_server_desc* desc, const dgw_request* reqs, int n, dgw_result* out,
                      dgw_serve_report* report);
 

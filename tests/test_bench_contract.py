@@ -26,3 +26,23 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_basis_map_matches_the_oracle():
+    """bench.basis_map (the device map the benchmark uses to compare states
+    kept at the Gauss points over the GL nodes) against the oracle's own
+    GL -> Gauss map on a random state, and its round trip."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads as W
+    from oracle import Mesh as OMesh
+    from oracle.operator import gl_to_gauss
+    k = 3
+    om = OMesh(3, k, W.box_nodes(3, 2, k, 0.05), W.box_neighbors(3, 2), W.ConstantMaterial())
+    U = W.random_state(3, (om.nc, 4, om.np_))
+    g = bench.basis_map(torch.from_numpy(U), k + 1, 4).numpy()
+    assert np.abs(g - gl_to_gauss(om, U)).max() < 1e-13 * np.abs(U).max()
+    back = bench.to_gl_nodes(torch.from_numpy(g), k + 1).numpy()
+    assert np.abs(back - U).max() < 1e-13 * np.abs(U).max()

@@ -1019,7 +1019,7 @@ struct Tck {
   template <bool HDG_ADD>
   __device__ static __forceinline__ void final_fused(const TckParams& p, double* sm, Regs& R, int ncl,
                                                      int64_t gofs) {
-    constexpr int EA = fin_elems(0), ET = fin_elems(1), EU = D == 3 ? fin_elems(2) : 0;
+    constexpr int EA = fin_elems(0), EU = D == 3 ? fin_elems(2) : 0;
     constexpr int LOW = (EA > EU ? EA : EU) * CPW * NC;  // A and U share the start, T follows
     double* A = sm;
     double* Tt = sm + LOW;

@@ -12,6 +12,7 @@ import torch
 import workloads as W
 from oracle import Mesh as OMesh
 from oracle import apply_operator, ader, norms, timestep as ts
+from oracle.operator import gl_to_gauss
 from tolerances import op_tol
 
 pytestmark = pytest.mark.gpu
@@ -241,10 +242,14 @@ def test_watchdog_trips_on_unstable_step(gpu_lib):
     assert e.value.status == B.EUNSTABLE
 
 
-def _sampled_parity(B, ncell, k, precision, tol, nsample=24):
+def _sampled_parity(B, ncell, k, precision, tol, nsample=24, storage_basis=0):
+    """Operator and one ADER step against the oracle on sampled cells; with
+    storage_basis = Gauss the states go in and come out at the Gauss points
+    and are compared with the oracle's GL results mapped there by its own S."""
     wl = W.c2_workload(ncell, k, 1805)
     nodes, nb = W.box_nodes(3, ncell, k, 0.05), W.box_neighbors(3, ncell)
-    gm = B.Mesh(3, k, nodes, nb, B.fourier_material_struct(wl["material"]), precision=precision)
+    gm = B.Mesh(3, k, nodes, nb, B.fourier_material_struct(wl["material"]), precision=precision,
+                storage_basis=storage_basis)
     om = OMesh(3, k, nodes, nb, wl["material"], cache=False)
     rng = np.random.default_rng(ncell * 10 + k)
     cells = np.unique(np.concatenate([rng.choice(om.nc, nsample, replace=False), [0, om.nc - 1]]))
@@ -257,22 +262,25 @@ def _sampled_parity(B, ncell, k, precision, tol, nsample=24):
     # operator on a random state (no cancellation between volume and face
     # terms, so the relative difference measures rounding, not conditioning)
     Ur = rng.standard_normal((om.nc, 4, om.np_))
-    L = gm.apply(to_dev(Ur)[None])[0].cpu().numpy()
-    want = apply_operator(om, Ur, cells=cells)
+    gauss = storage_basis == B.BASIS_GAUSS
+    to_storage = (lambda V: gl_to_gauss(om, V)) if gauss else (lambda V: V)
+    L = gm.apply(to_dev(to_storage(Ur))[None])[0].cpu().numpy()
+    want = to_storage(apply_operator(om, Ur, cells=cells))
     e_op = norms.rel_l2(L[cells], want)
     # one ADER step: TCK on the sampled cells and their face neighbours, then
     # the update on the sampled cells
     dt = 0.16 * gm.info.dt_unit
-    u = to_dev(U)[None]
+    u = to_dev(to_storage(U))[None]
     gm.step_ader(u, 0.0, dt, 1)
     nbrs = np.unique(np.concatenate([cells, om.neighbors[cells].ravel()]))
     Uo = np.zeros_like(U)
     Uo[nbrs] = om.interpolate(wl["ic"], cells=nbrs) + noise[nbrs]
     I = np.zeros_like(U)
     I[nbrs] = ader.tck(om, Uo, dt, cells=nbrs)
-    want = Uo[cells] + apply_operator(om, I, cells=cells)
+    want = to_storage(Uo[cells] + apply_operator(om, I, cells=cells))
     e_ad = norms.rel_l2(u[0].cpu().numpy()[cells], want)
-    say(f"sampled {ncell}^3 k={k} prec={precision}: operator {e_op:.2e}, ADER step {e_ad:.2e}")
+    say(f"sampled {ncell}^3 k={k} prec={precision} basis={storage_basis}: operator {e_op:.2e}, "
+        f"ADER step {e_ad:.2e}")
     assert e_op < max(tol, op_tol(k, 3)) and e_ad < tol
 
 
@@ -283,11 +291,20 @@ def test_full_size_c2_sampled(gpu_lib):
     _sampled_parity(gpu_lib, 24, 5, 0, 1e-12)
 
 
+def test_full_size_c2_sampled_gauss_basis(gpu_lib):
+    """The same with the state at the Gauss points, the storage the benchmark
+    times ADER in."""
+    say("c2 full size gauss")
+    _sampled_parity(gpu_lib, 24, 5, 0, 1e-12, storage_basis=gpu_lib.BASIS_GAUSS)
+
+
 def test_full_size_c3_sampled(gpu_lib):
-    """48^3 curved hexes, k=7 (2.26e8 DoF), FP64 and FP32-split, sampled cells."""
+    """48^3 curved hexes, k=7 (2.26e8 DoF), FP64 and FP32-split, sampled cells;
+    FP64 also with the state at the Gauss points."""
     say("c3 full size")
     _sampled_parity(gpu_lib, 48, 7, 0, 1e-12, nsample=8)
     _sampled_parity(gpu_lib, 48, 7, 1, 1e-5, nsample=8)
+    _sampled_parity(gpu_lib, 48, 7, 0, 1e-12, nsample=8, storage_basis=gpu_lib.BASIS_GAUSS)
 
 
 def _request(B, seed, ncell, k, scheme, t_end, arrival):

@@ -437,6 +437,32 @@ def test_steps_with_prescribed_faces(gpu_lib, scheme):
     close(u[0].cpu().numpy(), want, TOL)
 
 
+@pytest.mark.parametrize("scheme", ["lsrk", "ader"])
+def test_steps_with_prescribed_faces_gauss_basis(gpu_lib, scheme):
+    """The same with the state at the Gauss points: exterior data at the LSRK
+    stage times, integrated over the step for ADER (whose TCK sum stays in
+    the GL basis)."""
+    say("steps prescribed gauss", scheme)
+    B = gpu_lib
+    dim, nc, k = 3, 3, 3
+    gm, om, pw = build_prescribed(B, dim, nc, k, ("prescribed", "periodic", "prescribed"),
+                                  storage_basis=B.BASIS_GAUSS)
+    U = om.interpolate(lambda x: pw(x, 0.0)) + 0.01 * W.random_state(31, (om.nc, dim + 1, om.np_))
+    dt, t0 = 0.3 * gm.info.dt_unit, 0.37
+    u = to_dev(gl_to_gauss(om, U))[None]
+    want = U
+    if scheme == "ader":
+        gm.step_ader(u, t0, dt, 3)
+        for s in range(3):
+            want = ader.ader_step(om, want, dt, exterior_integral=lambda x: pw.integral(x, t0 + s * dt, dt))
+    else:
+        gm.step_lsrk(u, t0, dt, 3)
+        for s in range(3):
+            want = ts.lsrk_step(lambda x, t: apply_operator(om, x, exterior=lambda y: pw(y, t)), want,
+                                t0 + s * dt, dt)
+    close(u[0].cpu().numpy(), gl_to_gauss(om, want), TOL)
+
+
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_prescribed_graph_replay_equals_eager(gpu_lib, scheme):
     """Captured steps take the step time from the device counter: the same

@@ -130,14 +130,17 @@ __device__ __forceinline__ void contract(const TM* __restrict__ M, const TM (&x)
 
 // out = M in along DIR, for nslices independent tensors (cells x components).
 // in and out may be the same buffer when MI == MO (each line is read whole
-// before it is written, and lines are disjoint).
-template <int NT, int D, int DIR, int MI, int MO, int A0, int A1, int A2, int MODE, typename TM, typename TI,
-          typename TO>
+// before it is written, and lines are disjoint).  MAXS > 0: nslices is at
+// most MAXS, and the lines are visited in a fixed number of unrolled rounds
+// (the matrix entries are then loaded where they are used, not hoisted out
+// of a loop and spilled); MAXS = 0: a loop over any number of slices.
+template <int NT, int D, int DIR, int MI, int MO, int A0, int A1, int A2, int MODE, int MAXS, typename TM,
+          typename TI, typename TO>
 __device__ __forceinline__ void tpass(const TI* in, TO* out, int nslices, const TM* __restrict__ M,
                                       double scale = 1.0) {
   using P = Pass<D, DIR, MI, MO, A0, A1, A2>;
   const int total = nslices * P::NL;
-  for (int w = threadIdx.x; w < total; w += NT) {
+  auto line = [&](int w) {
     const int s = w / P::NL;
     const int L = w - s * P::NL;
     int bi, bo;
@@ -156,18 +159,29 @@ __device__ __forceinline__ void tpass(const TI* in, TO* out, int nslices, const 
       else
         dst[i * P::STEP_OUT] += (TO)(scale * (double)acc[i]);
     }
+  };
+  if constexpr (MAXS > 0) {
+#pragma unroll
+    for (int it = 0; it < cdiv(MAXS * P::NL, NT); ++it) {
+      const int w = threadIdx.x + it * NT;
+      if (w >= total) break;
+      line(w);
+    }
+  } else {
+    for (int w = threadIdx.x; w < total; w += NT) line(w);
   }
 }
 
-// Apply the same n x n matrix along all D directions in place (square passes).
-template <int NT, int D, int N, typename TM, typename TT>
+// Apply the same n x n matrix along all D directions in place (square passes);
+// MAXS as in tpass.
+template <int NT, int D, int N, int MAXS, typename TM, typename TT>
 __device__ __forceinline__ void tensor_apply_inplace(TT* buf, int nslices, const TM* M) {
-  tpass<NT, D, 0, N, N, N, N, N, PM_STORE, TM>(buf, buf, nslices, M);
+  tpass<NT, D, 0, N, N, N, N, N, PM_STORE, MAXS, TM>(buf, buf, nslices, M);
   __syncthreads();
-  tpass<NT, D, 1, N, N, N, N, N, PM_STORE, TM>(buf, buf, nslices, M);
+  tpass<NT, D, 1, N, N, N, N, N, PM_STORE, MAXS, TM>(buf, buf, nslices, M);
   __syncthreads();
   if constexpr (D == 3) {
-    tpass<NT, D, 2, N, N, N, N, N, PM_STORE, TM>(buf, buf, nslices, M);
+    tpass<NT, D, 2, N, N, N, N, N, PM_STORE, MAXS, TM>(buf, buf, nslices, M);
     __syncthreads();
   }
 }
@@ -470,15 +484,15 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>())))
     // ---- B: GL -> G of the cell tiles; tangential GL -> G of the neighbour traces
     if constexpr (!GB) {
       const T* S = tab + tab_S(N);
-      tpass<NT, D, 0, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
-      if constexpr (D == 2) tpass<NT, 1, 0, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
-      if constexpr (D == 3) tpass<NT, 2, 0, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
+      tpass<NT, D, 0, N, N, N, N, N, PM_STORE, 0, T>(sU, sU, ncl * NC, S);
+      if constexpr (D == 2) tpass<NT, 1, 0, N, N, N, N, N, PM_STORE, 0, T>(sN, sN, ncl * NFACE * NC, S);
+      if constexpr (D == 3) tpass<NT, 2, 0, N, N, N, N, N, PM_STORE, 0, T>(sN, sN, ncl * NFACE * NC, S);
       __syncthreads();
-      tpass<NT, D, 1, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
-      if constexpr (D == 3) tpass<NT, 2, 1, N, N, N, N, N, PM_STORE, T>(sN, sN, ncl * NFACE * NC, S);
+      tpass<NT, D, 1, N, N, N, N, N, PM_STORE, 0, T>(sU, sU, ncl * NC, S);
+      if constexpr (D == 3) tpass<NT, 2, 1, N, N, N, N, N, PM_STORE, 0, T>(sN, sN, ncl * NFACE * NC, S);
       __syncthreads();
       if constexpr (D == 3) {
-        tpass<NT, D, 2, N, N, N, N, N, PM_STORE, T>(sU, sU, ncl * NC, S);
+        tpass<NT, D, 2, N, N, N, N, N, PM_STORE, 0, T>(sU, sU, ncl * NC, S);
         __syncthreads();
       }
     }
@@ -619,7 +633,7 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>())))
       }
     }
     __syncthreads();
-    if constexpr (!GOUT) tensor_apply_inplace<NT, D, N, T>(sT, ncl * NC, tab + tab_Sinv(N));
+    if constexpr (!GOUT) tensor_apply_inplace<NT, D, N, 0, T>(sT, ncl * NC, tab + tab_Sinv(N));
     // ---- E: epilogue (coalesced; u from A, the second operand from D)
     {
       int scell = -1;
@@ -793,12 +807,18 @@ struct Tck {
   }
 
   // size-changing pass (MO x MI matrix) along DIR between buffers with
-  // NP-strided cell-component slices
+  // NP-strided cell-component slices.  Here and in the final phase the lines
+  // are visited in a fixed number of unrolled rounds rather than a loop over
+  // the group's cells: a loop would have its matrix entries hoisted into
+  // scalar registers ahead of it and spilled (the kernel ran 10 % slower)
   template <int DIR, int E0, int E1, int E2, int MO, typename TI, typename TO>
   __device__ static __forceinline__ void pass(const TI* in, TO* out, int ncl, const T* __restrict__ Mx) {
     constexpr int MI = DIR == 0 ? E0 : (DIR == 1 ? E1 : E2);
     using P = Pass<D, DIR, MI, MO, E0, E1, E2>;
-    for (int wi = threadIdx.x; wi < ncl * NC * P::NL; wi += NT) {
+#pragma unroll
+    for (int it = 0; it < cdiv(CPW * NC * P::NL, NT); ++it) {
+      const int wi = threadIdx.x + it * NT;
+      if (wi >= ncl * NC * P::NL) break;
       const int s = wi / P::NL;
       const int L = wi - s * P::NL;
       int bi, bo;
@@ -978,7 +998,10 @@ struct Tck {
       const double* src0 = in + CPW * NC * fin_off(DIR, L);
       double* dst0 = out + CPW * NC * fin_off(DIR + 1, L);
       const double* Q = qmat(L);
-      for (int w = threadIdx.x; w < ncl * NC * P::NL; w += NT) {
+#pragma unroll
+      for (int it = 0; it < cdiv(CPW * NC * P::NL, NT); ++it) {
+        const int w = threadIdx.x + it * NT;
+        if (w >= ncl * NC * P::NL) break;
         const int sl = w / P::NL;
         const int Ln = w - sl * P::NL;
         int bi, bo;
@@ -1037,7 +1060,10 @@ struct Tck {
     // one thread per output line along the last direction: (cell, component, tangential t)
     constexpr int NT1 = ipow(N, D - 1);
     constexpr int ST = ipow(N, D - 1);
-    for (int w = threadIdx.x; w < ncl * NC * NT1; w += NT) {
+#pragma unroll
+    for (int it = 0; it < cdiv(CPW * NC * NT1, NT); ++it) {
+      const int w = threadIdx.x + it * NT;
+      if (w >= ncl * NC * NT1) break;
       const int sl = w / NT1;
       const int t = w - sl * NT1;
       double acc[N];
@@ -1151,7 +1177,7 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck
     if (i < nel) C[i] = (T)ev[s];
   }
   __syncthreads();
-  if constexpr (!GS) tensor_apply_inplace<NT, D, N, T>(C, ncl * NC, tab + tab_S(N));
+  if constexpr (!GS) tensor_apply_inplace<NT, D, N, CPW * NC, T>(C, ncl * NC, tab + tab_S(N));
   // first term of the sum: dt u_G (ADER), dt^2/2 W_G (HDG-ADER)
   const double c0 = HDG ? 0.5 * p.dt * p.dt : p.dt;
 #pragma unroll
@@ -1191,7 +1217,7 @@ __attribute__((amdgpu_waves_per_eu(tck_waves_per_simd<D, N, T, CPW, RP>()))) tck
       }
     }
     __syncthreads();
-    tensor_apply_inplace<NT, D, N, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
+    tensor_apply_inplace<NT, D, N, CPW * NC, double>(sI, ncl * NC, ctab<double>(N) + tab_Sinv(N));
     if constexpr (HDG && !GS) {
       for (int i = threadIdx.x; i < nel; i += NT) p.I[gofs + i] = sI[i] + p.dt * p.u_base[gofs + i];
     } else {
@@ -1219,7 +1245,7 @@ __global__ void __launch_bounds__(op_threads(D, N)) energy_kernel(EnergyParams p
   const int64_t gofs = (int64_t)member * p.nc * NC * NP + cell0 * NC * NP;
   for (int i = threadIdx.x; i < ncl * NC * NP; i += NT) sU[i] = (T)p.u[gofs + i];
   __syncthreads();
-  if constexpr (!GS) tensor_apply_inplace<NT, D, N, T>(sU, ncl * NC, tab + tab_S(N));
+  if constexpr (!GS) tensor_apply_inplace<NT, D, N, 0, T>(sU, ncl * NC, tab + tab_S(N));
   double acc = 0.0;
   for (int i = threadIdx.x; i < ncl * NC * NP; i += NT) {
     const int q = i % NP;

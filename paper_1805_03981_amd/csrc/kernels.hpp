@@ -128,6 +128,30 @@ __device__ __forceinline__ void contract(const TM* __restrict__ M, const TM (&x)
     for (int i = 0; i < MO; ++i) acc[i] = fma(M[i * MI + j], x[j], acc[i]);
 }
 
+// Zero, opaque to the compiler (a scalar register it cannot see through).
+// A phase that addresses its matrix with it loads the entries itself: they
+// are not merged with the same entries loaded by an earlier phase, whose
+// values would otherwise be kept in scalar registers across the kernel and,
+// at n >= 7 where one n x n FP64 matrix alone exceeds the scalar register
+// file, spilled to vector lanes and read back entry by entry.
+__device__ __forceinline__ int opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  return z;
+}
+
+// Whether the operator sweep addresses each 1D phase's matrix with its own
+// opaque zero and visits the phase's lines in unrolled rounds: where an
+// n x n matrix fills most of the scalar registers (FP64 from n = 7, FP32
+// from n = 8).  Measured A/B on one box: at k = 6, 7, 8 in FP64 the LSRK
+// stage ran 1.3x, 2.3x, 2.2x and the ADER update 1.4x, 1.6x, 1.8x faster,
+// in FP32 at k = 7, 8 by 1-5 %; at k = 5 the same change cost 2-6 %, so
+// smaller matrices keep the plain loops.
+template <int N, typename T>
+constexpr bool op_phase_tables() {
+  return N >= (sizeof(T) == 8 ? 7 : 8);
+}
+
 // out = M in along DIR, for nslices independent tensors (cells x components).
 // in and out may be the same buffer when MI == MO (each line is read whole
 // before it is written, and lines are disjoint).  MAXS > 0: nslices is at
@@ -285,6 +309,44 @@ __device__ __forceinline__ void op_lines(const T* __restrict__ tab, T* sT, const
   const T* LF1 = tab + tab_LF1(N);
   constexpr int NT = op_threads(D, N);
   for (int w = threadIdx.x; w < ncl * NC * NF; w += NT) {
+    const int sl = w / NF;  // c * NC + v
+    const int L = w - sl * NF;
+    const int c = sl / NC, v = sl - c * NC;
+    int bq, bq2;
+    P::base(L, bq, bq2);
+    T* ln = sT + sl * NP + bq;
+    T F[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) F[j] = ln[j * P::STEP_IN];
+    const T f0 = sN[((c * NFACE + 2 * DIR) * NC + v) * NF + L];
+    const T f1 = sN[((c * NFACE + 2 * DIR + 1) * NC + v) * NF + L];
+    T acc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = fma(LF1[i], f1, LF0[i] * f0);
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc[i] = fma(Dm[j * N + i], F[j], acc[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) ln[i * P::STEP_IN] = acc[i];
+  }
+}
+
+// op_lines for large matrices (op_phase_tables): the phase loads its own
+// matrix entries (an opaque zero offset) and visits its lines in a fixed
+// number of unrolled rounds.
+template <int D, int N, typename T, int DIR, int CPW>
+__device__ __forceinline__ void op_lines_pt(const T* __restrict__ tab, T* sT, const T* sN, int ncl) {
+  constexpr int NC = D + 1, NP = ipow(N, D), NF = ipow(N, D - 1), NFACE = 2 * D;
+  using P = Pass<D, DIR, N, N, N, N, N>;
+  const int off = opaque_zero();
+  const T* Dm = tab + tab_D(N) + off;
+  const T* LF0 = tab + tab_LF0(N) + off;
+  const T* LF1 = tab + tab_LF1(N) + off;
+  constexpr int NT = op_threads(D, N);
+  constexpr int ROUNDS = cdiv(CPW * NC * NF, NT);
+#pragma unroll
+  for (int it = 0, w = threadIdx.x; it < ROUNDS && w < ncl * NC * NF; ++it, w += NT) {
     const int sl = w / NF;  // c * NC + v
     const int L = w - sl * NF;
     const int c = sl / NC, v = sl - c * NC;
@@ -483,16 +545,21 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>())))
 
     // ---- B: GL -> G of the cell tiles; tangential GL -> G of the neighbour traces
     if constexpr (!GB) {
-      const T* S = tab + tab_S(N);
-      tpass<NT, D, 0, N, N, N, N, N, PM_STORE, 0, T>(sU, sU, ncl * NC, S);
-      if constexpr (D == 2) tpass<NT, 1, 0, N, N, N, N, N, PM_STORE, 0, T>(sN, sN, ncl * NFACE * NC, S);
-      if constexpr (D == 3) tpass<NT, 2, 0, N, N, N, N, N, PM_STORE, 0, T>(sN, sN, ncl * NFACE * NC, S);
+      // with op_phase_tables each pass addresses S with its own opaque zero
+      constexpr bool PT = op_phase_tables<N, T>();
+      constexpr int MU = PT ? CPW * NC : 0, MN = PT ? CPW * NFACE * NC : 0;
+      const T* S = tab + tab_S(N) + (PT ? opaque_zero() : 0);
+      tpass<NT, D, 0, N, N, N, N, N, PM_STORE, MU, T>(sU, sU, ncl * NC, S);
+      if constexpr (D == 2) tpass<NT, 1, 0, N, N, N, N, N, PM_STORE, MN, T>(sN, sN, ncl * NFACE * NC, S);
+      if constexpr (D == 3) tpass<NT, 2, 0, N, N, N, N, N, PM_STORE, MN, T>(sN, sN, ncl * NFACE * NC, S);
       __syncthreads();
-      tpass<NT, D, 1, N, N, N, N, N, PM_STORE, 0, T>(sU, sU, ncl * NC, S);
-      if constexpr (D == 3) tpass<NT, 2, 1, N, N, N, N, N, PM_STORE, 0, T>(sN, sN, ncl * NFACE * NC, S);
+      if constexpr (PT) S = tab + tab_S(N) + opaque_zero();
+      tpass<NT, D, 1, N, N, N, N, N, PM_STORE, MU, T>(sU, sU, ncl * NC, S);
+      if constexpr (D == 3) tpass<NT, 2, 1, N, N, N, N, N, PM_STORE, MN, T>(sN, sN, ncl * NFACE * NC, S);
       __syncthreads();
       if constexpr (D == 3) {
-        tpass<NT, D, 2, N, N, N, N, N, PM_STORE, 0, T>(sU, sU, ncl * NC, S);
+        if constexpr (PT) S = tab + tab_S(N) + opaque_zero();
+        tpass<NT, D, 2, N, N, N, N, N, PM_STORE, MU, T>(sU, sU, ncl * NC, S);
         __syncthreads();
       }
     }
@@ -593,15 +660,24 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>())))
     T R[PS][NC];
     op_points<D, N, T, PS, 0>(g, sU, sT, R, ncl);
     __syncthreads();
-    op_lines<D, N, T, 0>(tab, sT, sN, ncl);
+    if constexpr (op_phase_tables<N, T>())
+      op_lines_pt<D, N, T, 0, CPW>(tab, sT, sN, ncl);
+    else
+      op_lines<D, N, T, 0>(tab, sT, sN, ncl);
     __syncthreads();
     op_points<D, N, T, PS, 1>(g, sU, sT, R, ncl);
     __syncthreads();
-    op_lines<D, N, T, 1>(tab, sT, sN, ncl);
+    if constexpr (op_phase_tables<N, T>())
+      op_lines_pt<D, N, T, 1, CPW>(tab, sT, sN, ncl);
+    else
+      op_lines<D, N, T, 1>(tab, sT, sN, ncl);
     __syncthreads();
     if constexpr (D == 3) {
       op_points<D, N, T, PS, 2>(g, sU, sT, R, ncl);
       __syncthreads();
+      if constexpr (op_phase_tables<N, T>())
+      op_lines_pt<D, N, T, 2, CPW>(tab, sT, sN, ncl);
+    else
       op_lines<D, N, T, 2>(tab, sT, sN, ncl);
       __syncthreads();
     }
@@ -633,7 +709,19 @@ __attribute__((amdgpu_waves_per_eu(op_waves_per_simd<D, N, T, EPI, CPW, MB>())))
       }
     }
     __syncthreads();
-    if constexpr (!GOUT) tensor_apply_inplace<NT, D, N, 0, T>(sT, ncl * NC, tab + tab_Sinv(N));
+    if constexpr (!GOUT && !op_phase_tables<N, T>()) {
+      tensor_apply_inplace<NT, D, N, 0, T>(sT, ncl * NC, tab + tab_Sinv(N));
+    } else if constexpr (!GOUT) {
+      constexpr int MU = CPW * NC;
+      tpass<NT, D, 0, N, N, N, N, N, PM_STORE, MU, T>(sT, sT, ncl * NC, tab + tab_Sinv(N) + opaque_zero());
+      __syncthreads();
+      tpass<NT, D, 1, N, N, N, N, N, PM_STORE, MU, T>(sT, sT, ncl * NC, tab + tab_Sinv(N) + opaque_zero());
+      __syncthreads();
+      if constexpr (D == 3) {
+        tpass<NT, D, 2, N, N, N, N, N, PM_STORE, MU, T>(sT, sT, ncl * NC, tab + tab_Sinv(N) + opaque_zero());
+        __syncthreads();
+      }
+    }
     // ---- E: epilogue (coalesced; u from A, the second operand from D)
     {
       int scell = -1;

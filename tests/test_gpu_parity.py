@@ -781,6 +781,36 @@ def test_fp32_split_error_stated(gpu_lib):
     assert 0 < err < 1e-6
 
 
+@pytest.mark.parametrize("k", [7, 8])
+def test_fp32_split_large_matrix_phases(gpu_lib, k):
+    """FP32-split at k = 7 and 8, where each phase of the operator sweep loads
+    its own matrix entries and visits its lines in unrolled rounds (another
+    code path than at lower degrees): the operator, one LSRK(5,4) step and
+    one ADER step against the FP64 oracle within the stated single-precision
+    bound, 1e-5 relative."""
+    say("fp32 split large matrices", k)
+    dim, nc = 3, 2
+    gm, om = build(gpu_lib, dim, nc, k, 0.05, precision=1)
+    U = om.interpolate(lambda x: W.gaussian_pulse(x, [0.5] * dim, 0.2))
+    U = U + 0.01 * W.random_state(11 + k, U.shape)
+    got = gm.apply(to_dev(U)[None]).cpu().numpy()[0]
+    err = rel(got, apply_operator(om, U))
+    say("operator rel err", err)
+    assert 0 < err < 1e-5
+    dt = 0.5 * gm.info.dt_unit
+    u = to_dev(U)[None]
+    gm.step_lsrk(u, 0.0, dt, 1)
+    err = rel(u[0].cpu().numpy(), ts.lsrk_step(lambda x, t: apply_operator(om, x), U, 0.0, dt))
+    say("lsrk step rel err", err)
+    assert 0 < err < 1e-5
+    dt = 0.15 * gm.info.dt_unit
+    u = to_dev(U)[None]
+    gm.step_ader(u, 0.0, dt, 1)
+    err = rel(u[0].cpu().numpy(), ader.ader_step(om, U, dt))
+    say("ader step rel err", err)
+    assert 0 < err < 1e-5
+
+
 def test_invalid_arguments(gpu_lib):
     say("invalid")
     gm, om = build(gpu_lib, 2, 3, 2, 0.0)
